@@ -1,0 +1,864 @@
+/*
+ * porta_oracle.cpp -- plain, slow FP64 CPU oracle of the PORTA hot path.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code, header,
+ * table or constant with the GPU library and the GPU library never calls it.
+ *
+ * What it computes (Stepan & Trujillo Bueno 2013, arXiv:1307.4217):
+ *   - the short-characteristics formal solution of the Stokes-vector transfer
+ *     equation (Sect. 3, Eqs. rte, fsint) with the BESSER monotonic quadratic
+ *     Bezier source-function interpolation (Sect. 3.2, steps 1-9) and the
+ *     linear treatment of K'I (Sect. 3.3, Eqs. fsbez, kappa, omega_M/O/C,
+ *     psi'_M/O, Table 1 for small optical depths), swept over a 3-D grid
+ *     that is periodic in x and y (Sect. 3.1, Appendix A);
+ *   - the diagonal Lambda* of Sect. 3.3 (Eq. 14);
+ *   - the radiation-field tensors J^K_Q of Eq. 1 on the discrete quadrature;
+ *   - one Jacobi update of the statistical equilibrium of a two-level
+ *     J_l = 0 -> J_u = 1 atom with Hanle rotation (Sect. 2, Eq. nonlte;
+ *     Sect. 5 for the Jacobi scheme and the convergence measure R_c);
+ *   - long characteristics along the same rays (brute force check);
+ *   - complex-step directional derivatives of the emergent Stokes vector.
+ *
+ * Readings where the paper is silent (same numbering as the design notes):
+ *   A1 M and P always lie on the neighbouring horizontal grid planes.
+ *   A3 emission and absorption coefficients are interpolated, S = eps/eta_I
+ *      and K' = K/eta_I - 1 are formed at M, O and P afterwards.
+ *   A4 tau_MO = (eta_I(M) + eta_I(O))/2 * |Delta s|.
+ *   A5 on the last plane of a ray (no downwind point) c_M = (y_M + y_O)/2.
+ *   A6 series thresholds: omega_M 0.14, omega_O and omega_C 0.18 (Table 1),
+ *      psi'_M and psi'_O 0.1.
+ *   A7 Lambda* is the response of I_O to a unit S_O (Stokes I only): omega_O +
+ *      omega_C, or omega_O + omega_C/2 on the last plane (A5); zero on the
+ *      boundary plane.
+ *   A8 K = 2 multipoles are updated by plain Lambda iteration.
+ *   A9/O7 T^K_Q(i, Omega) with reference direction gamma = 0, see tkq().
+ *
+ * Everything is double precision; the sweep is templated on the scalar so
+ * that std::complex<double> inputs p + i h v give the exact directional
+ * derivative Im(I(p + i h v))/h of the branch taken by the real evaluation.
+ */
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cd = std::complex<double>;
+
+inline double rp(double v) { return v; }
+inline double rp(const cd& v) { return v.real(); }
+
+/* A physical complex number; each part may itself carry a complex-step
+ * perturbation when T = std::complex<double>. */
+template <class T>
+struct Cx {
+  T re, im;
+};
+template <class T>
+inline Cx<T> cmul(const Cx<double>& a, const Cx<T>& b) {
+  return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+/* -------------------------------------------------------------------------- */
+/* Problem description (the oracle's own definition of the inputs).           */
+/* -------------------------------------------------------------------------- */
+}  // namespace
+
+extern "C" {
+typedef struct {
+  int nx, ny, nz;
+  double lx, ly;
+  const double* z;      /* nz heights, strictly increasing */
+  int nmu, nchi, nfreq;
+  const double* mu;     /* nmu inclination cosines in (0,1] (one hemisphere) */
+  const double* wmu;    /* nmu weights, sum 1 */
+  const double* phi;    /* nfreq profile values relative to line centre */
+  const double* wfreq;  /* nfreq frequency quadrature weights */
+  double i_bottom;      /* Stokes I entering at the bottom for upward rays */
+  double w2;            /* w^(2) of the transition */
+  int interp;           /* 0 bilinear, 1 9-point monotonic Bezier */
+} oracle_problem;
+}
+
+namespace {
+
+/* Ray enumeration: rays [0, nmu*nchi) go upward (mu > 0), the rest downward;
+ * inside a hemisphere the inclination index is slow and the azimuth fast.
+ * Azimuths follow the trapezoid rule with nodes (m + 1/2) 2 pi / nchi; the
+ * weight of a ray is wmu/2/nchi so that all weights sum to one. */
+struct Ray {
+  double mu, sint, chi, sx, sy, w;
+  bool up;
+};
+
+Ray make_ray(const oracle_problem& pb, int r) {
+  const int nh = pb.nmu * pb.nchi;
+  const int hemi = r / nh;
+  const int a = (r % nh) / pb.nchi;
+  const int m = r % pb.nchi;
+  Ray ray;
+  ray.up = (hemi == 0);
+  ray.mu = ray.up ? pb.mu[a] : -pb.mu[a];
+  ray.sint = std::sqrt(std::max(0.0, 1.0 - pb.mu[a] * pb.mu[a]));
+  ray.chi = (m + 0.5) * 2.0 * M_PI / pb.nchi;
+  ray.sx = ray.sint * std::cos(ray.chi);
+  ray.sy = ray.sint * std::sin(ray.chi);
+  ray.w = 0.5 * pb.wmu[a] / pb.nchi;
+  return ray;
+}
+
+/* Index of (K, Q) in a 9-slot table: K=0 -> 0; K=1, Q=-1..1 -> 1..3; K=2, Q=-2..2 -> 4..8 */
+inline int kq(int K, int Q) { return K == 0 ? 0 : (K == 1 ? 2 + Q : 6 + Q); }
+
+/* Spherical tensors T^K_Q(i, Omega) of Eq. 1 (i = I, Q, U, V), polarization
+ * reference: Q > 0 along e_a = (mu cos chi, mu sin chi, -sin theta). */
+void tkq(double mu, double chi, Cx<double> t[4][9]) {
+  for (int i = 0; i < 4; ++i)
+    for (int s = 0; s < 9; ++s) t[i][s] = Cx<double>{0.0, 0.0};
+  const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+  const double r2 = std::sqrt(2.0), r3 = std::sqrt(3.0);
+  auto ph = [&](int q, double amp) {  // amp * e^{i q chi}
+    return Cx<double>{amp * std::cos(q * chi), amp * std::sin(q * chi)};
+  };
+  auto iph = [&](int q, double amp) {  // i * amp * e^{i q chi}
+    return Cx<double>{-amp * std::sin(q * chi), amp * std::cos(q * chi)};
+  };
+  /* Stokes I */
+  t[0][kq(0, 0)] = Cx<double>{1.0, 0.0};
+  t[0][kq(2, 0)] = Cx<double>{(3.0 * mu * mu - 1.0) / (2.0 * r2), 0.0};
+  t[0][kq(2, 1)] = ph(1, -0.5 * r3 * st * mu);
+  t[0][kq(2, -1)] = ph(-1, +0.5 * r3 * st * mu);
+  t[0][kq(2, 2)] = ph(2, 0.25 * r3 * st * st);
+  t[0][kq(2, -2)] = ph(-2, 0.25 * r3 * st * st);
+  /* Stokes Q */
+  t[1][kq(2, 0)] = Cx<double>{-3.0 / (2.0 * r2) * st * st, 0.0};
+  t[1][kq(2, 1)] = ph(1, -0.5 * r3 * st * mu);
+  t[1][kq(2, -1)] = ph(-1, +0.5 * r3 * st * mu);
+  t[1][kq(2, 2)] = ph(2, -0.25 * r3 * (1.0 + mu * mu));
+  t[1][kq(2, -2)] = ph(-2, -0.25 * r3 * (1.0 + mu * mu));
+  /* Stokes U */
+  t[2][kq(2, 1)] = iph(1, -0.5 * r3 * st);
+  t[2][kq(2, -1)] = iph(-1, -0.5 * r3 * st);
+  t[2][kq(2, 2)] = iph(2, -0.5 * r3 * mu);
+  t[2][kq(2, -2)] = iph(-2, +0.5 * r3 * mu);
+  /* Stokes V */
+  t[3][kq(1, 0)] = Cx<double>{std::sqrt(1.5) * mu, 0.0};
+  t[3][kq(1, 1)] = ph(1, -0.5 * r3 * st);
+  t[3][kq(1, -1)] = ph(-1, +0.5 * r3 * st);
+}
+
+/* -------------------------------------------------------------------------- */
+/* Sect. 3.3: coefficients of Eq. fsbez.                                      */
+/* -------------------------------------------------------------------------- */
+template <class T>
+struct Coef {
+  T e, psiM, psiO, omM, omO, omC;
+};
+
+constexpr double kThreshOmegaM = 0.14;  // Table 1
+constexpr double kThreshOmegaOC = 0.18; // Table 1
+constexpr double kThreshPsi = 0.10;     // reading A6
+
+template <class T>
+Coef<T> coefficients(const T& tau) {
+  Coef<T> c;
+  const double t = rp(tau);
+  c.e = std::exp(-tau);
+  /* at tau = 0 the series branch gives e = 1 and all other coefficients 0 */
+  const T t2 = tau * tau;
+  /* Taylor series about tau = 0, 8 terms each, n = 0..7 */
+  T sM(0.0), sO(0.0), sC(0.0), pM(0.0), pO(0.0);
+  {
+    double fact = 1.0;  // n!
+    T tp = tau;         // tau^{n+1}
+    for (int n = 0; n < 8; ++n) {
+      if (n > 0) fact *= n;
+      const double sg = (n % 2 == 0) ? 1.0 : -1.0;
+      sM += sg * tp / (fact * (n + 3));
+      sO += sg * 2.0 * tp / (fact * (n + 1) * (n + 2) * (n + 3));   // 2 tau^{n+1}/(n+3)!
+      sC += sg * 2.0 * tp / (fact * (n + 2) * (n + 3));
+      pM += sg * tp / (fact * (n + 2));
+      pO += sg * tp / (fact * (n + 1) * (n + 2));                   // tau^{n+1}/(n+2)!
+      tp = tp * tau;
+    }
+  }
+  if (t < kThreshPsi) {
+    c.psiM = pM;
+    c.psiO = pO;
+  } else {
+    c.psiM = (1.0 - c.e * (1.0 + tau)) / tau;
+    c.psiO = (c.e + tau - 1.0) / tau;
+  }
+  if (t < kThreshOmegaM)
+    c.omM = sM;
+  else
+    c.omM = (2.0 - c.e * (t2 + 2.0 * tau + 2.0)) / t2;
+  if (t < kThreshOmegaOC) {
+    c.omO = sO;
+    c.omC = sC;
+  } else {
+    c.omO = 1.0 - 2.0 * (c.e + tau - 1.0) / t2;
+    c.omC = 2.0 * (tau - 2.0 + c.e * (tau + 2.0)) / t2;
+  }
+  return c;
+}
+
+/* -------------------------------------------------------------------------- */
+/* Sect. 3.2: BESSER control point c_M of the upwind interval MO.             */
+/* -------------------------------------------------------------------------- */
+template <class T>
+T besser_cm(const T& yM, const T& yO, const T& yP, const T& hM, const T& hP) {
+  if (!(rp(hM) > 0.0)) return yO;       // zero-length MO interval: c_M is irrelevant
+  if (!(rp(hP) > 0.0)) {                // limit h_P -> 0 of steps 3-6
+    if (rp(yO - yM) * rp(yP - yO) <= 0.0) return yO;
+    return yM;
+  }
+  /* step 1 */
+  const T dM = (yO - yM) / hM;
+  const T dP = (yP - yO) / hP;
+  /* step 2: not monotonic -> local extremum at O */
+  if (rp(dM) * rp(dP) <= 0.0) return yO;
+  /* step 3: derivative at O (Eq. deriv) */
+  T yd = (hM * dP + hP * dM) / (hM + hP);
+  /* step 4 */
+  T cM = yO - 0.5 * hM * yd;
+  T cP = yO + 0.5 * hP * yd;
+  /* steps 5-6: overshoot in MO */
+  const double lo = std::min(rp(yM), rp(yO)), hi = std::max(rp(yM), rp(yO));
+  if (rp(cM) < lo || rp(cM) > hi) return yM;
+  /* step 7: overshoot in OP */
+  const double lo2 = std::min(rp(yO), rp(yP)), hi2 = std::max(rp(yO), rp(yP));
+  if (rp(cP) < lo2 || rp(cP) > hi2) {
+    cP = yP;
+    /* step 8: new derivative at O */
+    yd = (cP - yO) / (0.5 * hP);
+    /* step 9: keep the derivative at O continuous */
+    cM = yO - 0.5 * hM * yd;
+  }
+  return cM;
+}
+
+/* One-dimensional monotonic quadratic Bezier interpolation through three
+ * equidistant nodes at -1, 0, +1, evaluated at t in [-1/2, 1/2].  The control
+ * point of each interval is the BESSER c_M of the triple read towards that
+ * interval, so the result does not depend on the reading direction. */
+template <class T>
+T bezier1d(const T& ym, const T& y0, const T& yp, double t) {
+  const T one(1.0);
+  if (t >= 0.0) {
+    const T c = besser_cm(yp, y0, ym, one, one);
+    return (1.0 - t) * (1.0 - t) * y0 + 2.0 * t * (1.0 - t) * c + t * t * yp;
+  }
+  const T c = besser_cm(ym, y0, yp, one, one);
+  const double u = 1.0 + t;
+  return (1.0 - u) * (1.0 - u) * ym + 2.0 * u * (1.0 - u) * c + u * u * y0;
+}
+
+inline int wrap(long i, int n) {
+  long r = i % n;
+  return (int)(r < 0 ? r + n : r);
+}
+
+/* Interpolation of a horizontal plane (x fastest) at a point given in cell
+ * units; x and y are periodic.  Mode 0: bilinear from the 4 surrounding
+ * nodes.  Mode 1: 9 nodes around the nearest node, monotonic Bezier along x
+ * for each of the three rows, then along y. */
+template <class T>
+T interp_plane(const T* f, int nx, int ny, double fx, double fy, int mode) {
+  if (mode == 0) {
+    const double fi = std::floor(fx), fj = std::floor(fy);
+    const double tx = fx - fi, ty = fy - fj;
+    const int i0 = wrap((long)fi, nx), i1 = wrap((long)fi + 1, nx);
+    const int j0 = wrap((long)fj, ny), j1 = wrap((long)fj + 1, ny);
+    return (1.0 - tx) * (1.0 - ty) * f[j0 * nx + i0] + tx * (1.0 - ty) * f[j0 * nx + i1] +
+           (1.0 - tx) * ty * f[j1 * nx + i0] + tx * ty * f[j1 * nx + i1];
+  }
+  const double fi = std::floor(fx + 0.5), fj = std::floor(fy + 0.5);
+  const double tx = fx - fi, ty = fy - fj;
+  T row[3];
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int j = wrap((long)fj + dj, ny);
+    const T* r = f + (size_t)j * nx;
+    row[dj + 1] = bezier1d(r[wrap((long)fi - 1, nx)], r[wrap((long)fi, nx)],
+                           r[wrap((long)fi + 1, nx)], tx);
+  }
+  return bezier1d(row[0], row[1], row[2], ty);
+}
+
+/* Emission vector component i from the multipoles (eps00, eps20, Re eps21,
+ * Im eps21, Re eps22, Im eps22): eps_i = Re sum_{KQ} w^(K) T^K_Q(i) eps^K_Q,
+ * summed over all Q with eps^K_{-Q} = (-1)^Q conj(eps^K_Q); no K = 1 terms. */
+template <class T>
+T emission(const Cx<double> t[4][9], int i, const T e[6], double w2) {
+  Cx<T> ek[9];
+  for (int s = 0; s < 9; ++s) ek[s] = Cx<T>{T(0.0), T(0.0)};
+  ek[kq(0, 0)] = Cx<T>{e[0], T(0.0)};
+  ek[kq(2, 0)] = Cx<T>{e[1], T(0.0)};
+  ek[kq(2, 1)] = Cx<T>{e[2], e[3]};
+  ek[kq(2, 2)] = Cx<T>{e[4], e[5]};
+  ek[kq(2, -1)] = Cx<T>{-e[2], e[3]};   // -(conj eps21)
+  ek[kq(2, -2)] = Cx<T>{e[4], -e[5]};   // conj eps22
+  T sum(0.0);
+  for (int K = 0; K <= 2; ++K)
+    for (int Q = -K; Q <= K; ++Q) {
+      const double wk = (K == 0) ? 1.0 : (K == 2 ? w2 : 0.0);
+      sum += wk * cmul(t[i][kq(K, Q)], ek[kq(K, Q)]).re;
+    }
+  return sum;
+}
+
+/* K' = K/eta_I - 1 from (eta_Q, eta_U, eta_V, rho_Q, rho_U, rho_V) and eta_I. */
+template <class T>
+void kprime(const T eta[6], const T& etaI, T k[4][4]) {
+  const T eQ = eta[0] / etaI, eU = eta[1] / etaI, eV = eta[2] / etaI;
+  const T rQ = eta[3] / etaI, rU = eta[4] / etaI, rV = eta[5] / etaI;
+  const T z(0.0);
+  const T m[4][4] = {{z, eQ, eU, eV}, {eQ, z, rV, -rU}, {eU, -rV, z, rQ}, {eV, rU, -rQ, z}};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) k[a][b] = m[a][b];
+}
+
+/* Gaussian elimination with partial pivoting on the real parts. */
+template <class T, int N>
+void gauss_solve(T A[N][N], T b[N], T x[N]) {
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(rp(A[r][c])) > std::fabs(rp(A[piv][c]))) piv = r;
+    if (piv != c) {
+      for (int k = 0; k < N; ++k) std::swap(A[c][k], A[piv][k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < N; ++r) {
+      const T f = A[r][c] / A[c][c];
+      for (int k = c; k < N; ++k) A[r][k] -= f * A[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = N - 1; r >= 0; --r) {
+    T s = b[r];
+    for (int k = r + 1; k < N; ++k) s -= A[r][k] * x[k];
+    x[r] = s / A[r][r];
+  }
+}
+
+template <class T>
+struct FieldsT {
+  const T* kappa;  // [N]
+  const T* prop;   // [6][N]
+  const T* emis;   // [6][N]
+};
+
+/* Formal solution for one ray and one frequency over the whole grid.
+ * Writes I ([4][N], one Stokes component after the other) and Lambda* (N). */
+template <class T>
+void sweep_one(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray, int jf,
+               T* I, double* lam) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny;
+  const size_t N = np * nz;
+  const double dx = pb.lx / nx, dy = pb.ly / ny;
+  const double phi = pb.phi[jf];
+  Cx<double> t[4][9];
+  tkq(ray.mu, ray.chi, t);
+  const int s = ray.up ? 1 : -1;
+  const int kb = ray.up ? 0 : nz - 1;   // boundary plane
+  /* boundary condition */
+  for (size_t p = 0; p < np; ++p) {
+    I[0 * N + kb * np + p] = T(ray.up ? pb.i_bottom : 0.0);
+    I[1 * N + kb * np + p] = I[2 * N + kb * np + p] = I[3 * N + kb * np + p] = T(0.0);
+    if (lam) lam[kb * np + p] = 0.0;
+  }
+  for (int step = 1; step < nz; ++step) {
+    const int k = kb + s * step;
+    const int kup = k - s, kdn = k + s;
+    const bool hasP = (kdn >= 0 && kdn < nz);
+    const double dsM = (pb.z[k] - pb.z[kup]) / ray.mu;
+    const double dsP = hasP ? (pb.z[kdn] - pb.z[k]) / ray.mu : 0.0;
+    for (int j = 0; j < ny; ++j) {
+      for (int i = 0; i < nx; ++i) {
+        const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+        /* M on the upwind plane, P on the downwind plane (reading A1) */
+        const double fxM = i - dsM * ray.sx / dx, fyM = j - dsM * ray.sy / dy;
+        const double fxP = i + dsP * ray.sx / dx, fyP = j + dsP * ray.sy / dy;
+        auto atM = [&](const T* arr) {
+          return interp_plane(arr + (size_t)kup * np, nx, ny, fxM, fyM, pb.interp);
+        };
+        auto atP = [&](const T* arr) {
+          return interp_plane(arr + (size_t)kdn * np, nx, ny, fxP, fyP, pb.interp);
+        };
+        /* absorption and emission at M, O, P (reading A3) */
+        T kapM = atM(f.kappa), kapO = f.kappa[pO], kapP(0.0);
+        T etaM[6], etaO[6], epsM[6], epsO[6], epsP[6];
+        for (int c = 0; c < 6; ++c) {
+          etaM[c] = atM(f.prop + c * N);
+          etaO[c] = f.prop[c * N + pO];
+          epsM[c] = atM(f.emis + c * N);
+          epsO[c] = f.emis[c * N + pO];
+          epsP[c] = T(0.0);
+        }
+        if (hasP) {
+          kapP = atP(f.kappa);
+          for (int c = 0; c < 6; ++c) epsP[c] = atP(f.emis + c * N);
+        }
+        /* Stokes vector at M, interpolated from the upwind plane */
+        T IM[4];
+        for (int st = 0; st < 4; ++st) IM[st] = atM(I + st * N);
+        /* monochromatic coefficients: eta_I(nu) = kappa * phi, eps(nu) = eps * phi */
+        const T etaIM = kapM * phi, etaIO = kapO * phi, etaIP = kapP * phi;
+        T eM[6], eO[6], eP[6], nM[6], nO[6];
+        for (int c = 0; c < 6; ++c) {
+          eM[c] = epsM[c] * phi; eO[c] = epsO[c] * phi; eP[c] = epsP[c] * phi;
+          nM[c] = etaM[c] * phi; nO[c] = etaO[c] * phi;
+        }
+        /* optical paths (reading A4) */
+        const T tauMO = 0.5 * (etaIM + etaIO) * std::fabs(dsM);
+        const T tauOP = 0.5 * (etaIO + etaIP) * std::fabs(dsP);
+        /* source vectors S = eps / eta_I */
+        T SM[4], SO[4], SP[4], cM[4];
+        for (int st = 0; st < 4; ++st) {
+          SM[st] = emission(t, st, eM, pb.w2) / etaIM;
+          SO[st] = emission(t, st, eO, pb.w2) / etaIO;
+          SP[st] = hasP ? emission(t, st, eP, pb.w2) / etaIP : T(0.0);
+          cM[st] = hasP ? besser_cm(SM[st], SO[st], SP[st], tauMO, tauOP)
+                        : 0.5 * (SM[st] + SO[st]);   // reading A5
+        }
+        T KM[4][4], KO[4][4];
+        kprime(nM, etaIM, KM);
+        kprime(nO, etaIO, KO);
+        const Coef<T> cf = coefficients(tauMO);
+        /* Eq. fsbez right-hand side */
+        T b[4];
+        for (int a = 0; a < 4; ++a) {
+          T acc = cf.e * IM[a];
+          for (int c = 0; c < 4; ++c) acc -= cf.psiM * KM[a][c] * IM[c];
+          acc += cf.omM * SM[a] + cf.omO * SO[a] + cf.omC * cM[a];
+          b[a] = acc;
+        }
+        /* Eq. kappa: kappa^{-1} = 1 + psi'_O K'_O; solve kappa^{-1} I_O = b */
+        T A[4][4];
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 4; ++c) A[a][c] = (a == c ? T(1.0) : T(0.0)) + cf.psiO * KO[a][c];
+        T IO[4];
+        gauss_solve<T, 4>(A, b, IO);
+        for (int st = 0; st < 4; ++st) I[st * N + pO] = IO[st];
+        /* Eq. 14: I_O for S_O = 1 and zero elsewhere; the unit source is a local
+         * maximum (c_M = 1) except on the last plane, where reading A5 gives c_M = 1/2 */
+        if (lam) lam[pO] = rp(cf.omO + (hasP ? 1.0 : 0.5) * cf.omC);
+      }
+    }
+  }
+}
+
+double freq_norm(const oracle_problem& pb) {
+  double s = 0.0;
+  for (int j = 0; j < pb.nfreq; ++j) s += pb.wfreq[j] * pb.phi[j];
+  return s;
+}
+
+/* Eq. 1 on the discrete quadrature: add w_Omega W_j sum_i T^K_Q(i) I_i to J,
+ * and w_Omega W_j Lambda* to the angle-frequency averaged Lambda*. */
+void accumulate_j(const Ray& ray, double Wj, const double* I,
+                  size_t sp, size_t sc, const double* lam, size_t N, double* jkq) {
+  /* I_i at point p is I[p * sp + i * sc] */
+  Cx<double> t[4][9];
+  tkq(ray.mu, ray.chi, t);
+  const double w = ray.w * Wj;
+  for (size_t p = 0; p < N; ++p) {
+    Cx<double> J[9];
+    for (int s = 0; s < 9; ++s) J[s] = Cx<double>{0.0, 0.0};
+    for (int K = 0; K <= 2; ++K)
+      for (int Q = 0; Q <= K; ++Q)
+        for (int st = 0; st < 4; ++st) {
+          const Cx<double>& tt = t[st][kq(K, Q)];
+          J[kq(K, Q)].re += tt.re * I[p * sp + st * sc];
+          J[kq(K, Q)].im += tt.im * I[p * sp + st * sc];
+        }
+    jkq[0 * N + p] += w * J[kq(0, 0)].re;
+    jkq[1 * N + p] += w * J[kq(1, 0)].re;
+    jkq[2 * N + p] += w * J[kq(1, 1)].re;
+    jkq[3 * N + p] += w * J[kq(1, 1)].im;
+    jkq[4 * N + p] += w * J[kq(2, 0)].re;
+    jkq[5 * N + p] += w * J[kq(2, 1)].re;
+    jkq[6 * N + p] += w * J[kq(2, 1)].im;
+    jkq[7 * N + p] += w * J[kq(2, 2)].re;
+    jkq[8 * N + p] += w * J[kq(2, 2)].im;
+    if (lam) jkq[9 * N + p] += w * lam[p];
+  }
+}
+
+bool valid_problem(const oracle_problem* pb) {
+  if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 2 || pb->nmu < 1 || pb->nchi < 1 ||
+      pb->nfreq < 1 || !pb->z || !pb->mu || !pb->wmu || !pb->phi || !pb->wfreq)
+    return false;
+  for (int k = 1; k < pb->nz; ++k)
+    if (!(pb->z[k] > pb->z[k - 1])) return false;
+  for (int a = 0; a < pb->nmu; ++a)
+    if (!(pb->mu[a] > 0.0 && pb->mu[a] <= 1.0)) return false;
+  return true;
+}
+
+int nthreads_of(int req) {
+#ifdef _OPENMP
+  return req > 0 ? req : omp_get_max_threads();
+#else
+  (void)req;
+  return 1;
+#endif
+}
+
+/* Long characteristics: integrate along the straight ray from the boundary to
+ * every grid point, interpolating only the material (never I) at the plane
+ * crossings, with the same BESSER step per segment. */
+void lc_one(const oracle_problem& pb, const FieldsT<double>& f, const Ray& ray, int jf,
+            double* Iout) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny, N = np * nz;
+  const double dx = pb.lx / nx, dy = pb.ly / ny;
+  const double phi = pb.phi[jf];
+  Cx<double> t[4][9];
+  tkq(ray.mu, ray.chi, t);
+  const int s = ray.up ? 1 : -1;
+  const int kb = ray.up ? 0 : nz - 1;
+  struct Node {
+    double kap, eta[6], eps[6];
+    double ds;  // path length from the previous node
+  };
+  std::vector<Node> path;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+        const int nsteps = s * (k - kb);  // planes between boundary and O
+        /* nodes from the boundary crossing (m = 0) to O (m = nsteps), plus the
+         * downwind crossing beyond O when it exists */
+        const int kend = k + s;
+        const bool hasP = (kend >= 0 && kend < nz);
+        const int nnodes = nsteps + 1 + (hasP ? 1 : 0);
+        path.assign(nnodes, Node());
+        for (int m = 0; m < nnodes; ++m) {
+          const int kk = kb + s * m;
+          const double dist = (pb.z[kk] - pb.z[k]) / ray.mu;  // signed path from O
+          const double fx = i + dist * ray.sx / dx, fy = j + dist * ray.sy / dy;
+          Node& nd = path[m];
+          nd.kap = interp_plane(f.kappa + (size_t)kk * np, nx, ny, fx, fy, pb.interp);
+          for (int c = 0; c < 6; ++c) {
+            nd.eta[c] = interp_plane(f.prop + c * N + (size_t)kk * np, nx, ny, fx, fy, pb.interp);
+            nd.eps[c] = interp_plane(f.emis + c * N + (size_t)kk * np, nx, ny, fx, fy, pb.interp);
+          }
+          nd.ds = (m == 0) ? 0.0 : std::fabs((pb.z[kk] - pb.z[kk - s]) / ray.mu);
+        }
+        double Ic[4] = {ray.up ? pb.i_bottom : 0.0, 0.0, 0.0, 0.0};
+        for (int m = 1; m <= nsteps; ++m) {
+          const Node &nM = path[m - 1], &nO = path[m];
+          const bool hp = (m + 1 < nnodes);
+          const Node* nP = hp ? &path[m + 1] : nullptr;
+          const double tauMO = 0.5 * (nM.kap + nO.kap) * phi * nO.ds;
+          const double tauOP = hp ? 0.5 * (nO.kap + nP->kap) * phi * nP->ds : 0.0;
+          double SM[4], SO[4], SP[4], cM[4], eM[6], eO[6], eP[6], hM[6], hO[6];
+          for (int c = 0; c < 6; ++c) {
+            eM[c] = nM.eps[c] * phi; eO[c] = nO.eps[c] * phi; eP[c] = hp ? nP->eps[c] * phi : 0.0;
+            hM[c] = nM.eta[c] * phi; hO[c] = nO.eta[c] * phi;
+          }
+          for (int st = 0; st < 4; ++st) {
+            SM[st] = emission(t, st, eM, pb.w2) / (nM.kap * phi);
+            SO[st] = emission(t, st, eO, pb.w2) / (nO.kap * phi);
+            SP[st] = hp ? emission(t, st, eP, pb.w2) / (nP->kap * phi) : 0.0;
+            cM[st] = hp ? besser_cm(SM[st], SO[st], SP[st], tauMO, tauOP) : 0.5 * (SM[st] + SO[st]);
+          }
+          double KM[4][4], KO[4][4];
+          kprime(hM, nM.kap * phi, KM);
+          kprime(hO, nO.kap * phi, KO);
+          const Coef<double> cf = coefficients(tauMO);
+          double b[4], A[4][4], x[4];
+          for (int a = 0; a < 4; ++a) {
+            double acc = cf.e * Ic[a];
+            for (int c = 0; c < 4; ++c) acc -= cf.psiM * KM[a][c] * Ic[c];
+            b[a] = acc + cf.omM * SM[a] + cf.omO * SO[a] + cf.omC * cM[a];
+            for (int c = 0; c < 4; ++c) A[a][c] = (a == c ? 1.0 : 0.0) + cf.psiO * KO[a][c];
+          }
+          gauss_solve<double, 4>(A, b, x);
+          for (int st = 0; st < 4; ++st) Ic[st] = x[st];
+        }
+        for (int st = 0; st < 4; ++st) Iout[4 * pO + st] = Ic[st];
+      }
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Formal solution of the selected rays and frequencies.
+ *   jkq   [10][N] accumulated (J00, J10, Re/Im J11, J20, Re/Im J21, Re/Im J22, Lambda-bar)
+ *   itop  [nray_sel][nfreq_sel][ny][nx][4]: I at the top plane (upward rays; zero for others)
+ *   ifull [nray_sel][nfreq_sel][N][4]:       I everywhere
+ *   lamf  [nray_sel][nfreq_sel][N]:          Lambda* everywhere
+ * Any output may be NULL.  Returns 0, or -1 for an invalid problem. */
+int oracle_fs_sweep(const oracle_problem* pb, const double* kappa, const double* prop,
+                    const double* emis, int nray_sel, const int* rays, int nfreq_sel,
+                    const int* freqs, double* jkq, double* itop, double* ifull, double* lamf,
+                    int nthreads) {
+  if (!valid_problem(pb) || !kappa || !prop || !emis || nray_sel < 0 || nfreq_sel < 0) return -1;
+  const size_t np = (size_t)pb->nx * pb->ny, N = np * pb->nz;
+  const int nrays = 2 * pb->nmu * pb->nchi;
+  for (int r = 0; r < nray_sel; ++r)
+    if (rays[r] < 0 || rays[r] >= nrays) return -1;
+  for (int q = 0; q < nfreq_sel; ++q)
+    if (freqs[q] < 0 || freqs[q] >= pb->nfreq) return -1;
+  const double fnorm = freq_norm(*pb);
+  const FieldsT<double> f{kappa, prop, emis};
+  const int nt = nthreads_of(nthreads);
+  const long npairs = (long)nray_sel * nfreq_sel;
+  std::vector<std::vector<double>> jpart(jkq ? nt : 0);
+  if (itop) std::memset(itop, 0, sizeof(double) * npairs * np * 4);
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double> I(4 * N), lam(N);
+    if (jkq) jpart[tid].assign(10 * N, 0.0);
+#pragma omp for schedule(static)
+    for (long pair = 0; pair < npairs; ++pair) {
+      const int r = rays[pair / nfreq_sel], jf = freqs[pair % nfreq_sel];
+      const Ray ray = make_ray(*pb, r);
+      sweep_one<double>(*pb, f, ray, jf, I.data(), lam.data());
+      if (jkq)
+        accumulate_j(ray, pb->wfreq[jf] * pb->phi[jf] / fnorm, I.data(), 1, N, lam.data(),
+                     N, jpart[tid].data());
+      if (itop && ray.up)
+        for (size_t q = 0; q < np; ++q)
+          for (int st = 0; st < 4; ++st)
+            itop[(pair * np + q) * 4 + st] = I[st * N + (size_t)(pb->nz - 1) * np + q];
+      if (ifull)
+        for (size_t q = 0; q < N; ++q)
+          for (int st = 0; st < 4; ++st) ifull[(pair * N + q) * 4 + st] = I[st * N + q];
+      if (lamf) std::memcpy(lamf + pair * N, lam.data(), sizeof(double) * N);
+    }
+  }
+  if (jkq)
+    for (int t = 0; t < nt; ++t)
+      for (size_t q = 0; q < 10 * N; ++q) jkq[q] += jpart[t][q];
+  return 0;
+}
+
+/* Complex-step variant: the inputs are (kappa + i h dkappa, prop + i h dprop,
+ * emis + i h demis); returns the real and imaginary parts of I at the top
+ * plane, [nray_sel][nfreq_sel][ny][nx][4], so Im/h is the exact directional
+ * derivative of the emergent Stokes vector along (dkappa, dprop, demis). */
+int oracle_fs_sweep_cs(const oracle_problem* pb, const double* kappa, const double* prop,
+                       const double* emis, const double* dkappa, const double* dprop,
+                       const double* demis, double h, int nray_sel, const int* rays,
+                       int nfreq_sel, const int* freqs, double* itop_re, double* itop_im,
+                       int nthreads) {
+  if (!valid_problem(pb) || !kappa || !prop || !emis || !dkappa || !dprop || !demis) return -1;
+  const size_t np = (size_t)pb->nx * pb->ny, N = np * pb->nz;
+  std::vector<cd> ck(N), cp(6 * N), ce(6 * N);
+  for (size_t p = 0; p < N; ++p) ck[p] = cd(kappa[p], h * dkappa[p]);
+  for (size_t p = 0; p < 6 * N; ++p) {
+    cp[p] = cd(prop[p], h * dprop[p]);
+    ce[p] = cd(emis[p], h * demis[p]);
+  }
+  const FieldsT<cd> f{ck.data(), cp.data(), ce.data()};
+  const long npairs = (long)nray_sel * nfreq_sel;
+  std::memset(itop_re, 0, sizeof(double) * npairs * np * 4);
+  std::memset(itop_im, 0, sizeof(double) * npairs * np * 4);
+  const int nt = nthreads_of(nthreads);
+#pragma omp parallel num_threads(nt)
+  {
+    std::vector<cd> I(4 * N);
+#pragma omp for schedule(static)
+    for (long pair = 0; pair < npairs; ++pair) {
+      const int r = rays[pair / nfreq_sel], jf = freqs[pair % nfreq_sel];
+      const Ray ray = make_ray(*pb, r);
+      if (!ray.up) continue;
+      sweep_one<cd>(*pb, f, ray, jf, I.data(), nullptr);
+      const size_t top = (size_t)(pb->nz - 1) * np;
+      for (size_t q = 0; q < np; ++q)
+        for (int st = 0; st < 4; ++st) {
+          itop_re[(pair * np + q) * 4 + st] = I[st * N + top + q].real();
+          itop_im[(pair * np + q) * 4 + st] = I[st * N + top + q].imag();
+        }
+    }
+  }
+  return 0;
+}
+
+/* Long-characteristics solution at every point, [nray_sel][nfreq_sel][N][4]. */
+int oracle_lc_sweep(const oracle_problem* pb, const double* kappa, const double* prop,
+                    const double* emis, int nray_sel, const int* rays, int nfreq_sel,
+                    const int* freqs, double* ifull) {
+  if (!valid_problem(pb) || !ifull) return -1;
+  const size_t N = (size_t)pb->nx * pb->ny * pb->nz;
+  const FieldsT<double> f{kappa, prop, emis};
+  for (int r = 0; r < nray_sel; ++r)
+    for (int q = 0; q < nfreq_sel; ++q)
+      lc_one(*pb, f, make_ray(*pb, rays[r]), freqs[q], ifull + ((size_t)r * nfreq_sel + q) * N * 4);
+  return 0;
+}
+
+/* Eq. 1 from a stored block of Stokes vectors, [nray][nf][N][4], for the rays
+ * ray0..ray0+nray-1 and frequencies f0..f0+nf-1; lam [nray][nf][N] or NULL. */
+int oracle_jkq_accumulate(const oracle_problem* pb, int ray0, int nray, int f0, int nf,
+                          const double* stokes, const double* lam, double* jkq) {
+  if (!valid_problem(pb) || !stokes || !jkq) return -1;
+  const int nrays = 2 * pb->nmu * pb->nchi;
+  if (ray0 < 0 || nray < 0 || ray0 + nray > nrays || f0 < 0 || nf < 0 || f0 + nf > pb->nfreq)
+    return -1;
+  const size_t N = (size_t)pb->nx * pb->ny * pb->nz;
+  const double fnorm = freq_norm(*pb);
+  for (int r = 0; r < nray; ++r) {
+    const Ray ray = make_ray(*pb, ray0 + r);
+    for (int q = 0; q < nf; ++q) {
+      const int jf = f0 + q;
+      const size_t off = ((size_t)r * nf + q) * N;
+      accumulate_j(ray, pb->wfreq[jf] * pb->phi[jf] / fnorm, stokes + 4 * off, 4, 1,
+                   lam ? lam + off : nullptr, N, jkq);
+    }
+  }
+  return 0;
+}
+
+/* One Jacobi update of the two-level (J_l = 0 -> J_u = 1) statistical
+ * equilibrium at every point.  s_old / s_new are [6][N] in the order
+ * S00, S20, Re S21, Im S21, Re S22, Im S22.
+ *   K = 0 (Jacobi with Lambda-bar):
+ *     S00 <- [(1-eps)(J00 - Lbar S00_old) + eps B] / [1 - (1-eps) Lbar]
+ *   K = 2 (Lambda iteration with Hanle rotation), Q = -2..2:
+ *     [1 + delta (1-eps)] S2_Q + i (1-eps) H sum_Q' Kmat_QQ'(b) S2_Q' = (1-eps) w2 conj(J2_Q)
+ *     with Kmat the matrix of b.J in the rank-2 representation.
+ * emis_new (= kappa * S_new) may be NULL; rc = max |dS00| / |S00_new|. */
+int oracle_see_update(int n, const double* jkq, const double* s_old, double eps_c, double delta2,
+                      double w2, double planck, const double* hanle, const double* bhat,
+                      const double* kappa, double* s_new, double* emis_new, double* rc) {
+  if (n < 0 || !jkq || !s_old || !s_new) return -1;
+  const size_t N = (size_t)n;
+  double rmax = 0.0;
+  for (size_t p = 0; p < N; ++p) {
+    const double J00 = jkq[0 * N + p], Lb = jkq[9 * N + p];
+    const double so = s_old[p];
+    const double s00 = ((1.0 - eps_c) * (J00 - Lb * so) + eps_c * planck) / (1.0 - (1.0 - eps_c) * Lb);
+    /* J^2_Q for Q = -2..2 from the stored Q >= 0 components */
+    cd J2[5];
+    J2[2] = cd(jkq[4 * N + p], 0.0);
+    J2[3] = cd(jkq[5 * N + p], jkq[6 * N + p]);
+    J2[4] = cd(jkq[7 * N + p], jkq[8 * N + p]);
+    J2[1] = -std::conj(J2[3]);
+    J2[0] = std::conj(J2[4]);
+    const double H = hanle ? hanle[p] : 0.0;
+    const double bx = bhat ? bhat[0 * N + p] : 0.0, by = bhat ? bhat[1 * N + p] : 0.0,
+                 bz = bhat ? bhat[2 * N + p] : 1.0;
+    cd A[5][5], rhs[5], x[5];
+    for (int a = 0; a < 5; ++a)
+      for (int c = 0; c < 5; ++c) A[a][c] = 0.0;
+    for (int qi = 0; qi < 5; ++qi) {
+      const int Q = qi - 2;
+      A[qi][qi] += 1.0 + delta2 * (1.0 - eps_c);
+      /* b.J: diagonal b_z Q; raising and lowering parts */
+      cd kd(bz * Q, 0.0);
+      A[qi][qi] += cd(0.0, (1.0 - eps_c) * H) * kd;
+      rhs[qi] = (1.0 - eps_c) * w2 * std::conj(J2[qi]);
+    }
+    for (int qpi = 0; qpi < 5; ++qpi) {
+      const int Qp = qpi - 2;
+      if (Qp + 1 <= 2) {  // <Q'+1| b.J |Q'>
+        const cd v = 0.5 * cd(bx, -by) * std::sqrt(6.0 - Qp * (Qp + 1.0));
+        A[qpi + 1][qpi] += cd(0.0, (1.0 - eps_c) * H) * v;
+      }
+      if (Qp - 1 >= -2) {  // <Q'-1| b.J |Q'>
+        const cd v = 0.5 * cd(bx, by) * std::sqrt(6.0 - Qp * (Qp - 1.0));
+        A[qpi - 1][qpi] += cd(0.0, (1.0 - eps_c) * H) * v;
+      }
+    }
+    /* complex Gaussian elimination with partial pivoting */
+    for (int c = 0; c < 5; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 5; ++r)
+        if (std::abs(A[r][c]) > std::abs(A[piv][c])) piv = r;
+      if (piv != c) {
+        for (int k = 0; k < 5; ++k) std::swap(A[c][k], A[piv][k]);
+        std::swap(rhs[c], rhs[piv]);
+      }
+      for (int r = c + 1; r < 5; ++r) {
+        const cd fct = A[r][c] / A[c][c];
+        for (int k = c; k < 5; ++k) A[r][k] -= fct * A[c][k];
+        rhs[r] -= fct * rhs[c];
+      }
+    }
+    for (int r = 4; r >= 0; --r) {
+      cd sacc = rhs[r];
+      for (int k = r + 1; k < 5; ++k) sacc -= A[r][k] * x[k];
+      x[r] = sacc / A[r][r];
+    }
+    s_new[0 * N + p] = s00;
+    s_new[1 * N + p] = x[2].real();
+    s_new[2 * N + p] = x[3].real();
+    s_new[3 * N + p] = x[3].imag();
+    s_new[4 * N + p] = x[4].real();
+    s_new[5 * N + p] = x[4].imag();
+    if (emis_new && kappa)
+      for (int c = 0; c < 6; ++c) emis_new[c * N + p] = kappa[p] * s_new[c * N + p];
+    const double rel = std::fabs(s00 - so) / std::fabs(s00);
+    if (rel > rmax) rmax = rel;
+  }
+  if (rc) *rc = rmax;
+  return 0;
+}
+
+/* ---- single-step helpers, exported for the pin tests ---------------------- */
+
+void oracle_coefficients(double tau, double* out6) {
+  const Coef<double> c = coefficients(tau);
+  out6[0] = c.e; out6[1] = c.psiM; out6[2] = c.psiO;
+  out6[3] = c.omM; out6[4] = c.omO; out6[5] = c.omC;
+}
+
+double oracle_besser_cm(double yM, double yO, double yP, double hM, double hP) {
+  return besser_cm(yM, yO, yP, hM, hP);
+}
+
+double oracle_bezier1d(double ym, double y0, double yp, double t) {
+  return bezier1d(ym, y0, yp, t);
+}
+
+double oracle_interp_plane(const double* f, int nx, int ny, double fx, double fy, int mode) {
+  return interp_plane(f, nx, ny, fx, fy, mode);
+}
+
+/* T^K_Q(i, Omega) for all 9 (K, Q) slots (K=0; K=1, Q=-1..1; K=2, Q=-2..2). */
+void oracle_tkq(double mu, double chi, double* re36, double* im36) {
+  Cx<double> t[4][9];
+  tkq(mu, chi, t);
+  for (int i = 0; i < 4; ++i)
+    for (int s = 0; s < 9; ++s) {
+      re36[9 * i + s] = t[i][s].re;
+      im36[9 * i + s] = t[i][s].im;
+    }
+}
+
+/* Emission vector (eps_I, eps_Q, eps_U, eps_V) of one ray from the 6 multipoles. */
+void oracle_emission(double mu, double chi, const double* e6, double w2, double* out4) {
+  Cx<double> t[4][9];
+  tkq(mu, chi, t);
+  for (int i = 0; i < 4; ++i) out4[i] = emission(t, i, e6, w2);
+}
+
+void oracle_solve4(const double* A16, const double* b4, double* x4) {
+  double A[4][4], b[4], x[4];
+  for (int a = 0; a < 4; ++a) {
+    b[a] = b4[a];
+    for (int c = 0; c < 4; ++c) A[a][c] = A16[4 * a + c];
+  }
+  gauss_solve<double, 4>(A, b, x);
+  for (int a = 0; a < 4; ++a) x4[a] = x[a];
+}
+
+}  // extern "C"

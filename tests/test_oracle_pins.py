@@ -1,0 +1,774 @@
+"""Pins of the FP64 CPU oracle against the paper and against mathematics.
+
+Each test compares the oracle with something other than its own formulas:
+numbers printed in the paper (tests/golden), closed-form solutions of the
+transfer equation, quadrature of the defining integrals, dipole-scattering
+geometry, brute-force long characteristics and an ODE integrator.
+"""
+import json
+import math
+import os
+import types
+
+import numpy as np
+import pytest
+from scipy.integrate import quad, solve_ivp
+from scipy.linalg import expm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- helpers
+def mk_atm(nx, ny, nz, lx, ly, z, kappa, prop=None, emis=None, i_bottom=0.0, w2=1.0):
+    n = nx * ny * nz
+    return types.SimpleNamespace(
+        nx=nx, ny=ny, nz=nz, lx=float(lx), ly=float(ly), z=np.asarray(z, float),
+        kappa=np.asarray(kappa, float).reshape(n),
+        propmat=np.zeros((6, n)) if prop is None else np.asarray(prop, float).reshape(6, n),
+        emis=np.zeros((6, n)) if emis is None else np.asarray(emis, float).reshape(6, n),
+        i_bottom=float(i_bottom), w2=float(w2))
+
+
+def mk_quad(mu, wmu, nchi, phi=(1.0,), wfreq=(1.0,)):
+    return types.SimpleNamespace(mu=np.asarray(mu, float), wmu=np.asarray(wmu, float),
+                                 nchi=int(nchi), phi=np.asarray(phi, float),
+                                 wfreq=np.asarray(wfreq, float), x=np.zeros(len(phi)))
+
+
+def gl_hemi(n):
+    t, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (t + 1), 0.5 * w
+
+
+# --------------------------------------------------------------------------- P1 coefficients
+TAUS = np.concatenate([np.logspace(-6, 2, 41), [0.0999, 0.1001, 0.1399, 0.1401, 0.1799, 0.1801]])
+
+
+def _defining_integrals(tau):
+    """Weights of the quadratic Bezier basis (and of the linear basis for K'I) in
+    t/tau, integrated against exp(-t) from O (t=0) to M (t=tau)."""
+    def f(g):  # substitute t = tau s
+        return tau * quad(lambda s: g(s) * math.exp(-tau * s), 0.0, 1.0, epsabs=0.0,
+                          epsrel=1e-13, limit=200)[0]
+    return dict(psiM=f(lambda s: s), psiO=f(lambda s: 1 - s), omM=f(lambda s: s * s),
+                omO=f(lambda s: (1 - s) ** 2), omC=f(lambda s: 2 * s * (1 - s)))
+
+
+@pytest.mark.parametrize("tau", TAUS)
+def test_coefficients_equal_defining_integrals(orc, tau):
+    e, psiM, psiO, omM, omO, omC = orc.coefficients(tau)
+    ref = _defining_integrals(tau)
+    assert e == pytest.approx(math.exp(-tau), rel=1e-15)
+    for name, val in dict(psiM=psiM, psiO=psiO, omM=omM, omO=omO, omC=omC).items():
+        assert val == pytest.approx(ref[name], rel=2e-12, abs=0), name
+
+
+@pytest.mark.parametrize("tau", TAUS)
+def test_coefficient_partitions_of_unity(orc, tau):
+    e, psiM, psiO, omM, omO, omC = orc.coefficients(tau)
+    one_minus_e = -math.expm1(-tau)
+    assert omM + omO + omC == pytest.approx(one_minus_e, rel=1e-13)
+    assert psiM + psiO == pytest.approx(one_minus_e, rel=1e-13)
+
+
+def test_table1_series_match_paper(orc):
+    tab = json.load(open(os.path.join(GOLDEN, "table1_taylor.json")))["rows"]
+    slot = {"omega_M": 3, "omega_O": 4, "omega_C": 5}
+    for name, row in tab.items():
+        # the python transcription must be the printed expression with '*' inserted
+        printed = row["printed"].replace(" ", "")
+        py = row["python"].replace("*", "")
+        assert py == printed, name
+        for t in np.linspace(1e-4, row["max_t"] * 0.999, 25):
+            val = eval(row["python"], {"__builtins__": {}}, {"t": float(t)})
+            assert orc.coefficients(t)[slot[name]] == pytest.approx(val, rel=1e-14), (name, t)
+
+
+def test_series_and_closed_forms_join_at_thresholds(orc):
+    for thr in (0.1, 0.14, 0.18):
+        lo = orc.coefficients(thr * (1 - 1e-9))
+        hi = orc.coefficients(thr * (1 + 1e-9))
+        np.testing.assert_allclose(lo, hi, rtol=1e-8)
+
+
+def test_coefficients_at_zero_tau(orc):
+    np.testing.assert_array_equal(orc.coefficients(0.0), [1, 0, 0, 0, 0, 0])
+
+
+# --------------------------------------------------------------------------- P2 Lambda*
+def test_lambda_star_range_and_limits(orc):
+    taus = np.logspace(-8, 3, 200)
+    lam = np.array([orc.coefficients(t)[4] + orc.coefficients(t)[5] for t in taus])
+    assert np.all(lam >= 0) and np.all(lam < 1)
+    assert lam[0] == pytest.approx(2 * taus[0] / 3, rel=1e-6)
+    assert lam[-1] > 0.998
+    # unit source at O only: the control point sits at the local maximum
+    assert orc.besser_cm(0.0, 1.0, 0.0, 0.7, 2.3) == 1.0
+
+
+def test_lambda_star_is_response_to_unit_source(orc):
+    """Lambda* of the sweep equals I_O for S = delta_O with nothing incident (Sect. 3.3)."""
+    nz = 9
+    z = np.linspace(0, 8, nz)
+    kap = np.full(nz, 0.37)
+    q = mk_quad([1.0], [1.0], 1)
+    base = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap), q), rays=[0],
+                        want_j=False, want_itop=False, want_lambda=True)["lam"][0, 0]
+    for k in range(1, nz):
+        e = np.zeros((6, nz))
+        e[0, k] = kap[k]          # S00 = 1 at node k only
+        out = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap, emis=e), q),
+                           rays=[0], want_j=False, want_itop=False, want_full=True)
+        assert out["ifull"][0, 0, k, 0] == pytest.approx(base[k], rel=1e-13)
+
+
+# --------------------------------------------------------------------------- BESSER control points
+def _rand_triple(rng, monotone):
+    y = np.sort(rng.normal(size=3)) * rng.choice([-1, 1])
+    if monotone:
+        return y
+    y = rng.normal(size=3)
+    if (y[1] - y[0]) * (y[2] - y[1]) > 0:
+        y[1] = max(y[0], y[2]) + abs(rng.normal())
+    return y
+
+
+def test_besser_monotone_and_smooth(orc):
+    rng = np.random.default_rng(11)
+    for _ in range(3000):
+        hM, hP = np.exp(rng.uniform(-5, 3, 2))
+        yM, yO, yP = _rand_triple(rng, True)
+        cM = orc.besser_cm(yM, yO, yP, hM, hP)
+        cP = orc.besser_cm(yP, yO, yM, hP, hM)   # read the other way round
+        tol = 1e-12 * (1 + abs(yM) + abs(yO) + abs(yP))
+        assert min(yM, yO) - tol <= cM <= max(yM, yO) + tol
+        assert min(yO, yP) - tol <= cP <= max(yO, yP) + tol
+        dl, dr = 2 * (yO - cM) / hM, 2 * (cP - yO) / hP
+        assert dl == pytest.approx(dr, rel=1e-9, abs=1e-9 * (abs(dl) + 1e-300))
+
+
+def test_besser_extremum_at_centre(orc):
+    rng = np.random.default_rng(12)
+    for _ in range(500):
+        hM, hP = np.exp(rng.uniform(-3, 3, 2))
+        yM, yO, yP = _rand_triple(rng, False)
+        assert orc.besser_cm(yM, yO, yP, hM, hP) == yO
+        assert orc.besser_cm(yP, yO, yM, hP, hM) == yO
+
+
+def test_besser_reproduces_monotone_parabola(orc):
+    rng = np.random.default_rng(13)
+    for _ in range(300):
+        hM, hP = np.exp(rng.uniform(-2, 2, 2))
+        c = rng.normal()
+        x1 = hM + hP
+        # slope b chosen so that the parabola is monotone on [0, x1]
+        # |b| > 2 |c| x1 puts the vertex outside [0, x1]
+        b = (abs(2 * c * x1) + abs(rng.normal()) + 0.1) * rng.choice([-1, 1])
+        par = lambda x: 0.3 + b * x + c * x * x
+        yM, yO, yP = par(0.0), par(hM), par(x1)
+        assert (yO - yM) * (yP - yO) > 0
+        cM = orc.besser_cm(yM, yO, yP, hM, hP)
+        for u in np.linspace(0, 1, 7):
+            bez = (1 - u) ** 2 * yM + 2 * u * (1 - u) * cM + u * u * yO
+            assert bez == pytest.approx(par(u * hM), rel=1e-10, abs=1e-10)
+
+
+def test_bezier1d_symmetry_and_quadratic(orc):
+    rng = np.random.default_rng(14)
+    for _ in range(300):
+        ym, y0, yp = rng.normal(size=3)
+        t = rng.uniform(-0.5, 0.5)
+        assert orc.bezier1d(ym, y0, yp, t) == pytest.approx(orc.bezier1d(yp, y0, ym, -t),
+                                                            rel=1e-13, abs=1e-13)
+    # monotone quadratic -> Lagrange quadratic through (-1, 0, 1)
+    q = lambda x: 2.0 + 0.7 * x + 0.2 * x * x
+    for t in np.linspace(-0.5, 0.5, 11):
+        assert orc.bezier1d(q(-1), q(0), q(1), t) == pytest.approx(q(t), rel=1e-14)
+
+
+# --------------------------------------------------------------------------- interpolation
+def test_bilinear_exact_and_periodic(orc):
+    ny, nx = 6, 8
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    f = 0.5 + 0.3 * ii - 0.2 * jj + 0.05 * ii * jj
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        fx, fy = rng.uniform(0, nx - 1), rng.uniform(0, ny - 1)
+        assert orc.interp_plane(f, fx, fy, 0) == pytest.approx(
+            0.5 + 0.3 * fx - 0.2 * fy + 0.05 * fx * fy, rel=1e-13)
+        assert orc.interp_plane(f, fx, fy, 0) == pytest.approx(
+            orc.interp_plane(f, fx + 3 * nx, fy - 2 * ny, 0), rel=1e-12)
+
+
+def test_bezier2d_reproduces_monotone_biquadratic(orc):
+    ny, nx = 12, 12
+    jj, ii = np.mgrid[0:ny, 0:nx].astype(float)
+    g = lambda x, y: (x + 10) ** 2 + 0.5 * (y + 10) ** 2 + 0.1 * (x + 10) * (y + 10)
+    f = g(ii, jj)
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        fx, fy = rng.uniform(1, nx - 2), rng.uniform(1, ny - 2)
+        assert orc.interp_plane(f, fx, fy, 1) == pytest.approx(g(fx, fy), rel=1e-13)
+
+
+def test_bezier2d_no_overshoot(orc):
+    """Monotone data along each row and column -> value inside the 3x3 range."""
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        f = np.cumsum(np.cumsum(rng.exponential(size=(5, 5)), axis=0), axis=1)
+        f[:, :] = f ** 3   # strongly curved, still monotone
+        fx, fy = rng.uniform(1.5, 2.5), rng.uniform(1.5, 2.5)
+        v = orc.interp_plane(f, fx, fy, 1)
+        i0, j0 = int(math.floor(fx + 0.5)), int(math.floor(fy + 0.5))
+        blk = f[j0 - 1:j0 + 2, i0 - 1:i0 + 2]
+        assert blk.min() - 1e-9 <= v <= blk.max() + 1e-9
+
+
+# --------------------------------------------------------------------------- P12 T^K_Q
+def _basis(mu, chi):
+    st = math.sqrt(max(0.0, 1 - mu * mu))
+    om = np.array([st * math.cos(chi), st * math.sin(chi), mu])
+    ea = np.array([mu * math.cos(chi), mu * math.sin(chi), -st])
+    eb = np.array([-math.sin(chi), math.cos(chi), 0.0])
+    return om, ea, eb
+
+
+def _dipole_matrix(o_in, o_out):
+    """3x3 (I, Q, U) scattering matrix of an isotropic dipole scatterer."""
+    _, a1, b1 = _basis(*o_in)
+    _, a2, b2 = _basis(*o_out)
+    M = np.zeros((3, 3))
+    for j, stokes in enumerate(np.eye(3)):
+        I, Q, U = stokes
+        C = 0.5 * ((I + Q) * np.outer(a1, a1) + (I - Q) * np.outer(b1, b1)
+                   + U * (np.outer(a1, b1) + np.outer(b1, a1)))
+        M[0, j] = a2 @ C @ a2 + b2 @ C @ b2
+        M[1, j] = a2 @ C @ a2 - b2 @ C @ b2
+        M[2, j] = a2 @ C @ b2 + b2 @ C @ a2
+    return M
+
+
+def test_tkq_hermiticity(orc):
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        t = orc.tkq(rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi))
+        for K, base in ((1, 2), (2, 6)):
+            for Q in range(1, K + 1):
+                np.testing.assert_allclose(t[:, base - Q], (-1) ** Q * np.conj(t[:, base + Q]),
+                                           atol=1e-15)
+
+
+def test_tkq_give_dipole_scattering_matrix(orc):
+    """sum_KQ (-1)^Q T^K_Q(i, out) T^K_-Q(j, in) = 3/2 x dipole scattering (K = 0, 2 for
+    I,Q,U) and 3/2 cos(Theta) for V-V (K = 1)."""
+    rng = np.random.default_rng(7)
+    slots = {0: [(0, 0)], 1: [(1, q) for q in (-1, 0, 1)], 2: [(2, q) for q in range(-2, 3)]}
+    idx = lambda K, Q: 0 if K == 0 else (2 + Q if K == 1 else 6 + Q)
+    for _ in range(30):
+        o_in = (rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi))
+        o_out = (rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi))
+        ti, to = orc.tkq(*o_in), orc.tkq(*o_out)
+        P = np.zeros((3, 3), complex)
+        for i in range(3):
+            for j in range(3):
+                for K in (0, 2):
+                    for (_, Q) in slots[K]:
+                        P[i, j] += (-1) ** Q * to[i, idx(K, Q)] * ti[j, idx(K, -Q)]
+        np.testing.assert_allclose(P.imag, 0, atol=1e-14)
+        np.testing.assert_allclose(P.real, 1.5 * _dipole_matrix(o_in, o_out), atol=1e-13)
+        pv = sum((-1) ** Q * to[3, idx(1, Q)] * ti[3, idx(1, -Q)] for (_, Q) in slots[1])
+        cos_theta = _basis(*o_in)[0] @ _basis(*o_out)[0]
+        assert pv.real == pytest.approx(1.5 * cos_theta, abs=1e-13)
+
+
+def test_emission_is_real_projection(orc):
+    """eps_i(Omega) for S^2_0 only is axisymmetric; U = V = 0 (Q reference e_a)."""
+    e = np.array([0.0, 1.0, 0, 0, 0, 0])
+    for mu in (0.2, 0.7):
+        a = orc.emission(mu, 0.3, e)
+        b = orc.emission(mu, 2.1, e)
+        np.testing.assert_allclose(a, b, atol=1e-15)
+        assert a[2] == 0 and a[3] == 0
+        assert a[1] == pytest.approx(-3 / (2 * math.sqrt(2)) * (1 - mu * mu), rel=1e-14)
+
+
+def test_emission_of_single_beam_multipoles_is_dipole_scattering(orc):
+    """Multipoles S^2_Q = conj(T^2_Q(I, Omega')) of one unpolarized beam from Omega' emit
+    eps_i(Omega) = 3/2 D_iI(Omega', Omega) - delta_iI (the K = 2 part of the dipole
+    scattering of that beam)."""
+    rng = np.random.default_rng(8)
+    for _ in range(30):
+        o_in = (rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi))
+        o_out = (rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi))
+        t_in = orc.tkq(*o_in)
+        s21, s22 = np.conj(t_in[0, 7]), np.conj(t_in[0, 8])
+        e = np.array([0.0, np.conj(t_in[0, 6]).real, s21.real, s21.imag, s22.real, s22.imag])
+        eps = orc.emission(*o_out, e, w2=1.0)
+        D = 1.5 * _dipole_matrix(o_in, o_out)[:, 0]
+        np.testing.assert_allclose(eps[:3], D - np.array([1.0, 0, 0]), atol=1e-13)
+        assert eps[3] == 0.0
+
+
+# --------------------------------------------------------------------------- P11 quadrature
+def test_j_of_isotropic_and_polynomial_fields(orc):
+    mu, w = gl_hemi(5)
+    q = mk_quad(mu, w, 8, phi=[0.2, 1.0, 0.2], wfreq=[0.5, 1.0, 0.5])
+    atm = mk_atm(2, 2, 2, 1, 1, [0, 1], np.ones(8))
+    op = orc.OracleProblem(atm, q)
+    nr = op.nrays
+    st = np.zeros((nr, 3, 8, 4))
+    st[..., 0] = 1.0
+    J = orc.jkq_accumulate(op, 0, 0, st)
+    np.testing.assert_allclose(J[0], 1.0, rtol=1e-14)
+    np.testing.assert_allclose(J[1:9], 0.0, atol=1e-15)
+    # I = 1 + mu^2 (Stokes I), V = mu
+    rt = orc.ray_table(op)
+    st[:] = 0
+    for r, (m, chi, _) in enumerate(rt):
+        st[r, :, :, 0] = 1 + m * m
+        st[r, :, :, 3] = m
+    J = orc.jkq_accumulate(op, 0, 0, st)
+    np.testing.assert_allclose(J[0], 4.0 / 3.0, rtol=1e-14)
+    np.testing.assert_allclose(J[4], (1 / (2 * math.sqrt(2))) * (4.0 / 15.0), rtol=1e-13)
+    np.testing.assert_allclose(J[1], math.sqrt(1.5) / 3.0, rtol=1e-13)
+    np.testing.assert_allclose(J[[2, 3, 5, 6, 7, 8]], 0.0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- P3 slabs
+def test_homogeneous_slab_closed_form(orc):
+    nz = 12
+    z = np.linspace(0, 100, nz)
+    kap0, S = 0.013, 0.8
+    mu, w = gl_hemi(3)
+    q = mk_quad(mu, w, 4, phi=[1.0, 0.3, 0.01], wfreq=[1, 1, 1])
+    n = 4 * 4 * nz
+    e = np.zeros((6, n))
+    e[0] = kap0 * S
+    atm = mk_atm(4, 4, nz, 40, 40, z, np.full(n, kap0), emis=e)
+    op = orc.OracleProblem(atm, q)
+    out = orc.fs_sweep(op, want_full=True)
+    full = out["ifull"].reshape(op.nrays, 3, nz, 16, 4)
+    for r, (m, _, _) in enumerate(orc.ray_table(op)):
+        for jf, ph in enumerate(q.phi):
+            depth = (z - z[0]) if m > 0 else (z[-1] - z)
+            expect = S * (1 - np.exp(-kap0 * ph * depth / abs(m)))
+            np.testing.assert_allclose(full[r, jf, :, :, 0], expect[:, None] * np.ones(16),
+                                       rtol=1e-12, atol=1e-16)
+            np.testing.assert_array_equal(full[r, jf, :, :, 1:], 0.0)
+    # top intensity of upward rays
+    for r in range(op.nrays // 2):
+        m = orc.ray_table(op)[r][0]
+        for jf, ph in enumerate(q.phi):
+            np.testing.assert_allclose(out["itop"][r, jf, ..., 0],
+                                       S * (1 - math.exp(-kap0 * ph * 100 / m)), rtol=1e-12)
+
+
+def _slab_dichroic(orc, nz, mu):
+    z = np.linspace(0, 1, nz)
+    kap0, S = 2.0, 1.0
+    prop_lc = np.array([0.08, -0.05, 0.06, 0.04, 0.07, -0.03])
+    n = nz
+    e = np.zeros((6, n))
+    e[0] = kap0 * S
+    atm = mk_atm(1, 1, nz, 1, 1, z, np.full(n, kap0), prop=np.outer(prop_lc * kap0, np.ones(n)),
+                 emis=e)
+    q = mk_quad([mu], [1.0], 1)
+    return orc.fs_sweep(orc.OracleProblem(atm, q), rays=[0])["itop"][0, 0, 0, 0], prop_lc, kap0, S
+
+
+def test_homogeneous_dichroic_slab_converges_to_matrix_exponential(orc):
+    """Constant propagation matrix: I_top = (1 - exp(-K T)) K^-1 (S,0,0,0), second order."""
+    mu = 1.0
+    errs = []
+    for nz in (11, 21, 41, 81):
+        itop, (eQ, eU, eV, rQ, rU, rV), kap0, S = _slab_dichroic(orc, nz, mu)
+        Kt = np.array([[1, eQ, eU, eV], [eQ, 1, rV, -rU], [eU, -rV, 1, rQ], [eV, rU, -rQ, 1]])
+        T = kap0 * 1.0 / mu
+        exact = (np.eye(4) - expm(-Kt * T)) @ np.linalg.solve(Kt, np.array([S, 0, 0, 0]))
+        errs.append(np.abs(itop - exact).max())
+        assert abs(itop[1]) > 1e-3   # dichroism produces polarization
+    errs = np.array(errs)
+    assert errs[-1] < 1e-5
+    assert np.all(errs[:-1] / errs[1:] > 3.0)   # second order
+
+
+def test_linear_source_eddington_barbier(orc):
+    """S = a + b tau_z in a plane-parallel, horizontally homogeneous slab: I(mu) = a + b mu."""
+    nz = 40
+    z = np.linspace(0, 10, nz)
+    kz = 4.0 * np.exp(-z / 2.0) + 0.05
+    # vertical optical depth from the top with the trapezoid rule used by the solver
+    dt = 0.5 * (kz[1:] + kz[:-1]) * np.diff(z)
+    tauz = np.concatenate([np.cumsum(dt[::-1])[::-1], [0.0]])
+    scale = 45.0 / tauz[0]
+    kz *= scale
+    tauz *= scale
+    a, b = 0.7, 1.3
+    Sz = a + b * tauz
+    nx = ny = 3
+    kap = np.repeat(kz, nx * ny)
+    e = np.zeros((6, kap.size))
+    e[0] = kap * np.repeat(Sz, nx * ny)
+    mu, w = gl_hemi(5)
+    atm = mk_atm(nx, ny, nz, 7, 5, z, kap, emis=e, i_bottom=a + b * tauz[0])
+    op = orc.OracleProblem(atm, mk_quad(mu, w, 4))
+    itop = orc.fs_sweep(op, rays=np.arange(op.nrays // 2), want_j=False)["itop"]
+    for r in range(op.nrays // 2):
+        m = orc.ray_table(op)[r][0]
+        np.testing.assert_allclose(itop[r, 0, ..., 0], a + b * m, rtol=1e-12)
+
+
+def _vertical_1d(orc, z, kap, S, i0):
+    nz = len(z)
+    e = np.zeros((6, nz))
+    e[0] = kap * S
+    atm = mk_atm(1, 1, nz, 1, 1, z, kap, emis=e, i_bottom=i0)
+    out = orc.fs_sweep(orc.OracleProblem(atm, mk_quad([1.0], [1.0], 1)), rays=[0],
+                       want_j=False, want_itop=False, want_full=True)
+    return out["ifull"][0, 0, :, 0]
+
+
+def test_quadratic_source_exact_except_last_plane(orc):
+    z = np.linspace(0, 6, 25)
+    kap = np.ones_like(z)
+    S = 0.5 + 0.4 * z + 0.06 * z * z          # monotone on [0, 6]
+    i0 = 0.2
+    I = _vertical_1d(orc, z, kap, S, i0)
+    # exact: I_p = S - S' + S'' for dI/dtau = S - I, plus the decaying homogeneous part
+    Ip = lambda t: (0.5 + 0.4 * t + 0.06 * t * t) - (0.4 + 0.12 * t) + 0.12
+    exact = Ip(z) + (i0 - Ip(0.0)) * np.exp(-z)
+    np.testing.assert_allclose(I[:-1], exact[:-1], rtol=1e-12)
+    assert abs(I[-1] - exact[-1]) > 1e-9      # linear control point on the last plane
+
+
+def test_sigmoid_accuracy_against_analytic_solution(orc):
+    g = json.load(open(os.path.join(GOLDEN, "sigmoid_test.json")))
+    sig = lambda a, d, z: 1.0 / (1.0 + np.exp(-a * (z - d)))
+    Ia = lambda z: (np.exp(15 - z) / (math.exp(20) - 1)
+                    * (math.exp(10) * np.arctan(np.exp(z - 5)) - np.arctan(np.exp(z + 5))))
+    # the analytic formula reproduces the printed boundary value
+    assert Ia(g["z_min"]) == pytest.approx(g["I_boundary_printed"], rel=5e-6)
+    errs = []
+    for dtau in (1.0, 0.5, 0.25, 0.125, 0.0625):
+        n = int(round((g["z_max"] - g["z_min"]) / dtau)) + 1
+        z = np.linspace(g["z_min"], g["z_max"], n)
+        S = sig(2, -5, z) * sig(-2, 5, z)
+        I = _vertical_1d(orc, z, np.ones(n), S, Ia(g["z_min"]))
+        errs.append(np.max(np.abs((I[:-1] - Ia(z[:-1])) / Ia(z[:-1]))))
+    errs = np.array(errs)
+    assert errs[-1] < 2e-3
+    assert np.all(np.diff(errs[1:]) < 0)
+    assert errs[1] / errs[-1] > 20       # close to second order over a factor 8 in dtau
+
+
+# --------------------------------------------------------------------------- P7 / P8 symmetry
+def _random_atm(nx, ny, nz, seed, polarized=True, dichroic=True):
+    rng = np.random.default_rng(seed)
+    n = nx * ny * nz
+    z = np.linspace(0, 400, nz)
+    kap = (0.5 * np.exp(-z / 80.0))[:, None] * np.exp(0.3 * rng.normal(size=(nx * ny)))[None, :]
+    kap = kap.reshape(n)
+    S = np.zeros((6, n))
+    S[0] = rng.uniform(0.5, 1.5, n)
+    if polarized:
+        S[1:] = rng.uniform(-0.05, 0.05, (5, n))
+    prop = kap * rng.uniform(-0.05, 0.05, (6, n)) if dichroic else np.zeros((6, n))
+    return mk_atm(nx, ny, nz, 300, 250, z, kap, prop=prop, emis=kap * S, i_bottom=1.0)
+
+
+def test_unpolarized_limit(orc):
+    atm = _random_atm(5, 4, 7, 21, polarized=False, dichroic=False)
+    mu, w = gl_hemi(3)
+    op = orc.OracleProblem(atm, mk_quad(mu, w, 4, phi=[1, 0.4], wfreq=[1, 1]))
+    out = orc.fs_sweep(op, want_full=True)
+    assert np.all(out["ifull"][..., 1:] == 0.0)
+    np.testing.assert_array_equal(out["jkq"][1:4], 0.0)
+
+
+def test_axisymmetric_plane_parallel(orc):
+    nz = 8
+    z = np.linspace(0, 300, nz)
+    kz = 0.3 * np.exp(-z / 60)
+    nx = ny = 3
+    kap = np.repeat(kz, nx * ny)
+    S = np.zeros((6, kap.size))
+    S[0] = np.repeat(np.linspace(1.4, 0.6, nz), nx * ny)
+    S[1] = np.repeat(np.linspace(0.0, 0.05, nz), nx * ny)
+    mu, w = gl_hemi(4)
+    atm = mk_atm(nx, ny, nz, 10, 10, z, kap, emis=kap * S, i_bottom=1.2)
+    op = orc.OracleProblem(atm, mk_quad(mu, w, 8, phi=[1, 0.2], wfreq=[1, 1]))
+    out = orc.fs_sweep(op)
+    it = out["itop"]
+    assert np.abs(it[..., 2:]).max() < 1e-15
+    assert np.abs(it[..., 1]).max() > 1e-3
+    for a in range(4):
+        qa = it[a * 8:(a + 1) * 8, :, :, :, 1]
+        np.testing.assert_allclose(qa, qa[0:1].repeat(8, 0), rtol=1e-12, atol=1e-16)
+    J = out["jkq"]
+    np.testing.assert_allclose(J[[1, 2, 3, 5, 6, 7, 8]], 0.0, atol=1e-15)
+    assert np.abs(J[4]).max() > 1e-3
+
+
+# --------------------------------------------------------------------------- P9 shift invariance
+def test_periodic_shift_invariance(orc):
+    nx, ny, nz = 6, 5, 6
+    atm = _random_atm(nx, ny, nz, 31)
+    mu, w = gl_hemi(2)
+    q = mk_quad(mu, w, 4, phi=[1, 0.3], wfreq=[1, 1])
+    out = orc.fs_sweep(orc.OracleProblem(atm, q))
+    di, dj = 2, 3
+    roll = lambda a: np.roll(a.reshape(a.shape[:-1] + (nz, ny, nx)), (dj, di), axis=(-2, -1)
+                             ).reshape(a.shape)
+    atm2 = mk_atm(nx, ny, nz, atm.lx, atm.ly, atm.z, roll(atm.kappa[None])[0],
+                  prop=roll(atm.propmat), emis=roll(atm.emis), i_bottom=1.0)
+    out2 = orc.fs_sweep(orc.OracleProblem(atm2, q))
+    np.testing.assert_allclose(out2["jkq"], roll(out["jkq"]), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out2["itop"], np.roll(out["itop"], (dj, di), axis=(2, 3)),
+                               rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- P10 long characteristics
+def test_node_aligned_rays_equal_long_characteristics(orc):
+    nx = ny = 4
+    nz = 8
+    dz = 1.0
+    z = np.arange(nz) * dz
+    # inclination with tan(theta) = sqrt(2) dx/dz: at chi = (m + 1/2) pi/2 each plane shifts by
+    # exactly one cell in x and y
+    dx = 1.0
+    mu0 = 1.0 / math.sqrt(1.0 + 2.0 * (dx / dz) ** 2)
+    rng = np.random.default_rng(41)
+    n = nx * ny * nz
+    kap = 0.3 * np.exp(0.4 * rng.normal(size=n))
+    S = np.zeros((6, n))
+    S[0] = rng.uniform(0.5, 1.5, n)
+    S[1:] = rng.uniform(-0.05, 0.05, (5, n))
+    prop = kap * rng.uniform(-0.05, 0.05, (6, n))
+    for interp in (0, 1):
+        for mus in ([mu0], [1.0]):
+            atm = mk_atm(nx, ny, nz, nx * dx, ny * dx, z, kap, prop=prop, emis=kap * S,
+                         i_bottom=1.0)
+            op = orc.OracleProblem(atm, mk_quad(mus, [1.0], 4, phi=[1, 0.3], wfreq=[1, 1]),
+                                   interp=interp)
+            rays = np.arange(op.nrays)
+            sc = orc.fs_sweep(op, want_full=True, want_j=False)["ifull"]
+            lc = orc.lc_sweep(op, rays, [0, 1])
+            np.testing.assert_allclose(sc, lc, rtol=1e-13, atol=1e-13)
+
+
+def test_general_rays_approach_long_characteristics_under_refinement(orc):
+    """SC differs from LC by the horizontal diffusion of interpolated I; it shrinks with
+    horizontal refinement (reported, loose gate)."""
+    diffs = []
+    for nh in (4, 8, 16):
+        nz = 6
+        z = np.linspace(0, 5, nz)
+        L = 8.0
+        xs = (np.arange(nh) + 0.0) * L / nh
+        X, Y = np.meshgrid(xs, xs)
+        kap = np.tile((0.4 * (1 + 0.3 * np.sin(2 * np.pi * X / L) * np.cos(2 * np.pi * Y / L))
+                       ).ravel(), nz)
+        S = np.zeros((6, kap.size))
+        S[0] = np.tile((1 + 0.5 * np.sin(2 * np.pi * (X + 2 * Y) / L)).ravel(), nz)
+        atm = mk_atm(nh, nh, nz, L, L, z, kap, emis=kap * S, i_bottom=1.0)
+        op = orc.OracleProblem(atm, mk_quad([0.45], [1.0], 4))
+        sc = orc.fs_sweep(op, rays=[0], want_full=True, want_j=False)["ifull"]
+        lc = orc.lc_sweep(op, [0], [0])
+        diffs.append(np.abs(sc - lc)[..., 0].max())
+    assert diffs[2] < diffs[0]
+
+
+def test_inclined_ray_direction_against_ode(orc):
+    """Node-aligned inclined ray through smooth periodic fields: the SC solution at the
+    top converges to the ODE dI/ds = kappa (S - I) integrated along the true ray."""
+    L = 16.0
+    ztop = 8.0
+    kfun = lambda x, y, z: 0.35 * (1 + 0.3 * np.sin(2 * np.pi * x / L) * np.cos(2 * np.pi * y / L)
+                                   ) * np.exp(-z / 6.0)
+    sfun = lambda x, y, z: 1 + 0.5 * np.sin(2 * np.pi * (x + 2 * y) / L) + 0.2 * z / ztop
+    chi = math.pi / 4
+    errs, mirrored = [], None
+    for n in (16, 32, 64):
+        d = L / n
+        nz = int(round(ztop / d)) + 1
+        z = np.arange(nz) * d
+        mu0 = 1.0 / math.sqrt(3.0)     # tan(theta) = sqrt(2): one cell per plane in x and y
+        Z, Y, X = np.meshgrid(z, np.arange(n) * d, np.arange(n) * d, indexing="ij")
+        kap = kfun(X, Y, Z).ravel()
+        e = np.zeros((6, kap.size))
+        e[0] = kap * sfun(X, Y, Z).ravel()
+        atm = mk_atm(n, n, nz, L, L, z, kap, emis=e, i_bottom=0.5)
+        op = orc.OracleProblem(atm, mk_quad([mu0], [1.0], 4))
+        itop = orc.fs_sweep(op, rays=[0], want_j=False)["itop"][0, 0, :, :, 0]
+        st = math.sqrt(1 - mu0 * mu0)
+        errs_n = []
+        for (jy, ix) in ((0, 0), (n // 3, n // 2), (n - 1, 1)):
+            xt, yt = ix * d, jy * d
+
+            def rhs(zz, I, sgn=1.0):
+                s = (ztop - zz) / mu0
+                x = xt - sgn * s * st * math.cos(chi)
+                y = yt - sgn * s * st * math.sin(chi)
+                return [kfun(x, y, zz) * (sfun(x, y, zz) - I[0]) / mu0]
+            ref = solve_ivp(rhs, (0.0, ztop), [0.5], rtol=1e-11, atol=1e-13).y[0, -1]
+            errs_n.append(abs(itop[jy, ix] - ref))
+            if n == 64 and mirrored is None:
+                mir = solve_ivp(lambda zz, I: rhs(zz, I, -1.0), (0.0, ztop), [0.5], rtol=1e-11,
+                                atol=1e-13).y[0, -1]
+                mirrored = abs(itop[jy, ix] - mir)
+        errs.append(max(errs_n))
+    assert errs[-1] < 2e-3
+    assert errs[0] > errs[1] > errs[2]
+    assert mirrored > 20 * errs[-1]
+
+
+# --------------------------------------------------------------------------- P13 SEE
+def _hanle_matrix(b):
+    """<Q|b.J|Q'> for rank 2, rows/cols Q = -2..2, standard angular momentum matrices."""
+    Jz = np.diag(np.arange(-2, 3)).astype(complex)
+    Jp = np.zeros((5, 5), complex)
+    for q in range(-2, 2):
+        Jp[q + 3, q + 2] = math.sqrt(6 - q * (q + 1))
+    Jm = Jp.conj().T
+    Jx, Jy = (Jp + Jm) / 2, (Jp - Jm) / 2j
+    return b[0] * Jx + b[1] * Jy + b[2] * Jz
+
+
+def _see_case(n, seed, field=True):
+    rng = np.random.default_rng(seed)
+    jkq = np.zeros((10, n))
+    jkq[0] = rng.uniform(0.5, 1.5, n)
+    jkq[1:9] = rng.uniform(-0.05, 0.05, (8, n))
+    jkq[9] = rng.uniform(0, 0.99, n)
+    s_old = np.zeros((6, n))
+    s_old[0] = rng.uniform(0.5, 1.5, n)
+    v = rng.normal(size=(3, n))
+    atm = types.SimpleNamespace(eps_c=0.03, delta2=0.4, w2=0.9, planck=1.1,
+                                hanle=rng.uniform(0, 5, n) if field else None,
+                                bhat=(v / np.linalg.norm(v, axis=0)) if field else None,
+                                kappa=rng.uniform(0.1, 2, n))
+    return jkq, s_old, atm
+
+
+def test_see_general_field_equals_library_solve(orc):
+    n = 40
+    jkq, s_old, atm = _see_case(n, 51)
+    s_new, emis, rc = orc.see_update(jkq, s_old, atm)
+    e = atm.eps_c
+    for p in range(n):
+        J2 = np.zeros(5, complex)
+        J2[2] = jkq[4, p]
+        J2[3] = jkq[5, p] + 1j * jkq[6, p]
+        J2[4] = jkq[7, p] + 1j * jkq[8, p]
+        J2[1] = -np.conj(J2[3])
+        J2[0] = np.conj(J2[4])
+        A = (1 + atm.delta2 * (1 - e)) * np.eye(5) + 1j * (1 - e) * atm.hanle[p] * \
+            _hanle_matrix(atm.bhat[:, p])
+        x = np.linalg.solve(A, (1 - e) * atm.w2 * np.conj(J2))
+        # the solution keeps the symmetry S_-Q = (-1)^Q conj(S_Q)
+        np.testing.assert_allclose(x[1], -np.conj(x[3]), atol=1e-14)
+        np.testing.assert_allclose(x[0], np.conj(x[4]), atol=1e-14)
+        assert abs(x[2].imag) < 1e-14
+        np.testing.assert_allclose(s_new[1:, p], [x[2].real, x[3].real, x[3].imag, x[4].real,
+                                                  x[4].imag], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(emis, atm.kappa * s_new, rtol=1e-15)
+    ev = np.linalg.eigvalsh(_hanle_matrix(atm.bhat[:, 0]))
+    np.testing.assert_allclose(ev, [-2, -1, 0, 1, 2], atol=1e-12)
+
+
+def test_see_vertical_field_and_destruction_limits(orc):
+    n = 16
+    jkq, s_old, atm = _see_case(n, 52)
+    atm.bhat = np.zeros((3, n))
+    atm.bhat[2] = 1.0
+    s_new, _, _ = orc.see_update(jkq, s_old, atm)
+    e = atm.eps_c
+    for Q, (re, im) in ((1, (5, 6)), (2, (7, 8))):
+        J = jkq[re] + 1j * jkq[im]
+        S = (1 - e) * atm.w2 * np.conj(J) / (1 + atm.delta2 * (1 - e) + 1j * Q * (1 - e) * atm.hanle)
+        np.testing.assert_allclose(s_new[2 * Q] + 1j * s_new[2 * Q + 1], S, rtol=1e-13)
+    np.testing.assert_allclose(s_new[1], (1 - e) * atm.w2 * jkq[4] / (1 + atm.delta2 * (1 - e)),
+                               rtol=1e-13)
+    # stronger field -> smaller coherences
+    atm2 = types.SimpleNamespace(**vars(atm))
+    atm2.hanle = atm.hanle * 3 + 0.5
+    s2, _, _ = orc.see_update(jkq, s_old, atm2)
+    assert np.all(np.hypot(s2[2], s2[3]) < np.hypot(s_new[2], s_new[3]))
+    # complete collisional destruction
+    atm3 = types.SimpleNamespace(**vars(atm))
+    atm3.eps_c = 1.0
+    s3, _, _ = orc.see_update(jkq, s_old, atm3)
+    np.testing.assert_allclose(s3[0], atm.planck, rtol=1e-15)
+    np.testing.assert_array_equal(s3[1:], 0.0)
+
+
+def test_see_rotational_covariance(orc):
+    """Rotating radiation field and magnetic field by alpha about z rotates the atomic
+    multipoles: J^2_Q -> e^{iQa} J^2_Q implies S^2_Q -> e^{-iQa} S^2_Q."""
+    n = 12
+    jkq, s_old, atm = _see_case(n, 53)
+    s1, _, _ = orc.see_update(jkq, s_old, atm)
+    a = 0.83
+    jr = jkq.copy()
+    for Q, (re, im) in ((1, (2, 3)), (1, (5, 6)), (2, (7, 8))):
+        c = (jkq[re] + 1j * jkq[im]) * np.exp(1j * Q * a)
+        jr[re], jr[im] = c.real, c.imag
+    atm_r = types.SimpleNamespace(**vars(atm))
+    b = atm.bhat
+    atm_r.bhat = np.array([b[0] * math.cos(a) - b[1] * math.sin(a),
+                           b[0] * math.sin(a) + b[1] * math.cos(a), b[2]])
+    s2, _, _ = orc.see_update(jr, s_old, atm_r)
+    np.testing.assert_allclose(s2[:2], s1[:2], rtol=1e-12)
+    for Q, (re, im) in ((1, (2, 3)), (2, (4, 5))):
+        np.testing.assert_allclose(s2[re] + 1j * s2[im],
+                                   (s1[re] + 1j * s1[im]) * np.exp(-1j * Q * a), atol=1e-14)
+
+
+def test_jacobi_reaches_see_fixed_point(orc):
+    nx, ny, nz = 3, 3, 6
+    atm = _random_atm(nx, ny, nz, 61)
+    mu, w = gl_hemi(2)
+    q = mk_quad(mu, w, 4, phi=[1, 0.3, 0.05], wfreq=[0.5, 1, 0.5])
+    n = nx * ny * nz
+    rng = np.random.default_rng(62)
+    v = rng.normal(size=(3, n))
+    see = types.SimpleNamespace(eps_c=0.1, delta2=0.0, w2=1.0, planck=1.0,
+                                hanle=rng.uniform(0, 2, n), bhat=v / np.linalg.norm(v, axis=0),
+                                kappa=atm.kappa)
+    S = atm.emis / atm.kappa
+    rcs = []
+    for _ in range(60):
+        a2 = types.SimpleNamespace(**vars(atm))
+        a2.emis = atm.kappa * S
+        J = orc.fs_sweep(orc.OracleProblem(a2, q), want_itop=False)["jkq"]
+        S, _, rc = orc.see_update(J, S, see)
+        rcs.append(rc)
+    assert rcs[-1] < 1e-11
+    a2 = types.SimpleNamespace(**vars(atm))
+    a2.emis = atm.kappa * S
+    J = orc.fs_sweep(orc.OracleProblem(a2, q), want_itop=False)["jkq"]
+    np.testing.assert_allclose(S[0], (1 - see.eps_c) * J[0] + see.eps_c * see.planck, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------- P15 complex step
+def test_complex_step_matches_finite_differences(orc):
+    atm = _random_atm(4, 3, 5, 71)
+    mu, w = gl_hemi(2)
+    q = mk_quad(mu, w, 4, phi=[1, 0.3], wfreq=[1, 1])
+    op = orc.OracleProblem(atm, q)
+    rng = np.random.default_rng(72)
+    n = atm.kappa.size
+    dk = rng.normal(size=n) * atm.kappa
+    dp = rng.normal(size=(6, n)) * atm.kappa
+    de = rng.normal(size=(6, n)) * atm.kappa * 0.1
+    re, im = orc.fs_sweep_cs(op, dk, dp, de, h=1e-30)
+    h = 1e-6
+    up = orc.fs_sweep(op.with_fields(atm.kappa + h * dk, atm.propmat + h * dp, atm.emis + h * de),
+                      rays=np.arange(op.nrays // 2), want_j=False)["itop"]
+    dn = orc.fs_sweep(op.with_fields(atm.kappa - h * dk, atm.propmat - h * dp, atm.emis - h * de),
+                      rays=np.arange(op.nrays // 2), want_j=False)["itop"]
+    base = orc.fs_sweep(op, rays=np.arange(op.nrays // 2), want_j=False)["itop"]
+    np.testing.assert_allclose(re, base, rtol=1e-15)
+    fd = (up - dn) / (2 * h)
+    np.testing.assert_allclose(im / 1e-30, fd, rtol=1e-5, atol=1e-9 * np.abs(fd).max())
