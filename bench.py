@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the PORTA hot path on one MI355X.
+
+One step = one Jacobi iteration at the 256x256x128 precision instance
+(160 rays, 101 frequencies): the FP32 short-characteristics BESSER sweep of
+every ray and frequency with the fused FP64 J^K_Q / Lambda* integration,
+followed by the FP64 statistical-equilibrium update that rewrites the
+emissivities for the next iteration.  Inputs are seeded synthetic fields
+already resident in HBM.  Prints one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--ray-batch", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-fp64-rate", action="store_true",
+                    help="skip the extra FP64 sweep used for the FP32-vs-FP64 rate")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=16,
+                    help="(ray, frequency) pairs of the workload swept by the CPU oracle")
+    return ap.parse_args()
+
+
+def sweep_launch_bytes(cfg, nrb, elem):
+    """Algorithmic HBM bytes of one plane launch of the sweep kernel: the upwind
+    Stokes vector read and the new one written per update, three planes of the
+    13 transfer coefficients, and the FP64 read-modify-write of the 10 J values
+    of the previous plane."""
+    np_ = cfg.nx * cfg.ny
+    updates = nrb * cfg.nfreq * np_
+    return updates * 8 * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
+
+
+def cpu_baseline(cfg, atm, q, pairs):
+    from oracle import oracle as orc
+    import numpy as np
+    nthreads = max(1, min(16, os.cpu_count() or 1, pairs))
+    rays = np.linspace(0, cfg.nrays - 1, pairs).round().astype(np.int32)
+    freqs = np.linspace(0, cfg.nfreq - 1, pairs).round().astype(np.int32)
+    op = orc.OracleProblem(atm, q)
+    t0 = time.perf_counter()
+    done = 0
+    # groups of `nthreads` rays at one frequency each, so every thread sweeps one pair
+    for i in range(0, pairs, nthreads):
+        rs = rays[i:i + nthreads]
+        fs = freqs[i:i + 1]
+        orc.fs_sweep(op, rays=rs, freqs=fs, want_j=True, want_itop=True, nthreads=nthreads)
+        done += len(rs) * len(fs)
+    dt = time.perf_counter() - t0
+    upd = done * cfg.npoints
+    return {"value": upd / dt, "unit": "point*ray*freq updates/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{done} (ray, freq) pairs of the {cfg.nx}x{cfg.ny}x{cfg.nz} grid, FP64 "
+                      f"sweep + J ({upd:.3e} updates in {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sweep would "
+              "shard by frequency across GPUs with one FP64 all-reduce of J per iteration, "
+              "which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1307_4217_amd import inputs, porta
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    cfg = inputs.CONFIGS[args.config]
+    prec = porta.F32 if args.prec == "f32" else porta.F64
+    tdt = torch.float32 if prec == porta.F32 else torch.float64
+    elem = 4 if prec == porta.F32 else 8
+    log(f"config {cfg.name}: {inputs.describe(cfg)}, {cfg.updates:.4e} updates per sweep")
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    q = inputs.make_quadrature(cfg)
+    hg = porta.HostGrid.from_inputs(atm, q)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    kappa, prop, emis = t(atm.kappa, tdt), t(atm.propmat, tdt), t(atm.emis, tdt)
+    s_a, s_b = t(atm.source, torch.float64), torch.empty((6, cfg.npoints), dtype=torch.float64,
+                                                          device=dev)
+    hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
+    bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
+    opts = porta.options(ray_batch=args.ray_batch, block=args.block)
+    nrb = args.ray_batch if args.ray_batch > 0 else cfg.nmu * cfg.nchi
+    nbatches = -(-(cfg.nmu * cfg.nchi) // nrb)
+    ws = torch.empty(porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts), dtype=torch.uint8,
+                     device=dev)
+    ws_see = torch.empty(8 * ((cfg.npoints + 255) // 256) + 256, dtype=torch.uint8, device=dev)
+    jkq = torch.empty((10, cfg.npoints), dtype=torch.float64, device=dev)
+    itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=tdt, device=dev)
+    rc = torch.empty((), dtype=torch.float64, device=dev)
+    log(f"workspace {ws.numel() / 1e9:.2f} GB, i_top {itop.numel() * elem / 1e9:.2f} GB")
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    state = {"s_old": s_a, "s_new": s_b}
+
+    def step(times):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        porta.fs_sweep(hg, kappa, prop, emis, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
+                       i_top=itop, opts=opts, workspace=ws)
+        e1.record()
+        porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
+                         bhat, kappa=kappa, emis_out=emis, prec=prec, s_new=state["s_new"], rc=rc,
+                         workspace=ws_see)
+        e2.record()
+        state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
+        times.append((e0, e1, e2))
+
+    for w in range(args.warmup):
+        step([])
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(times)
+        torch.cuda.synchronize()
+        log(f"step {k + 1}/{args.steps}: sweep {times[-1][0].elapsed_time(times[-1][1]):.1f} ms, "
+            f"SEE {times[-1][1].elapsed_time(times[-1][2]):.2f} ms, R_c {rc.item():.3e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in times) / args.steps
+    see_ms = sum(b.elapsed_time(c) for _, b, c in times) / args.steps
+    step_ms = wall * 1e3 / args.steps
+    value = cfg.updates * args.steps / wall
+
+    launches = 2 * (cfg.nz - 1) * nbatches
+    lbytes, lupd = sweep_launch_bytes(cfg, nrb, elem)
+    launch_ms = sweep_ms / launches
+    achieved = lbytes / (launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_sweep_plane<{'float' if elem == 4 else 'double'}>",
+                "launch_ms": round(launch_ms, 4), "bytes_per_launch": lbytes,
+                "updates_per_launch": lupd}
+    extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
+             "sweep_updates_per_s": cfg.updates / (sweep_ms * 1e-3),
+             "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4)}
+    if not args.no_fp64_rate and prec == porta.F32:
+        del ws
+        torch.cuda.empty_cache()
+        k64, p64, e64 = t(atm.kappa, torch.float64), t(atm.propmat, torch.float64), t(
+            atm.emis, torch.float64)
+        ws64 = torch.empty(porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, opts),
+                           dtype=torch.uint8, device=dev)
+        it64 = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=torch.float64,
+                           device=dev)
+        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, jkq=jkq,
+                       i_top=it64, opts=opts, workspace=ws64)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, jkq=jkq,
+                       i_top=it64, opts=opts, workspace=ws64)
+        b.record()
+        torch.cuda.synchronize()
+        ms64 = a.elapsed_time(b)
+        extra["fp64_sweep_ms"] = round(ms64, 2)
+        extra["fp64_sweep_updates_per_s"] = cfg.updates / (ms64 * 1e-3)
+        extra["fp32_over_fp64_rate"] = round(ms64 / sweep_ms, 3)
+        log(f"FP64 sweep {ms64:.1f} ms")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample of the workload ...")
+        cpu = cpu_baseline(cfg, atm, q, args.cpu_pairs)
+        log(f"CPU oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+    out = {
+        "metric": "point*ray*freq updates/s (one Jacobi iteration: sweep + J + SEE)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == porta.F32 else "f64",
+        "data": "synthetic (seeded two-level atmosphere with the paper's box geometry)",
+        "config": {"workload": f"{cfg.nx}x{cfg.ny}x{cfg.nz} grid, {cfg.nrays} rays, "
+                               f"{cfg.nfreq} freqs, Jacobi step (sweep+J+SEE), adjoint not "
+                               "included", "updates_per_step": cfg.updates,
+                   "ray_batch": nrb, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * porta.h -- C ABI of the MI355X (gfx950) implementation of the PORTA hot
+ * path: the short-characteristics BESSER formal solver of the Stokes-vector
+ * transfer equation on a horizontally periodic 3-D grid, the angle and
+ * frequency integration of the radiation-field tensors J^K_Q, the Jacobi
+ * update of the two-level (J_l = 0 -> J_u = 1) statistical equilibrium with
+ * Hanle rotation, and the reverse-mode adjoint of the sweep.
+ *
+ * Reference: J. Stepan and J. Trujillo Bueno, "PORTA: A three-dimensional
+ * multilevel radiative transfer code for modeling the intensity and
+ * polarization of spectral lines with massively parallel computers",
+ * A&A (2013), arXiv:1307.4217.  Sections, equations and tables cited below
+ * are those of that paper.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Points are stored x fastest: p = (k * ny + j) * nx + i, N = nx*ny*nz.
+ *    x and y are periodic with spacing lx/nx and ly/ny; z is given per plane.
+ *  - Rays: r in [0, nmu*nchi) propagate upward (mu > 0), r in
+ *    [nmu*nchi, 2*nmu*nchi) downward; inside a hemisphere the inclination
+ *    index a is slow and the azimuth index m fast.  The ray direction is
+ *    (sin t cos chi, sin t sin chi, +-mu[a]) with chi = (m + 1/2) 2 pi / nchi
+ *    (trapezoid rule, Appendix A) and weight wmu[a] / (2 nchi); the weights
+ *    of all rays sum to one.
+ *  - Frequencies: every absorption and emission coefficient is its
+ *    line-centre value times phi[j] (complete redistribution, one line
+ *    profile).  The frequency weights of Eq. 1 are renormalized on the
+ *    discrete grid: W_j = wfreq[j] phi[j] / sum_j' wfreq[j'] phi[j'].
+ *  - Multipole components are stored in the order
+ *    (X00, X20, Re X21, Im X21, Re X22, Im X22); the Q < 0 components follow
+ *    from X^K_-Q = (-1)^Q conj(X^K_Q).
+ *  - J output [10][N] (FP64): J00, J10, Re J11, Im J11, J20, Re J21, Im J21,
+ *    Re J22, Im J22, and the Lambda* average
+ *    Lbar = sum_rays w sum_j W_j Lambda*_{ray,j} (Sect. 3.3, Eq. 14).
+ *  - Pointers named "host" are read during the call only.  Every other data
+ *    pointer is device memory owned by the caller; the library never keeps
+ *    or frees it.  Work is enqueued on `stream` (a hipStream_t, NULL for the
+ *    default stream) and returns before it completes; the caller
+ *    synchronizes before reading results.  The library keeps no state
+ *    between calls; calls on different streams must not share a workspace.
+ *  - Inputs are validated on the host before anything is enqueued; a
+ *    failure returns a negative porta_status, enqueues nothing and records a
+ *    message for porta_last_error() (thread-local).  HIP launch failures
+ *    return PORTA_EDEVICE.
+ *  - Physical preconditions that are not checked: kappa > 0 everywhere and
+ *    all inputs finite.  Violations give undefined numbers, never a fault.
+ */
+#ifndef PORTA_H
+#define PORTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PORTA_OK = 0,
+  PORTA_EINVAL = -1,       /* invalid argument (shape, pointer, range) */
+  PORTA_EUNSUPPORTED = -2, /* valid but not implemented combination */
+  PORTA_ENOMEM = -3,       /* workspace smaller than porta_workspace_size() */
+  PORTA_EDEVICE = -4       /* a HIP call failed */
+} porta_status;
+
+typedef enum { PORTA_F64 = 0, PORTA_F32 = 1 } porta_prec;   /* sweep precision */
+
+typedef enum {
+  PORTA_INTERP_BILINEAR = 0, /* 4-point bilinear at M and P (Sect. 3.1) */
+  PORTA_INTERP_BEZIER2D = 1  /* 9-point monotonic quadratic Bezier, x then y */
+} porta_interp;
+
+typedef enum {
+  PORTA_WS_SWEEP = 0,   /* porta_fs_sweep */
+  PORTA_WS_ADJOINT = 1, /* porta_fs_adjoint */
+  PORTA_WS_JKQ = 2,     /* porta_jkq_accumulate */
+  PORTA_WS_SEE = 3      /* porta_see_update */
+} porta_ws_kind;
+
+/* Spatial grid (Sect. 3.1, Appendix A). */
+typedef struct {
+  int32_t nx, ny, nz; /* nx, ny >= 1; nz >= 2 */
+  double lx, ly;      /* horizontal periods, > 0 */
+  const double* z;    /* host, nz plane heights, strictly increasing */
+} porta_grid;
+
+/* Angle and frequency quadrature (Eq. 1, Appendix A). */
+typedef struct {
+  int32_t nmu;         /* inclinations per hemisphere, 1..64 */
+  int32_t nchi;        /* azimuths over 2 pi, >= 1 */
+  int32_t nfreq;       /* frequencies, >= 1 */
+  const double* mu;    /* host [nmu], each in (0, 1] */
+  const double* wmu;   /* host [nmu], >= 0, summing to 1 within 1e-12 */
+  const double* phi;   /* host [nfreq], profile relative to line centre, > 0 */
+  const double* wfreq; /* host [nfreq], >= 0, with sum wfreq*phi > 0 */
+} porta_quad;
+
+/* Transfer coefficients at line centre (Sect. 3, Eq. rte). Element type is
+ * double for PORTA_F64 and float for PORTA_F32. */
+typedef struct {
+  const void* kappa;   /* device [N]: eta_I (> 0) */
+  const void* propmat; /* device [6][N]: eta_Q, eta_U, eta_V, rho_Q, rho_U, rho_V;
+                          K = [[eI,eQ,eU,eV],[eQ,eI,rV,-rU],[eU,-rV,eI,rQ],[eV,rU,-rQ,eI]] */
+  const void* emis;    /* device [6][N]: eps^K_Q multipoles (component order above);
+                          eps_i(Omega) = sum_KQ w^K T^K_Q(i, Omega) eps^K_Q, w^0 = 1 */
+  double i_bottom;     /* Stokes I entering at z[0] for upward rays (Q=U=V=0);
+                          downward rays enter at z[nz-1] with I = 0 */
+  double w2;           /* w^(2) of the line (1 for J_l = 0 -> J_u = 1) */
+} porta_fields;
+
+/* Two-level atom for the statistical equilibrium (Sect. 2, Eq. nonlte). */
+typedef struct {
+  double eps_c;        /* collisional destruction probability, in [0, 1] */
+  double delta2;       /* depolarizing collision rate delta^(2) (>= 0) */
+  double w2;           /* w^(2) of the line */
+  double planck;       /* Planck function B */
+  const double* hanle; /* device [N] Hanle parameter H_u >= 0, or NULL for no field */
+  const double* bhat;  /* device [3][N] unit field direction; NULL for b = z */
+} porta_atom;
+
+/* Optional tuning; pass NULL for defaults. */
+typedef struct {
+  int32_t ray_batch;        /* rays swept together (0: a whole hemisphere) */
+  int32_t block;            /* threads per block of the sweep kernel (0: 256) */
+} porta_options;
+
+/* Bytes of device workspace needed by one call of the given kind (0 on invalid
+ * arguments).  `prec` selects the sweep precision; `checkpoint_stride` is
+ * used by PORTA_WS_ADJOINT only. */
+size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int prec,
+                            int kind, int checkpoint_stride, const porta_options* opts);
+
+/*
+ * Formal solution for every ray and frequency (Sect. 3; Eqs. fsint, fsbez,
+ * kappa; BESSER control points of Sect. 3.2; Table 1 for small tau_MO),
+ * sweeping the planes of each ray in upwind order, fused with the angle and
+ * frequency integration of Eq. 1 and of Lambda* (Eq. 14).
+ *   prec, interp  : porta_prec, porta_interp
+ *   jkq           : device [10][N] FP64, or NULL; overwritten (accumulate = 0)
+ *                   or added to (accumulate = 1)
+ *   i_top         : device [nmu*nchi][nfreq][ny][nx][4] (sweep precision),
+ *                   Stokes vectors of the upward rays at z[nz-1], or NULL
+ *   workspace     : device, >= porta_workspace_size(..., PORTA_WS_SWEEP, ...)
+ */
+int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
+                   int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
+                   void* i_top, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Eq. 1 (and the Lambda* average) from a stored block of Stokes vectors:
+ *   stokes      : device [nray][nf][N][4] (sweep precision) for rays
+ *                 ray0..ray0+nray-1 and frequencies f0..f0+nf-1
+ *   lambda_star : device [nray][nf][N] (sweep precision) or NULL
+ *   jkq         : device [10][N] FP64, added to
+ */
+int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray0, int nray,
+                         int f0, int nf, const void* stokes, const void* lambda_star, int prec,
+                         double* jkq, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * One Jacobi update of the two-level statistical equilibrium at every point
+ * (Sect. 2 Eq. nonlte; Jacobi iteration of Sect. 5):
+ *   S00 <- [(1-eps)(J00 - Lbar S00_old) + eps B] / [1 - (1-eps) Lbar]
+ *   [1 + delta (1-eps)] S2_Q + i (1-eps) H_u sum_Q' <Q|b.J|Q'> S2_Q'
+ *        = (1-eps) w2 conj(J2_Q)                        (Q = -2..2)
+ *   s_old, s_new : device [6][N] FP64 source-function multipoles S^K_Q
+ *   kappa        : device [N] (sweep precision), used for emis_out only
+ *   emis_out     : device [6][N] (sweep precision) = kappa * S_new, or NULL
+ *   rc_out       : device FP64 scalar, max_p |S00_new - S00_old| / |S00_new|,
+ *                  or NULL (the convergence measure R_c of Sect. 5.3)
+ */
+int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
+                     const double* s_old, double* s_new, const void* kappa, void* emis_out,
+                     int prec, double* rc_out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Reverse-mode derivative of a scalar loss L(i_top) through the sweep of the
+ * upward rays: given dL/d i_top (same layout and precision as i_top), adds
+ * dL/dkappa, dL/dpropmat and dL/demis (each in the layout of its field, in
+ * the sweep precision) to g_kappa [N], g_propmat [6][N], g_emis [6][N].
+ * The intensity field is recomputed from plane checkpoints every
+ * `checkpoint_stride` planes (>= 1) instead of being stored.
+ */
+int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
+                     int prec, int interp, const porta_options* opts, const void* dl_ditop,
+                     int checkpoint_stride, void* g_kappa, void* g_propmat, void* g_emis,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Text of a porta_status. */
+const char* porta_strerror(int status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* porta_last_error(void);
+
+/* Library version string. */
+const char* porta_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PORTA_H */

@@ -1,0 +1,460 @@
+// porta_abi.hip -- host side of the C ABI declared in include/porta.h:
+// argument validation, workspace layout and the launch sequence of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/porta.h"
+#include "porta_kernels.hpp"
+
+namespace {
+
+using namespace porta;
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PORTA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return PORTA_OK;
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+int validate_grid(const porta_grid* g) {
+  if (!g) return fail(PORTA_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 2)
+    return fail(PORTA_EINVAL, "grid sizes must be nx >= 1, ny >= 1, nz >= 2 (got %d %d %d)",
+                g->nx, g->ny, g->nz);
+  const double n = (double)g->nx * g->ny * g->nz;
+  if (n * 10.0 >= 9.0e18 || (double)g->nx * g->ny >= 2147483647.0)
+    return fail(PORTA_EINVAL, "grid too large");
+  if (!(g->lx > 0.0) || !(g->ly > 0.0) || !std::isfinite(g->lx) || !std::isfinite(g->ly))
+    return fail(PORTA_EINVAL, "horizontal periods must be positive and finite");
+  if (!g->z) return fail(PORTA_EINVAL, "grid z is NULL");
+  for (int k = 0; k < g->nz; ++k)
+    if (!std::isfinite(g->z[k])) return fail(PORTA_EINVAL, "z[%d] is not finite", k);
+  for (int k = 1; k < g->nz; ++k)
+    if (!(g->z[k] > g->z[k - 1])) return fail(PORTA_EINVAL, "z must increase strictly (z[%d])", k);
+  return PORTA_OK;
+}
+
+int validate_quad(const porta_quad* q) {
+  if (!q) return fail(PORTA_EINVAL, "quadrature is NULL");
+  if (q->nmu < 1 || q->nmu > kMaxMu) return fail(PORTA_EINVAL, "nmu must be in 1..%d", kMaxMu);
+  if (q->nchi < 1 || q->nchi > 4096) return fail(PORTA_EINVAL, "nchi must be in 1..4096");
+  if (q->nfreq < 1 || q->nfreq > 65536) return fail(PORTA_EINVAL, "nfreq must be in 1..65536");
+  if (!q->mu || !q->wmu || !q->phi || !q->wfreq)
+    return fail(PORTA_EINVAL, "quadrature arrays must not be NULL");
+  double sw = 0.0;
+  for (int a = 0; a < q->nmu; ++a) {
+    if (!(q->mu[a] > 0.0 && q->mu[a] <= 1.0))
+      return fail(PORTA_EINVAL, "mu[%d] = %g is not in (0, 1]", a, q->mu[a]);
+    if (!(q->wmu[a] >= 0.0) || !std::isfinite(q->wmu[a]))
+      return fail(PORTA_EINVAL, "wmu[%d] must be finite and >= 0", a);
+    sw += q->wmu[a];
+  }
+  if (std::fabs(sw - 1.0) > 1e-12) return fail(PORTA_EINVAL, "wmu must sum to 1 (sum = %.17g)", sw);
+  double sf = 0.0;
+  for (int j = 0; j < q->nfreq; ++j) {
+    if (!(q->phi[j] > 0.0) || !std::isfinite(q->phi[j]))
+      return fail(PORTA_EINVAL, "phi[%d] must be finite and > 0", j);
+    if (!(q->wfreq[j] >= 0.0) || !std::isfinite(q->wfreq[j]))
+      return fail(PORTA_EINVAL, "wfreq[%d] must be finite and >= 0", j);
+    sf += q->wfreq[j] * q->phi[j];
+  }
+  if (!(sf > 0.0)) return fail(PORTA_EINVAL, "sum of wfreq * phi must be > 0");
+  return PORTA_OK;
+}
+
+int validate_prec(int prec) {
+  if (prec != PORTA_F64 && prec != PORTA_F32) return fail(PORTA_EINVAL, "unknown precision %d", prec);
+  return PORTA_OK;
+}
+
+int validate_interp(int interp) {
+  if (interp != PORTA_INTERP_BILINEAR && interp != PORTA_INTERP_BEZIER2D)
+    return fail(PORTA_EINVAL, "unknown interpolation mode %d", interp);
+  return PORTA_OK;
+}
+
+size_t elem(int prec) { return prec == PORTA_F32 ? sizeof(float) : sizeof(double); }
+
+int ray_batch(const porta_quad* q, const porta_options* o) {
+  const int nh = q->nmu * q->nchi;
+  int rb = (o && o->ray_batch > 0) ? o->ray_batch : nh;
+  return std::min(rb, nh);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (every region 256-byte aligned)
+// ---------------------------------------------------------------------------
+struct Layout {
+  size_t stage;     // doubles: mu[kMaxMu], wmu[kMaxMu], phi[nfreq], wfreq[nfreq]
+  size_t rays;      // RayConsts[nrays]
+  size_t phiT;      // T[nfreq]
+  size_t wn;        // double[nfreq]
+  size_t end_tables;
+  size_t stateA, stateB;   // sweep plane states
+  size_t jpart;
+  size_t adj;              // adjoint region (see porta_adjoint.hpp)
+  size_t total;
+};
+
+Layout tables_layout(const porta_quad* q, int prec) {
+  Layout L{};
+  size_t off = 0;
+  L.stage = off;
+  off = align_up(off + sizeof(double) * (2 * kMaxMu + 2 * (size_t)q->nfreq));
+  L.rays = off;
+  off = align_up(off + sizeof(RayConsts) * 2 * (size_t)q->nmu * q->nchi);
+  L.phiT = off;
+  off = align_up(off + elem(prec) * q->nfreq);
+  L.wn = off;
+  off = align_up(off + sizeof(double) * q->nfreq);
+  L.end_tables = off;
+  L.total = off;
+  return L;
+}
+
+Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const porta_options* o) {
+  Layout L = tables_layout(q, prec);
+  const size_t np = (size_t)g->nx * g->ny;
+  const size_t nrb = (size_t)ray_batch(q, o);
+  const size_t state = nrb * q->nfreq * np * 4 * elem(prec);
+  size_t off = L.end_tables;
+  L.stateA = off;
+  off = align_up(off + state);
+  L.stateB = off;
+  off = align_up(off + state);
+  L.jpart = off;
+  off = align_up(off + 2 * nrb * 5 * np * sizeof(double));   // double-buffered partial sums
+  L.total = off;
+  return L;
+}
+
+// Adjoint workspace (filled in with the adjoint kernels).
+Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int stride,
+                      const porta_options* o) {
+  (void)stride;
+  return sweep_layout(g, q, prec, o);
+}
+
+// Upload host doubles through kernel arguments (ordered on the stream).
+int upload(double* dst, const double* src, size_t n, hipStream_t st) {
+  for (size_t o = 0; o < n; o += kUploadChunk) {
+    UploadChunk c;
+    c.n = (int)std::min<size_t>(kUploadChunk, n - o);
+    std::memcpy(c.v, src + o, sizeof(double) * c.n);
+    c.dst = dst + o;
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, st, c);
+  }
+  return check_launch("upload");
+}
+
+template <class T>
+int prepare_tables(char* ws, const Layout& L, const porta_quad* q, double w2, hipStream_t st) {
+  double* stage = reinterpret_cast<double*>(ws + L.stage);
+  int rc;
+  if ((rc = upload(stage, q->mu, q->nmu, st))) return rc;
+  if ((rc = upload(stage + kMaxMu, q->wmu, q->nmu, st))) return rc;
+  if ((rc = upload(stage + 2 * kMaxMu, q->phi, q->nfreq, st))) return rc;
+  if ((rc = upload(stage + 2 * kMaxMu + q->nfreq, q->wfreq, q->nfreq, st))) return rc;
+  hipLaunchKernelGGL(k_prepare<T>, dim3(1), dim3(256), 0, st, stage, stage + kMaxMu, q->nmu,
+                     q->nchi, w2, stage + 2 * kMaxMu, stage + 2 * kMaxMu + q->nfreq, q->nfreq,
+                     reinterpret_cast<RayConsts*>(ws + L.rays), reinterpret_cast<T*>(ws + L.phiT),
+                     reinterpret_cast<double*>(ws + L.wn));
+  return check_launch("prepare");
+}
+
+int fill(double* p, size_t n, double v, hipStream_t st) {
+  if (n == 0) return PORTA_OK;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return check_launch("fill");
+}
+
+// ---------------------------------------------------------------------------
+// Forward sweep
+// ---------------------------------------------------------------------------
+template <class T>
+int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
+               const porta_options* o, double* jkq, int accumulate, T* itop, char* ws,
+               const Layout& L, hipStream_t st) {
+  int rc;
+  if ((rc = prepare_tables<T>(ws, L, q, f->w2, st))) return rc;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int np = nx * ny;
+  const size_t N = (size_t)np * nz;
+  if (jkq && !accumulate)
+    if ((rc = fill(jkq, 10 * N, 0.0, st))) return rc;
+  const int nh = q->nmu * q->nchi;
+  const int nrb_max = ray_batch(q, o);
+  const int block = (o && o->block > 0) ? o->block : 256;
+  if (block % 64 != 0 || block > 256) return fail(PORTA_EINVAL, "block must be 64, 128, 192 or 256");
+  const RayConsts* rays = reinterpret_cast<const RayConsts*>(ws + L.rays);
+  const T* phiT = reinterpret_cast<const T*>(ws + L.phiT);
+  const double* wn = reinterpret_cast<const double*>(ws + L.wn);
+  T* state[2] = {reinterpret_cast<T*>(ws + L.stateA), reinterpret_cast<T*>(ws + L.stateB)};
+  double* jpart[2] = {nullptr, nullptr};
+  if (jkq) {
+    jpart[0] = reinterpret_cast<double*>(ws + L.jpart);
+    jpart[1] = jpart[0] + (size_t)nrb_max * 5 * np;
+  }
+  const dim3 rblk(256), rgrid((np + 255) / 256);
+
+  for (int hemi = 0; hemi < 2; ++hemi) {
+    const bool up = (hemi == 0);
+    const int kb = up ? 0 : nz - 1, s = up ? 1 : -1;
+    const T ibound = up ? (T)f->i_bottom : T(0);
+    for (int r0 = 0; r0 < nh; r0 += nrb_max) {
+      const int nrb = std::min(nrb_max, nh - r0);
+      const int ray0 = hemi * nh + r0;
+      const T* prev = nullptr;
+      for (int step = 1; step < nz; ++step) {
+        const int k = kb + s * step;
+        PlaneArgs<T> a;
+        a.kappa = static_cast<const T*>(f->kappa);
+        a.prop = static_cast<const T*>(f->propmat);
+        a.emis = static_cast<const T*>(f->emis);
+        a.rays = rays;
+        a.phi = phiT;
+        a.wn = wn;
+        a.iprev = prev;
+        const bool last = (step == nz - 1);
+        a.inext = (last && up && itop) ? itop + (size_t)r0 * q->nfreq * np * 4 : state[step & 1];
+        // plane k writes partial sums into jpart[step & 1] while the first ray row of
+        // blocks adds those of plane k - s (or the boundary plane) to J
+        a.jpart = jpart[step & 1];
+        a.jkq = jkq;
+        a.jpart_prev = (step == 1) ? nullptr : jpart[(step - 1) & 1];
+        a.prev_off = (size_t)(k - s) * np;
+        a.N = N;
+        a.nx = nx;
+        a.ny = ny;
+        a.np = np;
+        a.nfreq = q->nfreq;
+        a.kO = k;
+        a.kM = k - s;
+        a.kP = last ? -1 : k + s;
+        a.dzM = std::fabs(g->z[k] - g->z[k - s]);
+        a.dzP = last ? 0.0 : std::fabs(g->z[k + s] - g->z[k]);
+        a.inv_dx = nx / g->lx;
+        a.inv_dy = ny / g->ly;
+        a.ray0 = ray0;
+        a.ibound = ibound;
+        hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
+                           0, st, a);
+        if ((rc = check_launch("sweep_plane"))) return rc;
+        prev = a.inext;
+      }
+      if (jkq) {
+        // the last plane of the batch
+        const int klast = kb + s * (nz - 1);
+        hipLaunchKernelGGL(k_jreduce, rgrid, rblk, 0, st, jkq, (const double*)jpart[(nz - 1) & 1],
+                           rays, ray0, nrb, np, N, (size_t)klast * np, 0, 0.0);
+        if ((rc = check_launch("jreduce"))) return rc;
+      }
+    }
+  }
+  return PORTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* porta_version(void) { return "porta-mi355x 0.1.0 (gfx950)"; }
+
+const char* porta_last_error(void) { return g_last_error.c_str(); }
+
+const char* porta_strerror(int status) {
+  switch (status) {
+    case PORTA_OK: return "success";
+    case PORTA_EINVAL: return "invalid argument";
+    case PORTA_EUNSUPPORTED: return "unsupported combination of arguments";
+    case PORTA_ENOMEM: return "workspace too small";
+    case PORTA_EDEVICE: return "HIP device error";
+    default: return "unknown status";
+  }
+}
+
+size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int prec, int kind,
+                            int checkpoint_stride, const porta_options* opts) {
+  if (validate_prec(prec)) return 0;
+  switch (kind) {
+    case PORTA_WS_SWEEP:
+      if (validate_grid(grid) || validate_quad(quad)) return 0;
+      return sweep_layout(grid, quad, prec, opts).total;
+    case PORTA_WS_ADJOINT:
+      if (validate_grid(grid) || validate_quad(quad) || checkpoint_stride < 1) return 0;
+      return adjoint_layout(grid, quad, prec, checkpoint_stride, opts).total;
+    case PORTA_WS_JKQ:
+      if (validate_quad(quad)) return 0;
+      return tables_layout(quad, prec).total;
+    case PORTA_WS_SEE: {
+      if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return 0;
+      const size_t n = (size_t)grid->nx * grid->ny * grid->nz;
+      return align_up(sizeof(double) * ((n + 255) / 256));
+    }
+    default:
+      fail(PORTA_EINVAL, "unknown workspace kind %d", kind);
+      return 0;
+  }
+}
+
+int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
+                   int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
+                   void* i_top, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
+      (rc = validate_interp(interp)))
+    return rc;
+  if (!fields || !fields->kappa || !fields->propmat || !fields->emis)
+    return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
+  if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
+    return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
+  if (opts && (opts->ray_batch < 0 || opts->block < 0))
+    return fail(PORTA_EINVAL, "options must be >= 0");
+  if (interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the sweep");
+  if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
+  const Layout L = sweep_layout(grid, quad, prec, opts);
+  if (ws_bytes < L.total)
+    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                L.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  if (prec == PORTA_F64)
+    return sweep_impl<double>(grid, quad, fields, opts, jkq, accumulate,
+                              static_cast<double*>(i_top), ws, L, st);
+  return sweep_impl<float>(grid, quad, fields, opts, jkq, accumulate, static_cast<float*>(i_top),
+                           ws, L, st);
+}
+
+int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray0, int nray,
+                         int f0, int nf, const void* stokes, const void* lambda_star, int prec,
+                         double* jkq, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)))
+    return rc;
+  const int nrays = 2 * quad->nmu * quad->nchi;
+  if (ray0 < 0 || nray < 0 || ray0 + nray > nrays)
+    return fail(PORTA_EINVAL, "ray range [%d, %d) outside [0, %d)", ray0, ray0 + nray, nrays);
+  if (f0 < 0 || nf < 0 || f0 + nf > quad->nfreq)
+    return fail(PORTA_EINVAL, "frequency range [%d, %d) outside [0, %d)", f0, f0 + nf,
+                quad->nfreq);
+  if (!stokes || !jkq) return fail(PORTA_EINVAL, "stokes and jkq must not be NULL");
+  if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
+  const Layout L = tables_layout(quad, prec);
+  if (ws_bytes < L.total)
+    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                L.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const size_t N = (size_t)grid->nx * grid->ny * grid->nz;
+  if (nray == 0 || nf == 0) return PORTA_OK;
+  const dim3 grd((unsigned)((N + 255) / 256)), blk(256);
+  if (prec == PORTA_F64) {
+    if ((rc = prepare_tables<double>(ws, L, quad, 1.0, st))) return rc;
+    hipLaunchKernelGGL(k_jkq_accumulate<double>, grd, blk, 0, st, jkq,
+                       static_cast<const double*>(stokes), static_cast<const double*>(lambda_star),
+                       reinterpret_cast<const RayConsts*>(ws + L.rays),
+                       reinterpret_cast<const double*>(ws + L.wn), ray0, nray, f0, nf, N);
+  } else {
+    if ((rc = prepare_tables<float>(ws, L, quad, 1.0, st))) return rc;
+    hipLaunchKernelGGL(k_jkq_accumulate<float>, grd, blk, 0, st, jkq,
+                       static_cast<const float*>(stokes), static_cast<const float*>(lambda_star),
+                       reinterpret_cast<const RayConsts*>(ws + L.rays),
+                       reinterpret_cast<const double*>(ws + L.wn), ray0, nray, f0, nf, N);
+  }
+  return check_launch("jkq_accumulate");
+}
+
+int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
+                     const double* s_old, double* s_new, const void* kappa, void* emis_out,
+                     int prec, double* rc_out, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = validate_prec(prec))) return rc;
+  if (npoints < 1 || npoints > (int64_t)1 << 40) return fail(PORTA_EINVAL, "npoints out of range");
+  if (!jkq || !atom || !s_old || !s_new) return fail(PORTA_EINVAL, "NULL argument");
+  if (emis_out && !kappa) return fail(PORTA_EINVAL, "emis_out needs kappa");
+  if (!(atom->eps_c >= 0.0 && atom->eps_c <= 1.0))
+    return fail(PORTA_EINVAL, "eps_c must be in [0, 1]");
+  if (!(atom->delta2 >= 0.0) || !std::isfinite(atom->delta2) || !std::isfinite(atom->w2) ||
+      !std::isfinite(atom->planck))
+    return fail(PORTA_EINVAL, "atom parameters must be finite (delta2 >= 0)");
+  const size_t N = (size_t)npoints;
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  double* blockmax = nullptr;
+  if (rc_out) {
+    if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
+    if (ws_bytes < sizeof(double) * nb)
+      return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
+                  ws_bytes, sizeof(double) * nb);
+    blockmax = static_cast<double*>(workspace);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == PORTA_F64) {
+    SeeArgs<double> a{jkq, s_old, s_new, atom->hanle, atom->bhat,
+                      static_cast<const double*>(kappa), static_cast<double*>(emis_out),
+                      blockmax, N, atom->eps_c, atom->delta2, atom->w2, atom->planck};
+    hipLaunchKernelGGL(k_see<double>, dim3(nb), dim3(256), 0, st, a);
+  } else {
+    SeeArgs<float> a{jkq, s_old, s_new, atom->hanle, atom->bhat,
+                     static_cast<const float*>(kappa), static_cast<float*>(emis_out),
+                     blockmax, N, atom->eps_c, atom->delta2, atom->w2, atom->planck};
+    hipLaunchKernelGGL(k_see<float>, dim3(nb), dim3(256), 0, st, a);
+  }
+  if ((rc = check_launch("see"))) return rc;
+  if (rc_out) {
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, blockmax, (int)nb, rc_out);
+    if ((rc = check_launch("see_rc"))) return rc;
+  }
+  return PORTA_OK;
+}
+
+int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
+                     int prec, int interp, const porta_options* opts, const void* dl_ditop,
+                     int checkpoint_stride, void* g_kappa, void* g_propmat, void* g_emis,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
+      (rc = validate_interp(interp)))
+    return rc;
+  if (!fields || !fields->kappa || !fields->propmat || !fields->emis)
+    return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
+  if (!dl_ditop || !g_kappa || !g_propmat || !g_emis)
+    return fail(PORTA_EINVAL, "seed and gradient arrays must not be NULL");
+  if (checkpoint_stride < 1) return fail(PORTA_EINVAL, "checkpoint_stride must be >= 1");
+  if (interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
+  if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
+  const Layout L = adjoint_layout(grid, quad, prec, checkpoint_stride, opts);
+  if (ws_bytes < L.total)
+    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                L.total);
+  return fail(PORTA_EUNSUPPORTED, "adjoint not available yet");
+  (void)stream;
+}
+
+}  // extern "C"

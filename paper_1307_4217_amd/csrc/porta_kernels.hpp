@@ -1,0 +1,456 @@
+// porta_kernels.hpp -- HIP kernels of the forward path for gfx950: table
+// preparation, the plane step of the short-characteristics sweep, the
+// ray/frequency reduction of J^K_Q, the stand-alone J accumulation and the
+// statistical-equilibrium update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "porta_math.hpp"
+
+namespace porta {
+
+constexpr int kMaxMu = 64;
+constexpr int kUploadChunk = 240;   // doubles per upload launch (kernel-argument copy)
+
+// ---------------------------------------------------------------------------
+// Small host -> device uploads travel inside the kernel arguments, which the
+// runtime copies at launch time; the host buffer can be reused at once and
+// the copy is ordered on the caller's stream.
+// ---------------------------------------------------------------------------
+struct UploadChunk {
+  double v[kUploadChunk];
+  double* dst;
+  int n;
+};
+
+__global__ void k_upload(const UploadChunk c) {
+  const int t = threadIdx.x;
+  if (t < c.n) c.dst[t] = c.v[t];
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Ray constants (direction, weight, emission and J projection tables) and the
+// normalized frequency weights, from the uploaded quadrature.
+template <class T>
+__global__ void k_prepare(const double* __restrict__ mu, const double* __restrict__ wmu, int nmu,
+                          int nchi, double w2, const double* __restrict__ phi,
+                          const double* __restrict__ wfreq, int nfreq,
+                          RayConsts* __restrict__ rays, T* __restrict__ phiT,
+                          double* __restrict__ wn) {
+  __shared__ double norm;
+  const int nh = nmu * nchi;
+  for (int r = threadIdx.x; r < 2 * nh; r += blockDim.x) {
+    const int a = (r % nh) / nchi, m = r % nchi;
+    const double m0 = mu[a];
+    const double chi = (m + 0.5) * (2.0 * M_PI / nchi);
+    ray_consts(r < nh ? m0 : -m0, chi, 0.5 * wmu[a] / nchi, w2, rays[r]);
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int j = 0; j < nfreq; ++j) s += wfreq[j] * phi[j];
+    norm = s;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nfreq; j += blockDim.x) {
+    wn[j] = wfreq[j] * phi[j] / norm;
+    phiT[j] = (T)phi[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector loads and stores of one Stokes vector.
+// ---------------------------------------------------------------------------
+__device__ inline void load4(const float* p, float v[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ inline void load4(const double* p, double v[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ inline void store4(float* p, const float v[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void store4(double* p, const double v[4]) {
+  *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+__device__ inline int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Bilinear stencil on a periodic plane for a point displaced by (u, v) cells
+// from node (i, j).  For one ray and one pair of planes the displacement is
+// the same at every node, so every thread of a plane sees the same weights.
+struct Stencil {
+  int i00, i10, i01, i11;
+  double w00, w10, w01, w11;
+};
+
+__device__ inline Stencil make_stencil(int i, int j, int nx, int ny, double u, double v) {
+  // reduce the displacement to one period first so the integer shift stays in range
+  u -= nx * floor(u / nx);
+  v -= ny * floor(v / ny);
+  const double fu = floor(u), fv = floor(v);
+  const double tx = u - fu, ty = v - fv;
+  const int i0 = wrapi(i + (int)fu, nx), i1 = (i0 + 1 == nx) ? 0 : i0 + 1;
+  const int j0 = wrapi(j + (int)fv, ny), j1 = (j0 + 1 == ny) ? 0 : j0 + 1;
+  Stencil s;
+  s.i00 = j0 * nx + i0;
+  s.i10 = j0 * nx + i1;
+  s.i01 = j1 * nx + i0;
+  s.i11 = j1 * nx + i1;
+  s.w00 = (1.0 - tx) * (1.0 - ty);
+  s.w10 = tx * (1.0 - ty);
+  s.w01 = (1.0 - tx) * ty;
+  s.w11 = tx * ty;
+  return s;
+}
+
+template <class T>
+__device__ inline double bil(const T* __restrict__ f, const Stencil& s) {
+  return s.w00 * (double)f[s.i00] + s.w10 * (double)f[s.i10] + s.w01 * (double)f[s.i01] +
+         s.w11 * (double)f[s.i11];
+}
+
+// ---------------------------------------------------------------------------
+// Add the frequency-integrated Stokes vectors of a batch of rays on one plane
+// to J^K_Q (Eq. 1) and Lbar, in a fixed ray order (no atomics).  On the
+// boundary plane the Stokes vector is (ibound, 0, 0, 0) at every frequency.
+// ---------------------------------------------------------------------------
+__device__ inline void jreduce_point(double* __restrict__ jkq, const double* __restrict__ jpart,
+                                     const RayConsts* __restrict__ rays, int ray0, int nrb,
+                                     int np, size_t N, size_t plane_off, int p, int boundary,
+                                     double ibound) {
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int rb = 0; rb < nrb; ++rb) {
+    const RayConsts& rc = rays[ray0 + rb];
+    double ib[4], lam;
+    if (boundary) {
+      ib[0] = ibound;
+      ib[1] = ib[2] = ib[3] = 0.0;
+      lam = 0.0;
+    } else {
+      const double* jp = jpart + (size_t)rb * 5 * np + p;
+      ib[0] = jp[0];
+      ib[1] = jp[(size_t)np];
+      ib[2] = jp[2 * (size_t)np];
+      ib[3] = jp[3 * (size_t)np];
+      lam = jp[4 * (size_t)np];
+    }
+    const double w = rc.weight;
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      acc[c] += w * (rc.proj[c][0] * ib[0] + rc.proj[c][1] * ib[1] + rc.proj[c][2] * ib[2] +
+                     rc.proj[c][3] * ib[3]);
+    acc[9] += w * lam;
+  }
+#pragma unroll
+  for (int c = 0; c < 10; ++c) jkq[c * N + plane_off + p] += acc[c];
+}
+
+__global__ void __launch_bounds__(256)
+    k_jreduce(double* __restrict__ jkq, const double* __restrict__ jpart,
+              const RayConsts* __restrict__ rays, int ray0, int nrb, int np, size_t N,
+              size_t plane_off, int boundary, double ibound) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  jreduce_point(jkq, jpart, rays, ray0, nrb, np, N, plane_off, p, boundary, ibound);
+}
+
+// ---------------------------------------------------------------------------
+// One plane of the sweep for a batch of rays of one hemisphere and every
+// frequency.  Thread = (node of plane k, ray of the batch); the frequency
+// loop runs inside the thread so that the frequency-independent work
+// (interpolation of the coefficients at M and P, S and K' at M and O, the
+// BESSER control points) is done once per node and ray.
+//
+// Plane state layout: [ray in batch][frequency][node][Stokes].
+// ---------------------------------------------------------------------------
+template <class T>
+struct PlaneArgs {
+  const T* kappa;
+  const T* prop;
+  const T* emis;
+  const RayConsts* rays;
+  const T* phi;
+  const double* wn;
+  const T* iprev;    // upwind plane state, or nullptr when the upwind plane is the boundary
+  T* inext;          // state of plane k
+  double* jpart;     // [ray in batch][5][node]: sum_j W_j I_i and sum_j W_j Lambda*, or nullptr
+  // J of the previous plane (reduced by the blocks of the first ray of the batch)
+  double* jkq;               // [10][N] or nullptr
+  const double* jpart_prev;  // partial sums of the previous plane, or nullptr (boundary plane)
+  size_t prev_off;           // offset of the previous plane in jkq
+  size_t N;
+  int nx, ny, np, nfreq;
+  int kO, kM, kP;    // plane of O, upwind plane, downwind plane (-1: none)
+  double dzM, dzP;   // |z_kO - z_kM|, |z_kP - z_kO|
+  double inv_dx, inv_dy;
+  int ray0;
+  T ibound;          // Stokes I on the boundary plane of this hemisphere
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const int rb = blockIdx.y;
+  if (rb == 0 && a.jkq)
+    jreduce_point(a.jkq, a.jpart_prev, a.rays, a.ray0, gridDim.y, a.np, a.N, a.prev_off, p,
+                  a.jpart_prev == nullptr, (double)a.ibound);
+  const RayConsts& rc = a.rays[a.ray0 + rb];
+  const int i = p % a.nx, j = p / a.nx;
+  const double inv_mu = 1.0 / fabs(rc.mu);
+  const size_t N = a.N;
+
+  // upwind point M on plane kM (Sect. 3.1)
+  const double dsM = a.dzM * inv_mu;
+  const Stencil sM = make_stencil(i, j, a.nx, a.ny, -dsM * rc.sx * a.inv_dx,
+                                  -dsM * rc.sy * a.inv_dy);
+  const size_t bM = (size_t)a.kM * a.np, bO = (size_t)a.kO * a.np + p;
+  const double kapM = bil(a.kappa + bM, sM);
+  const double kapO = (double)a.kappa[bO];
+  double epsM[6], epsO[6], etaM[6], etaO[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    epsM[c] = bil(a.emis + c * N + bM, sM);
+    etaM[c] = bil(a.prop + c * N + bM, sM);
+    epsO[c] = (double)a.emis[c * N + bO];
+    etaO[c] = (double)a.prop[c * N + bO];
+  }
+  double SM[4], SO[4], cM[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double em = 0.0, eo = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      em += rc.emis[s][c] * epsM[c];
+      eo += rc.emis[s][c] * epsO[c];
+    }
+    SM[s] = em / kapM;
+    SO[s] = eo / kapO;
+  }
+  const double tau0M = 0.5 * (kapM + kapO) * dsM;   // line-centre tau_MO
+
+  // downwind point P and the BESSER control points (Sect. 3.2)
+  double lamfac;
+  if (a.kP >= 0) {
+    const double dsP = a.dzP * inv_mu;
+    const Stencil sP = make_stencil(i, j, a.nx, a.ny, dsP * rc.sx * a.inv_dx,
+                                    dsP * rc.sy * a.inv_dy);
+    const size_t bP = (size_t)a.kP * a.np;
+    const double kapP = bil(a.kappa + bP, sP);
+    double epsP[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) epsP[c] = bil(a.emis + c * N + bP, sP);
+    const double tau0P = 0.5 * (kapO + kapP) * dsP;
+    const double ratio = tau0M / tau0P;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double ep = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ep += rc.emis[s][c] * epsP[c];
+      cM[s] = besser_cm(SM[s], SO[s], ep / kapP, ratio);
+    }
+    lamfac = 1.0;
+  } else {
+    // no downwind plane: linear control point
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cM[s] = 0.5 * (SM[s] + SO[s]);
+    lamfac = 0.5;
+  }
+
+  // frequency-independent pieces in the sweep precision
+  const T eMv[3] = {(T)(etaM[0] / kapM), (T)(etaM[1] / kapM), (T)(etaM[2] / kapM)};
+  const T rMv[3] = {(T)(etaM[3] / kapM), (T)(etaM[4] / kapM), (T)(etaM[5] / kapM)};
+  const T eOv[3] = {(T)(etaO[0] / kapO), (T)(etaO[1] / kapO), (T)(etaO[2] / kapO)};
+  const T rOv[3] = {(T)(etaO[3] / kapO), (T)(etaO[4] / kapO), (T)(etaO[5] / kapO)};
+  T SMt[4], SOt[4], cMt[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    SMt[s] = (T)SM[s];
+    SOt[s] = (T)SO[s];
+    cMt[s] = (T)cM[s];
+  }
+  const T tau0 = (T)tau0M;
+  const T w00 = (T)sM.w00, w10 = (T)sM.w10, w01 = (T)sM.w01, w11 = (T)sM.w11;
+  const T lf = (T)lamfac;
+
+  const size_t fstride = (size_t)a.np * 4;
+  const T* ip = a.iprev ? a.iprev + (size_t)rb * a.nfreq * fstride : nullptr;
+  T* op = a.inext + (size_t)rb * a.nfreq * fstride + (size_t)p * 4;
+  double jacc0 = 0.0, jacc1 = 0.0, jacc2 = 0.0, jacc3 = 0.0, lacc = 0.0;
+
+  for (int f = 0; f < a.nfreq; ++f) {
+    const T tau = tau0 * a.phi[f];
+    const Coefs<T> cf = coefficients(tau);
+    T IM[4];
+    if (ip) {
+      const T* q = ip + (size_t)f * fstride;
+      T v00[4], v10[4], v01[4], v11[4];
+      load4(q + 4 * (size_t)sM.i00, v00);
+      load4(q + 4 * (size_t)sM.i10, v10);
+      load4(q + 4 * (size_t)sM.i01, v01);
+      load4(q + 4 * (size_t)sM.i11, v11);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) IM[s] = w00 * v00[s] + w10 * v10[s] + w01 * v01[s] + w11 * v11[s];
+    } else {
+      IM[0] = a.ibound;
+      IM[1] = IM[2] = IM[3] = T(0);
+    }
+    // Eq. fsbez right-hand side
+    T KI[4];
+    kprime_apply(eMv, rMv, IM, KI);
+    T b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      b[s] = cf.e * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
+    // Eq. kappa: (1 + psi'_O K'_O) I_O = b
+    const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
+    const T ro[3] = {cf.psiO * rOv[0], cf.psiO * rOv[1], cf.psiO * rOv[2]};
+    T x[4];
+    solve_stokes(eo, ro, b, x);
+    store4(op + (size_t)f * fstride, x);
+    const double W = a.wn[f];
+    jacc0 += W * (double)x[0];
+    jacc1 += W * (double)x[1];
+    jacc2 += W * (double)x[2];
+    jacc3 += W * (double)x[3];
+    lacc += W * (double)(cf.omO + lf * cf.omC);
+  }
+  if (a.jpart) {
+    double* jp = a.jpart + (size_t)rb * 5 * a.np + p;
+    jp[0] = jacc0;
+    jp[(size_t)a.np] = jacc1;
+    jp[2 * (size_t)a.np] = jacc2;
+    jp[3 * (size_t)a.np] = jacc3;
+    jp[4 * (size_t)a.np] = lacc;
+  }
+}
+
+// Eq. 1 from a stored block of Stokes vectors [nray][nf][N][4].
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_jkq_accumulate(double* __restrict__ jkq, const T* __restrict__ stokes,
+                     const T* __restrict__ lam, const RayConsts* __restrict__ rays,
+                     const double* __restrict__ wn, int ray0, int nray, int f0, int nf, size_t N) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r = 0; r < nray; ++r) {
+    double ib[4] = {0, 0, 0, 0}, lb = 0.0;
+    for (int q = 0; q < nf; ++q) {
+      const double W = wn[f0 + q];
+      const size_t off = ((size_t)r * nf + q) * N + p;
+      T v[4];
+      load4(stokes + 4 * off, v);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ib[s] += W * (double)v[s];
+      if (lam) lb += W * (double)lam[off];
+    }
+    const RayConsts& rc = rays[ray0 + r];
+    const double w = rc.weight;
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      acc[c] += w * (rc.proj[c][0] * ib[0] + rc.proj[c][1] * ib[1] + rc.proj[c][2] * ib[2] +
+                     rc.proj[c][3] * ib[3]);
+    acc[9] += w * lb;
+  }
+#pragma unroll
+  for (int c = 0; c < 10; ++c) jkq[c * N + p] += acc[c];
+}
+
+// ---------------------------------------------------------------------------
+// Statistical equilibrium (Jacobi for K = 0, Lambda iteration with Hanle
+// rotation for K = 2) and the per-block maximum of |dS00| / |S00|.
+// ---------------------------------------------------------------------------
+template <class T>
+struct SeeArgs {
+  const double* jkq;
+  const double* s_old;
+  double* s_new;
+  const double* hanle;   // or nullptr
+  const double* bhat;    // or nullptr
+  const T* kappa;        // or nullptr
+  T* emis_out;           // or nullptr
+  double* blockmax;      // [gridDim.x] or nullptr
+  size_t N;
+  double eps_c, delta2, w2, planck;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_see(const SeeArgs<T> a) {
+  __shared__ double red[256];
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rel = 0.0;
+  if (p < a.N) {
+    const size_t N = a.N;
+    const double oe = 1.0 - a.eps_c;
+    const double J00 = a.jkq[p], Lb = a.jkq[9 * N + p];
+    const double so = a.s_old[p];
+    const double s00 = (oe * (J00 - Lb * so) + a.eps_c * a.planck) / (1.0 - oe * Lb);
+    const double c = oe * a.w2;
+    double x[5] = {c * a.jkq[4 * N + p], c * a.jkq[5 * N + p], -c * a.jkq[6 * N + p],
+                   c * a.jkq[7 * N + p], -c * a.jkq[8 * N + p]};
+    const double ad = 1.0 + a.delta2 * oe;
+    const double h = a.hanle ? oe * a.hanle[p] : 0.0;
+    if (h != 0.0) {
+      const double bx = a.bhat ? a.bhat[p] : 0.0;
+      const double by = a.bhat ? a.bhat[N + p] : 0.0;
+      const double bz = a.bhat ? a.bhat[2 * N + p] : 1.0;
+      double A[5][5];
+      hanle_system(ad, h, bx, by, bz, A);
+      solve_pivot<5>(A, x);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) x[q] /= ad;
+    }
+    a.s_new[p] = s00;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a.s_new[(q + 1) * N + p] = x[q];
+    if (a.emis_out) {
+      const double k = (double)a.kappa[p];
+      a.emis_out[p] = (T)(k * s00);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) a.emis_out[(q + 1) * N + p] = (T)(k * x[q]);
+    }
+    rel = fabs(s00 - so) / fabs(s00);
+  }
+  if (!a.blockmax) return;
+  red[threadIdx.x] = rel;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.blockmax[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_max_final(const double* __restrict__ v, int n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+}  // namespace porta

@@ -1,0 +1,333 @@
+// porta_math.hpp -- per-update arithmetic of the BESSER short-characteristics
+// step (Stepan & Trujillo Bueno 2013, Sect. 3), written for gfx950 and usable
+// from host code as well (the host build only serves unit tests of this file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace porta {
+
+// ---------------------------------------------------------------------------
+// exp(-t) for t >= 0.  On the GPU the FP32 form maps to v_exp_f32.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float exp_neg(float t) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __expf(-t);
+#else
+  return std::exp(-t);
+#endif
+}
+__host__ __device__ inline double exp_neg(double t) { return exp(-t); }
+
+// ---------------------------------------------------------------------------
+// Coefficients of Eq. fsbez (Sect. 3.3):
+//   e = exp(-tau), psi'_M, psi'_O (linear K'I), omega_M, omega_O, omega_C
+//   (quadratic Bezier source function with control point c_M).
+// Below a threshold the closed forms cancel; a Taylor series about tau = 0 is
+// used instead (Table 1 gives the FP64 thresholds 0.14 / 0.18 for the omegas).
+// FP32 uses ten terms below tau = 1.2, which keeps every coefficient within
+// 1e-6 relative of its exact value; FP64 uses eight terms below the paper's
+// thresholds (0.1 for the psi').
+// ---------------------------------------------------------------------------
+template <class T>
+struct Coefs {
+  T e, psiM, psiO, omM, omO, omC;
+};
+
+// Horner evaluation of tau * sum_{n<NT} c_n tau^n.
+template <class T, int NT>
+__host__ __device__ inline T series(T tau, const T (&c)[NT]) {
+  T acc = c[NT - 1];
+#pragma unroll
+  for (int n = NT - 2; n >= 0; --n) acc = acc * tau + c[n];
+  return acc * tau;
+}
+
+// Series coefficients (-1)^n a_n for n = 0..9 of
+//   psi'_M: 1/(n! (n+2))      psi'_O: 1/(n+2)!
+//   omega_M: 1/(n! (n+3))     omega_O: 2/(n+3)!     omega_C: 2/(n! (n+2)(n+3))
+#define PORTA_SERIES_TABLES(T)                                                        \
+  const T kPM[10] = {T(1.0 / 2), T(-1.0 / 3), T(1.0 / 8), T(-1.0 / 30), T(1.0 / 144),  \
+                     T(-1.0 / 840), T(1.0 / 5760), T(-1.0 / 45360), T(1.0 / 403200),  \
+                     T(-1.0 / 3991680)};                                               \
+  const T kPO[10] = {T(1.0 / 2), T(-1.0 / 6), T(1.0 / 24), T(-1.0 / 120), T(1.0 / 720), \
+                     T(-1.0 / 5040), T(1.0 / 40320), T(-1.0 / 362880),                  \
+                     T(1.0 / 3628800), T(-1.0 / 39916800)};                            \
+  const T kOM[10] = {T(1.0 / 3), T(-1.0 / 4), T(1.0 / 10), T(-1.0 / 36), T(1.0 / 168),  \
+                     T(-1.0 / 960), T(1.0 / 6480), T(-1.0 / 50400), T(1.0 / 443520),  \
+                     T(-1.0 / 4354560)};                                               \
+  const T kOO[10] = {T(1.0 / 3), T(-1.0 / 12), T(1.0 / 60), T(-1.0 / 360),             \
+                     T(1.0 / 2520), T(-1.0 / 20160), T(1.0 / 181440),                  \
+                     T(-1.0 / 1814400), T(1.0 / 19958400), T(-1.0 / 239500800)};       \
+  const T kOC[10] = {T(1.0 / 3), T(-1.0 / 6), T(1.0 / 20), T(-1.0 / 90), T(1.0 / 504),  \
+                     T(-1.0 / 3360), T(1.0 / 25920), T(-1.0 / 226800),                 \
+                     T(1.0 / 2217600), T(-1.0 / 23950080)};
+
+__host__ __device__ inline Coefs<float> coefficients(float tau) {
+  PORTA_SERIES_TABLES(float)
+  Coefs<float> c;
+  c.e = exp_neg(tau);
+  if (tau < 1.2f) {
+    c.psiM = series(tau, kPM);
+    c.psiO = series(tau, kPO);
+    c.omM = series(tau, kOM);
+    c.omO = series(tau, kOO);
+    c.omC = series(tau, kOC);
+  } else {
+    const float it = 1.0f / tau, it2 = it * it;
+    const float g = c.e + tau - 1.0f;               // e + tau - 1
+    c.psiO = g * it;
+    c.psiM = (1.0f - c.e * (1.0f + tau)) * it;
+    c.omM = (2.0f - c.e * (tau * tau + 2.0f * tau + 2.0f)) * it2;
+    c.omO = 1.0f - 2.0f * g * it2;
+    c.omC = 2.0f * (tau - 2.0f + c.e * (tau + 2.0f)) * it2;
+  }
+  return c;
+}
+
+__host__ __device__ inline Coefs<double> coefficients(double tau) {
+  // eight terms, identical to the rows of Table 1 for the omegas
+  const double kPM[8] = {1.0 / 2, -1.0 / 3, 1.0 / 8, -1.0 / 30, 1.0 / 144, -1.0 / 840,
+                         1.0 / 5760, -1.0 / 45360};
+  const double kPO[8] = {1.0 / 2, -1.0 / 6, 1.0 / 24, -1.0 / 120, 1.0 / 720, -1.0 / 5040,
+                         1.0 / 40320, -1.0 / 362880};
+  const double kOM[8] = {1.0 / 3, -1.0 / 4, 1.0 / 10, -1.0 / 36, 1.0 / 168, -1.0 / 960,
+                         1.0 / 6480, -1.0 / 50400};
+  const double kOO[8] = {1.0 / 3, -1.0 / 12, 1.0 / 60, -1.0 / 360, 1.0 / 2520, -1.0 / 20160,
+                         1.0 / 181440, -1.0 / 1814400};
+  const double kOC[8] = {1.0 / 3, -1.0 / 6, 1.0 / 20, -1.0 / 90, 1.0 / 504, -1.0 / 3360,
+                         1.0 / 25920, -1.0 / 226800};
+  Coefs<double> c;
+  c.e = exp_neg(tau);
+  const double it = 1.0 / tau, it2 = it * it;
+  if (tau < 0.1) {
+    c.psiM = series(tau, kPM);
+    c.psiO = series(tau, kPO);
+  } else {
+    c.psiM = (1.0 - c.e * (1.0 + tau)) * it;
+    c.psiO = (c.e + tau - 1.0) * it;
+  }
+  if (tau < 0.14)
+    c.omM = series(tau, kOM);
+  else
+    c.omM = (2.0 - c.e * (tau * tau + 2.0 * tau + 2.0)) * it2;
+  if (tau < 0.18) {
+    c.omO = series(tau, kOO);
+    c.omC = series(tau, kOC);
+  } else {
+    c.omO = 1.0 - 2.0 * (c.e + tau - 1.0) * it2;
+    c.omC = 2.0 * (tau - 2.0 + c.e * (tau + 2.0)) * it2;
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// BESSER control point of the upwind interval (Sect. 3.2, steps 1-9), in the
+// scale-free form with D_M = y_O - y_M, D_P = y_P - y_O and r = h_M / h_P:
+//   parabolic c_M = y_O - (r^2 D_P + D_M) / (2 (1 + r)),
+//   parabolic c_P = y_O + (r D_P + D_M / r) / (2 (1 + r)).
+// Only the ratio of the optical paths enters, so c_M is the same for every
+// frequency when all opacities share one profile.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double besser_cm(double yM, double yO, double yP, double r) {
+  const double dM = yO - yM, dP = yP - yO;
+  if (dM * dP <= 0.0) return yO;                       // extremum at O (step 2)
+  const double inv = 0.5 / (1.0 + r);
+  const double cM = yO - (r * r * dP + dM) * inv;      // steps 3-4
+  if ((cM - yM) * (cM - yO) > 0.0) return yM;          // overshoot in MO (steps 5-6)
+  const double cP = yO + (r * dP + dM / r) * inv;
+  if ((cP - yO) * (cP - yP) > 0.0)                     // overshoot in OP (step 7)
+    return yO - r * dP;                                // c_P = y_P; steps 8-9
+  return cM;
+}
+
+// ---------------------------------------------------------------------------
+// Solve (1 + K') x = b for a Stokes 4-vector, K' with the symmetric
+// dichroism block e = (e_Q, e_U, e_V) and the antisymmetric dispersion block
+// r = (r_Q, r_U, r_V):
+//   K' = [[0, eQ, eU, eV], [eQ, 0, rV, -rU], [eU, -rV, 0, rQ], [eV, rU, -rQ, 0]].
+// Eliminating x_0 leaves (B - e e^T) x_v = b_v - b_0 e with B y = y + y x r,
+// whose inverse is B^-1 y = (y - y x r + (y.r) r) / (1 + r.r); the rank-one
+// term is removed with the Sherman-Morrison formula.
+// ---------------------------------------------------------------------------
+template <class T>
+__host__ __device__ inline void binv(const T y[3], const T r[3], T inv_den, T out[3]) {
+  const T yr = y[0] * r[0] + y[1] * r[1] + y[2] * r[2];
+  out[0] = (y[0] - (y[1] * r[2] - y[2] * r[1]) + yr * r[0]) * inv_den;
+  out[1] = (y[1] - (y[2] * r[0] - y[0] * r[2]) + yr * r[1]) * inv_den;
+  out[2] = (y[2] - (y[0] * r[1] - y[1] * r[0]) + yr * r[2]) * inv_den;
+}
+
+template <class T>
+__host__ __device__ inline void solve_stokes(const T e[3], const T r[3], const T b[4], T x[4]) {
+  const T inv_den = T(1) / (T(1) + r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const T c[3] = {b[1] - b[0] * e[0], b[2] - b[0] * e[1], b[3] - b[0] * e[2]};
+  T u[3], v[3];
+  binv(c, r, inv_den, u);
+  binv(e, r, inv_den, v);
+  const T eu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
+  const T ev = e[0] * v[0] + e[1] * v[1] + e[2] * v[2];
+  const T f = eu / (T(1) - ev);
+  x[1] = u[0] + f * v[0];
+  x[2] = u[1] + f * v[1];
+  x[3] = u[2] + f * v[2];
+  x[0] = b[0] - (e[0] * x[1] + e[1] * x[2] + e[2] * x[3]);
+}
+
+// K' x for the same layout (eta = e, rho = r).
+template <class T>
+__host__ __device__ inline void kprime_apply(const T e[3], const T r[3], const T x[4], T y[4]) {
+  y[0] = e[0] * x[1] + e[1] * x[2] + e[2] * x[3];
+  y[1] = e[0] * x[0] + r[2] * x[2] - r[1] * x[3];
+  y[2] = e[1] * x[0] - r[2] * x[1] + r[0] * x[3];
+  y[3] = e[2] * x[0] + r[1] * x[1] - r[0] * x[2];
+}
+
+// ---------------------------------------------------------------------------
+// Per-ray projection tables built from the spherical tensors T^K_Q(i, Omega)
+// of Eq. 1 (reference direction of Stokes Q along (mu cos chi, mu sin chi,
+// -sin theta)):
+//   emis[i][c]: eps_i = sum_c emis[i][c] e_c for the six real multipole
+//               components e = (eps00, eps20, Re eps21, Im eps21, Re eps22,
+//               Im eps22), i.e. eps_i = sum_KQ w^K T^K_Q(i) eps^K_Q summed
+//               over +-Q with eps^K_-Q = (-1)^Q conj(eps^K_Q);
+//   proj[c][i]: J_c = sum_i proj[c][i] I_i for c = J00, J10, Re J11, Im J11,
+//               J20, Re J21, Im J21, Re J22, Im J22.
+// ---------------------------------------------------------------------------
+struct RayConsts {
+  double mu;        // signed direction cosine
+  double sx, sy;    // horizontal direction components sin(theta) cos/sin(chi)
+  double weight;    // quadrature weight (all rays sum to 1)
+  double emis[4][6];
+  double proj[9][4];
+};
+
+__host__ __device__ inline void ray_consts(double mu, double chi, double weight, double w2,
+                                           RayConsts& rc) {
+  const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  const double c1 = cos(chi), s1 = sin(chi), c2 = cos(2.0 * chi), s2 = sin(2.0 * chi);
+  const double r3h = 0.5 * sqrt(3.0);            // sqrt(3)/2
+  const double r3q = 0.25 * sqrt(3.0);           // sqrt(3)/4
+  const double k20 = 1.0 / (2.0 * sqrt(2.0));
+  rc.mu = mu;
+  rc.sx = st * c1;
+  rc.sy = st * s1;
+  rc.weight = weight;
+  // T^K_Q for Q >= 0 as (re, im): index 0 -> K=0; 1 -> (1,0); 2 -> (1,1);
+  // 3 -> (2,0); 4 -> (2,1); 5 -> (2,2).
+  double tr[4][6] = {}, ti[4][6] = {};
+  // Stokes I
+  tr[0][0] = 1.0;
+  tr[0][3] = k20 * (3.0 * mu * mu - 1.0);
+  tr[0][4] = -r3h * st * mu * c1;  ti[0][4] = -r3h * st * mu * s1;
+  tr[0][5] = r3q * st * st * c2;   ti[0][5] = r3q * st * st * s2;
+  // Stokes Q
+  tr[1][3] = -3.0 * k20 * st * st;
+  tr[1][4] = -r3h * st * mu * c1;  ti[1][4] = -r3h * st * mu * s1;
+  tr[1][5] = -r3q * (1.0 + mu * mu) * c2;  ti[1][5] = -r3q * (1.0 + mu * mu) * s2;
+  // Stokes U: -i (sqrt3/2) sin(theta) e^{i chi}, -i (sqrt3/2) mu e^{2 i chi}
+  tr[2][4] = r3h * st * s1;        ti[2][4] = -r3h * st * c1;
+  tr[2][5] = r3h * mu * s2;        ti[2][5] = -r3h * mu * c2;
+  // Stokes V
+  tr[3][1] = sqrt(1.5) * mu;
+  tr[3][2] = -r3h * st * c1;       ti[3][2] = -r3h * st * s1;
+  for (int i = 0; i < 4; ++i) {
+    rc.emis[i][0] = tr[i][0];
+    rc.emis[i][1] = w2 * tr[i][3];
+    rc.emis[i][2] = 2.0 * w2 * tr[i][4];    // 2 Re(T e) = 2 (Tr er - Ti ei)
+    rc.emis[i][3] = -2.0 * w2 * ti[i][4];
+    rc.emis[i][4] = 2.0 * w2 * tr[i][5];
+    rc.emis[i][5] = -2.0 * w2 * ti[i][5];
+    rc.proj[0][i] = tr[i][0];
+    rc.proj[1][i] = tr[i][1];
+    rc.proj[2][i] = tr[i][2];
+    rc.proj[3][i] = ti[i][2];
+    rc.proj[4][i] = tr[i][3];
+    rc.proj[5][i] = tr[i][4];
+    rc.proj[6][i] = ti[i][4];
+    rc.proj[7][i] = tr[i][5];
+    rc.proj[8][i] = ti[i][5];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-level statistical equilibrium for K = 2 with Hanle rotation, written as
+// a real 5x5 system in x = (S20, Re S21, Im S21, Re S22, Im S22).  With
+// a = 1 + delta (1 - eps), h = (1 - eps) H_u, g = sqrt(6)/2 and the right-hand
+// side R_Q = (1 - eps) w2 conj(J^2_Q):
+//   a S_Q + i h sum_Q' <Q|b.J|Q'> S_Q' = R_Q, using S_-Q = (-1)^Q conj(S_Q).
+// Rows Q = 0, 1 (re, im), 2 (re, im).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void hanle_system(double a, double h, double bx, double by,
+                                             double bz, double A[5][5]) {
+  const double g = 0.5 * sqrt(6.0);
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) A[i][j] = 0.0;
+  // Q = 0
+  A[0][0] = a;
+  A[0][1] = -2.0 * h * g * by;
+  A[0][2] = -2.0 * h * g * bx;
+  // Q = 1, real part
+  A[1][0] = h * g * by;
+  A[1][1] = a;
+  A[1][2] = -h * bz;
+  A[1][3] = -h * by;
+  A[1][4] = -h * bx;
+  // Q = 1, imaginary part
+  A[2][0] = h * g * bx;
+  A[2][1] = h * bz;
+  A[2][2] = a;
+  A[2][3] = h * bx;
+  A[2][4] = -h * by;
+  // Q = 2, real part
+  A[3][1] = h * by;
+  A[3][2] = -h * bx;
+  A[3][3] = a;
+  A[3][4] = -2.0 * h * bz;
+  // Q = 2, imaginary part
+  A[4][1] = h * bx;
+  A[4][2] = h * by;
+  A[4][3] = 2.0 * h * bz;
+  A[4][4] = a;
+}
+
+template <int N>
+__host__ __device__ inline void solve_pivot(double A[N][N], double b[N]) {
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    double best = fabs(A[c][c]);
+    for (int r = c + 1; r < N; ++r) {
+      const double v = fabs(A[r][c]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (piv != c) {
+      for (int k = 0; k < N; ++k) {
+        const double t = A[c][k];
+        A[c][k] = A[piv][k];
+        A[piv][k] = t;
+      }
+      const double t = b[c];
+      b[c] = b[piv];
+      b[piv] = t;
+    }
+    const double inv = 1.0 / A[c][c];
+    for (int r = c + 1; r < N; ++r) {
+      const double f = A[r][c] * inv;
+      for (int k = c; k < N; ++k) A[r][k] -= f * A[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = N - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < N; ++k) s -= A[r][k] * b[k];
+    b[r] = s / A[r][r];
+  }
+}
+
+}  // namespace porta

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of the C ABI in include/porta.h.
+
+Only argument marshalling happens here: every step of the computation runs in
+the HIP kernels of libporta.so.  PyTorch provides device memory and the
+current stream.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libporta.so")
+
+F64, F32 = 0, 1
+BILINEAR, BEZIER2D = 0, 1
+WS_SWEEP, WS_ADJOINT, WS_JKQ, WS_SEE = 0, 1, 2, 3
+
+_dp = C.POINTER(C.c_double)
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("z", _dp)]
+
+
+class Quad(C.Structure):
+    _fields_ = [("nmu", C.c_int32), ("nchi", C.c_int32), ("nfreq", C.c_int32),
+                ("mu", _dp), ("wmu", _dp), ("phi", _dp), ("wfreq", _dp)]
+
+
+class Fields(C.Structure):
+    _fields_ = [("kappa", C.c_void_p), ("propmat", C.c_void_p), ("emis", C.c_void_p),
+                ("i_bottom", C.c_double), ("w2", C.c_double)]
+
+
+class Atom(C.Structure):
+    _fields_ = [("eps_c", C.c_double), ("delta2", C.c_double), ("w2", C.c_double),
+                ("planck", C.c_double), ("hanle", C.c_void_p), ("bhat", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32)]
+
+
+class PortaError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load libporta.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -c 'import __graft_entry__ as g; g.build()'`")
+            L = C.CDLL(LIB_PATH)
+            vp, sz = C.c_void_p, C.c_size_t
+            L.porta_workspace_size.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int, C.c_int,
+                                               C.c_int, C.POINTER(Options)]
+            L.porta_workspace_size.restype = sz
+            L.porta_fs_sweep.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
+                                         C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
+                                         vp, sz, vp]
+            L.porta_jkq_accumulate.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int, C.c_int,
+                                               C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, sz, vp]
+            L.porta_see_update.argtypes = [C.c_int64, vp, C.POINTER(Atom), vp, vp, vp, vp,
+                                           C.c_int, vp, vp, sz, vp]
+            L.porta_fs_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
+                                           C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
+                                           vp, vp, vp, sz, vp]
+            L.porta_strerror.argtypes = [C.c_int]
+            L.porta_strerror.restype = C.c_char_p
+            L.porta_last_error.restype = C.c_char_p
+            L.porta_version.restype = C.c_char_p
+            _lib = L
+    return _lib
+
+
+EXPORTED = ("porta_workspace_size", "porta_fs_sweep", "porta_jkq_accumulate",
+            "porta_see_update", "porta_fs_adjoint", "porta_strerror", "porta_last_error",
+            "porta_version")
+
+
+def _check(fn, status):
+    if status != 0:
+        L = lib()
+        raise PortaError(fn, status, f"{L.porta_strerror(status).decode()}: "
+                                     f"{L.porta_last_error().decode()}")
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor/array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class HostGrid:
+    """Host-side grid/quadrature structs with the arrays they point to."""
+
+    def __init__(self, nx, ny, nz, lx, ly, z, mu, wmu, nchi, phi, wfreq):
+        self._z = np.ascontiguousarray(z, np.float64)
+        self._mu = np.ascontiguousarray(mu, np.float64)
+        self._wmu = np.ascontiguousarray(wmu, np.float64)
+        self._phi = np.ascontiguousarray(phi, np.float64)
+        self._wfreq = np.ascontiguousarray(wfreq, np.float64)
+        self.grid = Grid(int(nx), int(ny), int(nz), float(lx), float(ly),
+                         self._z.ctypes.data_as(_dp))
+        self.quad = Quad(len(self._mu), int(nchi), len(self._phi), self._mu.ctypes.data_as(_dp),
+                         self._wmu.ctypes.data_as(_dp), self._phi.ctypes.data_as(_dp),
+                         self._wfreq.ctypes.data_as(_dp))
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.N = self.nx * self.ny * self.nz
+        self.nmu, self.nchi, self.nfreq = len(self._mu), int(nchi), len(self._phi)
+        self.nrays = 2 * self.nmu * self.nchi
+        self.nray_up = self.nmu * self.nchi
+
+    @classmethod
+    def from_inputs(cls, atm, quad):
+        return cls(atm.nx, atm.ny, atm.nz, atm.lx, atm.ly, atm.z, quad.mu, quad.wmu, quad.nchi,
+                   quad.phi, quad.wfreq)
+
+
+def options(ray_batch=0, block=0):
+    return Options(int(ray_batch), int(block))
+
+
+def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:
+    n = lib().porta_workspace_size(C.byref(hg.grid), C.byref(hg.quad), int(prec), int(kind),
+                                   int(checkpoint_stride), C.byref(opts) if opts else None)
+    if n == 0:
+        raise PortaError("porta_workspace_size", -1, lib().porta_last_error().decode())
+    return int(n)
+
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def dtype_of(prec):
+    import torch
+    return torch.float64 if prec == F64 else torch.float32
+
+
+def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, interp=BILINEAR,
+             jkq=None, accumulate=False, i_top=None, want_jkq=True, want_itop=True,
+             opts=None, workspace=None, stream=None):
+    """porta_fs_sweep.  Returns (jkq [10][N] float64, i_top [nray_up][nfreq][ny][nx][4])."""
+    import torch
+    dev = kappa.device
+    if want_jkq and jkq is None:
+        jkq = torch.empty((10, hg.N), dtype=torch.float64, device=dev)
+    if want_itop and i_top is None:
+        i_top = torch.empty((hg.nray_up, hg.nfreq, hg.ny, hg.nx, 4), dtype=dtype_of(prec),
+                            device=dev)
+    if workspace is None:
+        workspace = _workspace(workspace_size(hg, prec, WS_SWEEP, 1, opts), dev)
+    f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))
+    st = lib().porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), int(prec),
+                              int(interp), C.byref(opts) if opts else None,
+                              _ptr(jkq) if want_jkq else None, int(bool(accumulate)),
+                              _ptr(i_top) if want_itop else None, _ptr(workspace),
+                              workspace.numel(), _stream(stream))
+    _check("porta_fs_sweep", st)
+    return (jkq if want_jkq else None), (i_top if want_itop else None)
+
+
+def jkq_accumulate(hg: HostGrid, ray0, f0, stokes, lambda_star=None, jkq=None, prec=F64,
+                   workspace=None, stream=None):
+    """porta_jkq_accumulate for stokes [nray][nf][N][4]."""
+    import torch
+    dev = stokes.device
+    if jkq is None:
+        jkq = torch.zeros((10, hg.N), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = _workspace(workspace_size(hg, prec, WS_JKQ), dev)
+    nray, nf = stokes.shape[0], stokes.shape[1]
+    st = lib().porta_jkq_accumulate(C.byref(hg.grid), C.byref(hg.quad), int(ray0), int(nray),
+                                    int(f0), int(nf), _ptr(stokes), _ptr(lambda_star), int(prec),
+                                    _ptr(jkq), _ptr(workspace), workspace.numel(),
+                                    _stream(stream))
+    _check("porta_jkq_accumulate", st)
+    return jkq
+
+
+def see_update(jkq, s_old, eps_c, delta2, w2, planck, hanle=None, bhat=None, kappa=None,
+               emis_out=None, prec=F64, want_rc=True, s_new=None, rc=None, workspace=None,
+               stream=None):
+    """porta_see_update.  Returns (s_new [6][N], emis_out or None, rc device scalar or None)."""
+    import torch
+    dev = jkq.device
+    n = s_old.shape[1]
+    if s_new is None:
+        s_new = torch.empty_like(s_old)
+    if want_rc and rc is None:
+        rc = torch.empty((), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = _workspace(8 * ((n + 255) // 256), dev)
+    atom = Atom(float(eps_c), float(delta2), float(w2), float(planck), _ptr(hanle), _ptr(bhat))
+    st = lib().porta_see_update(int(n), _ptr(jkq), C.byref(atom), _ptr(s_old), _ptr(s_new),
+                                _ptr(kappa), _ptr(emis_out), int(prec),
+                                _ptr(rc) if want_rc else None, _ptr(workspace),
+                                workspace.numel(), _stream(stream))
+    _check("porta_see_update", st)
+    return s_new, emis_out, (rc if want_rc else None)
+
+
+def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, prec=F64,
+               interp=BILINEAR, checkpoint_stride=8, g_kappa=None, g_propmat=None, g_emis=None,
+               opts=None, workspace=None, stream=None):
+    """porta_fs_adjoint; gradients are added to g_* (allocated as zeros if None)."""
+    import torch
+    dev = kappa.device
+    if g_kappa is None:
+        g_kappa = torch.zeros_like(kappa)
+    if g_propmat is None:
+        g_propmat = torch.zeros_like(propmat)
+    if g_emis is None:
+        g_emis = torch.zeros_like(emis)
+    if workspace is None:
+        workspace = _workspace(workspace_size(hg, prec, WS_ADJOINT, checkpoint_stride, opts), dev)
+    f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))
+    st = lib().porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), int(prec),
+                                int(interp), C.byref(opts) if opts else None, _ptr(dl_ditop),
+                                int(checkpoint_stride), _ptr(g_kappa), _ptr(g_propmat),
+                                _ptr(g_emis), _ptr(workspace), workspace.numel(), _stream(stream))
+    _check("porta_fs_adjoint", st)
+    return g_kappa, g_propmat, g_emis
+
+
+def version() -> str:
+    return lib().porta_version().decode()

@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: exported symbols and host-side validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1307_4217_amd import inputs, porta
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "porta.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(porta_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = porta.lib()
+    names = declared_symbols()
+    assert set(names) == set(porta.EXPORTED), names
+    for n in names:
+        assert hasattr(L, n), n
+    assert "gfx950" in porta.version()
+
+
+def small_hg(**kw):
+    cfg = inputs.CONFIGS["C1"]
+    atm = inputs.make_atmosphere(cfg)
+    q = inputs.make_quadrature(cfg)
+    args = dict(nx=atm.nx, ny=atm.ny, nz=atm.nz, lx=atm.lx, ly=atm.ly, z=atm.z, mu=q.mu,
+                wmu=q.wmu, nchi=q.nchi, phi=q.phi, wfreq=q.wfreq)
+    args.update(kw)
+    return porta.HostGrid(**args)
+
+
+def call_sweep(hg, prec=porta.F64, interp=porta.BILINEAR, ws_bytes=None, fields=True, ws=True):
+    L = porta.lib()
+    dummy = np.zeros(8)
+    f = porta.Fields(dummy.ctypes.data if fields else None, dummy.ctypes.data,
+                     dummy.ctypes.data, 1.0, 1.0)
+    return L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), prec, interp, None,
+                            None, 0, None, dummy.ctypes.data if ws else None,
+                            0 if ws_bytes is None else ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw, code", [
+    (dict(nz=1, z=[0.0]), -1),
+    (dict(nx=0), -1),
+    (dict(z=np.linspace(1, 0, 32)), -1),
+    (dict(z=np.r_[np.linspace(0, 1, 31), np.nan]), -1),
+    (dict(lx=-1.0), -1),
+    (dict(mu=[0.5, 1.2, 0.3, 0.2, 0.1]), -1),
+    (dict(mu=[0.0, 0.5, 0.3, 0.2, 0.1]), -1),
+    (dict(wmu=[0.2] * 4 + [0.3]), -1),
+    (dict(phi=-np.ones(21)), -1),
+    (dict(wfreq=np.zeros(21)), -1),
+])
+def test_sweep_rejects_bad_geometry(kw, code):
+    hg = small_hg(**kw)
+    assert call_sweep(hg) == -1
+    assert porta.lib().porta_last_error().decode() != ""
+
+
+def test_sweep_rejects_bad_enums_and_pointers():
+    hg = small_hg()
+    assert call_sweep(hg, prec=7) == -1
+    assert call_sweep(hg, interp=9) == -1
+    assert call_sweep(hg, fields=False) == -1
+    assert call_sweep(hg, ws=False) == -1
+
+
+def test_sweep_reports_short_workspace():
+    hg = small_hg()
+    need = porta.workspace_size(hg, porta.F64, porta.WS_SWEEP)
+    assert need > 0
+    assert call_sweep(hg, ws_bytes=need - 1) == -3
+    assert "workspace" in porta.lib().porta_last_error().decode()
+
+
+def test_workspace_sizes_scale_with_precision_and_batch():
+    hg = small_hg()
+    w64 = porta.workspace_size(hg, porta.F64, porta.WS_SWEEP)
+    w32 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP)
+    assert w32 < w64
+    wb = porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, opts=porta.options(ray_batch=8))
+    assert wb < w64
+    assert porta.workspace_size(hg, porta.F64, porta.WS_JKQ) < wb
+    assert porta.lib().porta_workspace_size(C.byref(hg.grid), C.byref(hg.quad), 5, 0, 1,
+                                            None) == 0
+
+
+def test_other_entry_points_validate():
+    L = porta.lib()
+    hg = small_hg()
+    dummy = np.zeros(8)
+    a = porta.Atom(1.5, 0.0, 1.0, 1.0, None, None)
+    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+                              dummy.ctypes.data, None, None, 0, None, None, 0, None) == -1
+    a = porta.Atom(0.1, 0.0, 1.0, 1.0, None, None)
+    assert L.porta_see_update(0, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+                              dummy.ctypes.data, None, None, 0, None, None, 0, None) == -1
+    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+                              dummy.ctypes.data, None, None, 0, dummy.ctypes.data,
+                              dummy.ctypes.data, 1, None) == -3
+    assert L.porta_jkq_accumulate(C.byref(hg.grid), C.byref(hg.quad), 70, 20, 0, 1,
+                                  dummy.ctypes.data, None, 0, dummy.ctypes.data,
+                                  dummy.ctypes.data, 1 << 20, None) == -1
+    assert L.porta_jkq_accumulate(C.byref(hg.grid), C.byref(hg.quad), 0, 1, 20, 2,
+                                  dummy.ctypes.data, None, 0, dummy.ctypes.data,
+                                  dummy.ctypes.data, 1 << 20, None) == -1
+    f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
+    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None,
+                              dummy.ctypes.data, 0, dummy.ctypes.data, dummy.ctypes.data,
+                              dummy.ctypes.data, dummy.ctypes.data, 1 << 30, None) == -1
+    assert porta.lib().porta_strerror(-3) == b"workspace too small"

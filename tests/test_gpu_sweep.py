@@ -1,0 +1,169 @@
+"""GPU parity of the forward path (C-ABI calls) against the FP64 CPU oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from gpu_common import (Case, compare_jkq, compare_stokes, oracle_full, require_gpu, rounded,
+                        to_dev, up_rays)
+from paper_1307_4217_amd import inputs, porta
+
+pytestmark = pytest.mark.gpu
+
+
+def test_library_is_in_tree():
+    import os
+    require_gpu()
+    assert os.path.dirname(porta.LIB_PATH).endswith("paper_1307_4217_amd")
+    assert "gfx950" in porta.version()
+
+
+def test_sweep_fp64_c1_matches_oracle():
+    atm, q, ref = oracle_full("C1", 0, "f64")
+    case = Case(atm, q, porta.F64)
+    jkq, itop = case.sweep()
+    print("C1 FP64:", compare_stokes(itop, ref["itop"], 1e-10, 1e-12, "itop"),
+          compare_jkq(jkq, ref["jkq"], 1e-10, "jkq"))
+
+
+def test_sweep_fp32_c1_matches_oracle():
+    atm, q, ref = oracle_full("C1", 0, "f32")
+    case = Case(atm, q, porta.F32)
+    jkq, itop = case.sweep()
+    print("C1 FP32:", compare_stokes(itop, ref["itop"], 2e-5, 1e-7, "itop"),
+          compare_jkq(jkq, ref["jkq"], 2e-5, "jkq"))
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+@pytest.mark.parametrize("ray_batch, block", [(0, 256), (3, 64), (7, 192)])
+def test_sweep_ragged_grid_batches_and_blocks(orc, prec, ray_batch, block):
+    """Odd sizes (plane of 7x5 nodes, partial blocks and ray batches, 3 azimuths)."""
+    cfg = inputs.Config("ragged", 7, 5, 9, 2, 3, 5, True)
+    atm = inputs.make_atmosphere(cfg, seed=3)
+    atm = dataclasses.replace(atm, lx=530.0, ly=410.0, z=np.sort(np.random.default_rng(9).uniform(0, 900, 9)))
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q))
+    case = Case(atm, q, prec)
+    jkq, itop = case.sweep(opts=porta.options(ray_batch=ray_batch, block=block))
+    tol_i, tol_p = (1e-10, 1e-12) if prec == porta.F64 else (2e-5, 1e-7)
+    compare_stokes(itop, up_rays(ref["itop"], q), tol_i, tol_p, "itop")
+    compare_jkq(jkq, ref["jkq"], tol_i, "jkq")
+
+
+def test_single_plane_pair_and_single_column(orc):
+    """Degenerate grids: nz = 2 (boundary + last plane only) and a 1x1 column."""
+    for (nx, ny, nz) in ((4, 3, 2), (1, 1, 6)):
+        cfg = inputs.Config("tiny", nx, ny, nz, 2, 4, 3, False)
+        atm = inputs.make_atmosphere(cfg, seed=5)
+        q = inputs.make_quadrature(cfg)
+        ref = orc.fs_sweep(orc.OracleProblem(atm, q))
+        jkq, itop = Case(atm, q, porta.F64).sweep()
+        compare_stokes(itop, up_rays(ref["itop"], q), 1e-10, 1e-12, f"itop {nx}x{ny}x{nz}")
+        compare_jkq(jkq, ref["jkq"], 1e-10, f"jkq {nx}x{ny}x{nz}")
+
+
+def test_accumulate_adds_to_existing_j():
+    torch = require_gpu()
+    atm, q, ref = oracle_full("C1", 0, "f64")
+    case = Case(atm, q, porta.F64)
+    j0 = torch.full((10, case.hg.N), 0.25, dtype=torch.float64, device="cuda")
+    porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                   jkq=j0, accumulate=True, want_itop=False)
+    torch.cuda.synchronize()
+    compare_jkq(j0.cpu().numpy() - 0.25, ref["jkq"], 1e-10, "accumulated jkq")
+
+
+def test_sweep_is_deterministic():
+    atm, q, _ = oracle_full("C1", 0, "f64")
+    for prec in (porta.F64, porta.F32):
+        case = Case(atm, q, prec)
+        a = case.sweep()
+        b = case.sweep()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_periodic_shift_is_exact_on_gpu():
+    atm, q, _ = oracle_full("C1", 0, "f64")
+    nx, ny, nz = atm.nx, atm.ny, atm.nz
+    di, dj = 5, 11
+    roll = lambda a: np.roll(a.reshape(a.shape[:-1] + (nz, ny, nx)), (dj, di),
+                             axis=(-2, -1)).reshape(a.shape)
+    atm2 = dataclasses.replace(atm, kappa=roll(atm.kappa[None])[0], propmat=roll(atm.propmat),
+                               emis=roll(atm.emis))
+    j1, t1 = Case(atm, q, porta.F32).sweep()
+    j2, t2 = Case(atm2, q, porta.F32).sweep()
+    assert np.array_equal(j2, roll(j1))
+    assert np.array_equal(t2, np.roll(t1, (dj, di), axis=(2, 3)))
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_jkq_accumulate_matches_oracle(orc, prec):
+    torch = require_gpu()
+    cfg = inputs.Config("blk", 6, 5, 4, 3, 4, 7, False)
+    atm = inputs.make_atmosphere(cfg, seed=2)
+    q = inputs.make_quadrature(cfg)
+    op = orc.OracleProblem(atm, q)
+    rng = np.random.default_rng(7)
+    ray0, nray, f0, nf = 5, 9, 2, 4
+    st = rng.normal(size=(nray, nf, op.N, 4))
+    st[..., 0] += 3.0
+    lam = rng.uniform(0, 1, size=(nray, nf, op.N))
+    dt = np.float64 if prec == porta.F64 else np.float32
+    st, lam = st.astype(dt).astype(np.float64), lam.astype(dt).astype(np.float64)
+    ref = orc.jkq_accumulate(op, ray0, f0, st, lam)
+    hg = porta.HostGrid.from_inputs(atm, q)
+    tdt = torch.float64 if prec == porta.F64 else torch.float32
+    got = porta.jkq_accumulate(hg, ray0, f0, to_dev(st, tdt), to_dev(lam, tdt), prec=prec)
+    torch.cuda.synchronize()
+    compare_jkq(got.cpu().numpy(), ref, 1e-13, "jkq_accumulate")
+
+
+@pytest.mark.parametrize("magnetic", [True, False])
+def test_see_update_matches_oracle(orc, magnetic):
+    torch = require_gpu()
+    atm, q, ref = oracle_full("C1", 0, "f64", magnetic)
+    s_ref, e_ref, rc_ref = orc.see_update(ref["jkq"], atm.source, atm)
+    for prec in (porta.F64, porta.F32):
+        tdt = torch.float64 if prec == porta.F64 else torch.float32
+        emis = torch.empty((6, atm.npoints), dtype=tdt, device="cuda")
+        s_new, _, rc = porta.see_update(
+            to_dev(ref["jkq"], torch.float64), to_dev(atm.source, torch.float64), atm.eps_c,
+            atm.delta2, atm.w2, atm.planck,
+            hanle=None if atm.hanle is None else to_dev(atm.hanle, torch.float64),
+            bhat=None if atm.bhat is None else to_dev(atm.bhat, torch.float64),
+            kappa=to_dev(atm.kappa, tdt), emis_out=emis, prec=prec)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(s_new.cpu().numpy(), s_ref, rtol=1e-12, atol=1e-14)
+        # emis_out = kappa * S_new, in the sweep precision
+        e = emis.cpu().numpy().astype(np.float64) / atm.kappa.astype(tdt == torch.float32 and
+                                                                     np.float32 or np.float64)
+        if prec == porta.F64:
+            np.testing.assert_allclose(e, s_ref, rtol=1e-12, atol=1e-14)
+        else:
+            np.testing.assert_allclose(e, s_ref, rtol=1e-6, atol=1e-7 * np.abs(s_ref).max())
+        assert rc.item() == pytest.approx(rc_ref, rel=1e-12)
+
+
+def test_jacobi_iterations_c1_match_oracle(orc):
+    """Five Jacobi iterations (sweep + J + SEE) in FP64 on the GPU and on the oracle."""
+    torch = require_gpu()
+    atm = inputs.make_atmosphere(inputs.CONFIGS["C1"], seed=1, magnetic=True)
+    q = inputs.make_quadrature(inputs.CONFIGS["C1"])
+    case = Case(atm, q, porta.F64)
+    S = to_dev(atm.source, torch.float64)
+    hanle, bhat = to_dev(atm.hanle, torch.float64), to_dev(atm.bhat, torch.float64)
+    s_host = atm.source.copy()
+    emis_host = atm.emis.copy()
+    for it in range(5):
+        jkq, _ = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                                want_itop=False)
+        S, _, rc = porta.see_update(jkq, S, atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
+                                    bhat, kappa=case.kappa, emis_out=case.emis)
+        torch.cuda.synchronize()
+        ref = orc.fs_sweep(orc.OracleProblem(dataclasses.replace(atm, emis=emis_host), q),
+                           want_itop=False)
+        s_host, emis_host, rc_ref = orc.see_update(ref["jkq"], s_host, atm)
+        np.testing.assert_allclose(S.cpu().numpy(), s_host, rtol=1e-10, atol=1e-12)
+        assert rc.item() == pytest.approx(rc_ref, rel=1e-8)

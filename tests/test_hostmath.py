@@ -1,0 +1,136 @@
+"""The per-update arithmetic of the GPU kernels (porta_math.hpp, compiled for the
+host) against the oracle and closed forms."""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1307_4217_amd import build as pbuild
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+
+
+@pytest.fixture(scope="module")
+def hm():
+    if not os.path.exists(pbuild.HOSTTEST_LIB):
+        pbuild.build_hostmath()
+    L = C.CDLL(pbuild.HOSTTEST_LIB)
+    L.hm_coefficients_f32.argtypes = [C.c_float, _fp]
+    L.hm_coefficients_f64.argtypes = [C.c_double, _dp]
+    L.hm_besser_cm.argtypes = [C.c_double] * 4
+    L.hm_besser_cm.restype = C.c_double
+    L.hm_solve_stokes_f64.argtypes = [_dp] * 4
+    L.hm_solve_stokes_f32.argtypes = [_fp] * 4
+    L.hm_kprime_apply.argtypes = [_dp] * 4
+    L.hm_ray_consts.argtypes = [C.c_double] * 4 + [_dp]
+    L.hm_hanle_solve.argtypes = [C.c_double] * 5 + [_dp, _dp]
+    return L
+
+
+def p(a):
+    return a.ctypes.data_as(_dp if a.dtype == np.float64 else _fp)
+
+
+def coef(hm, tau, f32=False):
+    out = np.zeros(6, np.float32 if f32 else np.float64)
+    (hm.hm_coefficients_f32 if f32 else hm.hm_coefficients_f64)(tau, p(out))
+    return out.astype(np.float64)
+
+
+def test_coefficients_f64_match_oracle(hm, orc):
+    for tau in np.concatenate([np.logspace(-7, 2.5, 300), [0.1, 0.14, 0.18]]):
+        np.testing.assert_allclose(coef(hm, tau), orc.coefficients(tau), rtol=3e-13, atol=0)
+
+
+def test_coefficients_f32_accuracy(hm, orc):
+    worst = 0.0
+    for tau in np.logspace(-7, 2, 600):
+        t32 = float(np.float32(tau))
+        ref = orc.coefficients(t32)
+        got = coef(hm, t32, f32=True)
+        rel = np.abs(got[1:] / ref[1:] - 1)
+        worst = max(worst, rel.max())
+        assert got[0] == pytest.approx(ref[0], rel=1e-6, abs=1e-30)
+    assert worst < 1.5e-6
+
+
+def test_besser_matches_oracle(hm, orc):
+    rng = np.random.default_rng(1)
+    for _ in range(5000):
+        y = rng.normal(size=3)
+        if rng.uniform() < 0.5:
+            y = np.sort(y) * rng.choice([-1, 1])
+        hM, hP = np.exp(rng.uniform(-6, 4, 2))
+        ref = orc.besser_cm(*y, hM, hP)
+        got = hm.hm_besser_cm(*y, hM / hP)
+        assert got == pytest.approx(ref, rel=1e-12, abs=1e-12)
+
+
+def test_solve_stokes_matches_dense_solve(hm, orc):
+    rng = np.random.default_rng(2)
+    for _ in range(500):
+        e = rng.uniform(-0.3, 0.3, 3)
+        r = rng.uniform(-0.3, 0.3, 3)
+        b = rng.normal(size=4)
+        A = np.eye(4) + np.array([[0, e[0], e[1], e[2]], [e[0], 0, r[2], -r[1]],
+                                  [e[1], -r[2], 0, r[0]], [e[2], r[1], -r[0], 0]])
+        x = np.zeros(4)
+        hm.hm_solve_stokes_f64(p(e), p(r), p(b), p(x))
+        np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(x, orc.solve4(A, b), rtol=1e-12, atol=1e-13)
+        y = np.zeros(4)
+        hm.hm_kprime_apply(p(e), p(r), p(x), p(y))
+        np.testing.assert_allclose(y, (A - np.eye(4)) @ x, rtol=1e-13, atol=1e-14)
+        x32 = np.zeros(4, np.float32)
+        hm.hm_solve_stokes_f32(p(e.astype(np.float32)), p(r.astype(np.float32)),
+                               p(b.astype(np.float32)), p(x32))
+        np.testing.assert_allclose(x32, x, rtol=2e-5, atol=2e-6)
+
+
+def test_ray_tables_match_oracle_tensors(hm, orc):
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        mu, chi, w2 = rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi), rng.uniform(0.3, 1.0)
+        out = np.zeros(24 + 36 + 4)
+        hm.hm_ray_consts(mu, chi, 0.1, w2, p(out))
+        emis = out[:24].reshape(4, 6)
+        proj = out[24:60].reshape(9, 4)
+        e6 = rng.normal(size=6)
+        np.testing.assert_allclose(emis @ e6, orc.emission(mu, chi, e6, w2), rtol=1e-13,
+                                   atol=1e-14)
+        t = orc.tkq(mu, chi)        # [4][9], slots K0; K1 Q-1..1; K2 Q-2..2
+        ref = np.array([t[:, 0].real, t[:, 2].real, t[:, 3].real, t[:, 3].imag, t[:, 6].real,
+                        t[:, 7].real, t[:, 7].imag, t[:, 8].real, t[:, 8].imag])
+        np.testing.assert_allclose(proj, ref, atol=1e-15)
+        st = math.sqrt(1 - mu * mu)
+        np.testing.assert_allclose(out[60:], [mu, st * math.cos(chi), st * math.sin(chi), 0.1],
+                                   rtol=1e-15, atol=1e-16)
+
+
+def test_hanle_real_system_matches_complex_solve(hm):
+    rng = np.random.default_rng(4)
+    Jz = np.diag(np.arange(-2, 3)).astype(complex)
+    Jp = np.zeros((5, 5), complex)
+    for q in range(-2, 2):
+        Jp[q + 3, q + 2] = math.sqrt(6 - q * (q + 1))
+    Jm = Jp.conj().T
+    for _ in range(200):
+        a, h = 1 + rng.uniform(0, 1), rng.uniform(0, 10)
+        b = rng.normal(size=3)
+        b /= np.linalg.norm(b)
+        K = b[0] * (Jp + Jm) / 2 + b[1] * (Jp - Jm) / 2j + b[2] * Jz
+        R = np.zeros(5, complex)
+        R[2] = rng.normal()
+        R[3] = rng.normal() + 1j * rng.normal()
+        R[4] = rng.normal() + 1j * rng.normal()
+        R[1] = -np.conj(R[3])
+        R[0] = np.conj(R[4])
+        S = np.linalg.solve(a * np.eye(5) + 1j * h * K, R)
+        rhs = np.array([R[2].real, R[3].real, R[3].imag, R[4].real, R[4].imag])
+        x = np.zeros(5)
+        hm.hm_hanle_solve(a, h, *b, p(rhs), p(x))
+        np.testing.assert_allclose(x, [S[2].real, S[3].real, S[3].imag, S[4].real, S[4].imag],
+                                   rtol=1e-11, atol=1e-13)
