@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-fp64-rate", action="store_true",
                     help="skip the extra FP64 sweep used for the FP32-vs-FP64 rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 1 GiB device-to-device first (counter calibration for profiles)")
     ap.add_argument("--cpu-pairs", type=int, default=16,
                     help="(ray, frequency) pairs of the workload swept by the CPU oracle")
     return ap.parse_args()
@@ -117,6 +119,12 @@ def main():
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     state = {"s_old": s_a, "s_new": s_b}
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(times):
         e0, e1, e2 = ev(), ev(), ev()

@@ -88,7 +88,7 @@ typedef struct {
 typedef struct {
   int32_t nmu;         /* inclinations per hemisphere, 1..64 */
   int32_t nchi;        /* azimuths over 2 pi, >= 1 */
-  int32_t nfreq;       /* frequencies, >= 1 */
+  int32_t nfreq;       /* frequencies, 1..4096 */
   const double* mu;    /* host [nmu], each in (0, 1] */
   const double* wmu;   /* host [nmu], >= 0, summing to 1 within 1e-12 */
   const double* phi;   /* host [nfreq], profile relative to line centre, > 0 */
@@ -122,6 +122,8 @@ typedef struct {
 typedef struct {
   int32_t ray_batch;        /* rays swept together (0: a whole hemisphere) */
   int32_t block;            /* threads per block of the sweep kernel (0: 256) */
+  int32_t xcd_remap;        /* 1: hand each XCD a contiguous range of tiles;
+                               0 or -1 (default): hardware order */
 } porta_options;
 
 /* Bytes of device workspace needed by one call of the given kind (0 on invalid

@@ -62,7 +62,8 @@ int validate_quad(const porta_quad* q) {
   if (!q) return fail(PORTA_EINVAL, "quadrature is NULL");
   if (q->nmu < 1 || q->nmu > kMaxMu) return fail(PORTA_EINVAL, "nmu must be in 1..%d", kMaxMu);
   if (q->nchi < 1 || q->nchi > 4096) return fail(PORTA_EINVAL, "nchi must be in 1..4096");
-  if (q->nfreq < 1 || q->nfreq > 65536) return fail(PORTA_EINVAL, "nfreq must be in 1..65536");
+  if (q->nfreq < 1 || q->nfreq > kMaxFreq)
+    return fail(PORTA_EINVAL, "nfreq must be in 1..%d", kMaxFreq);
   if (!q->mu || !q->wmu || !q->phi || !q->wfreq)
     return fail(PORTA_EINVAL, "quadrature arrays must not be NULL");
   double sw = 0.0;
@@ -261,9 +262,11 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
         a.inv_dx = nx / g->lx;
         a.inv_dy = ny / g->ly;
         a.ray0 = ray0;
+        a.xcd_remap = (o && o->xcd_remap >= 0) ? o->xcd_remap : 0;
         a.ibound = ibound;
+        const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
         hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
-                           0, st, a);
+                           lds, st, a);
         if ((rc = check_launch("sweep_plane"))) return rc;
         prev = a.inext;
       }
@@ -333,7 +336,8 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
-  if (opts && (opts->ray_batch < 0 || opts->block < 0))
+  if (opts && (opts->ray_batch < 0 || opts->block < 0 || opts->xcd_remap < -1 ||
+               opts->xcd_remap > 1))
     return fail(PORTA_EINVAL, "options must be >= 0");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the sweep");

@@ -200,19 +200,76 @@ struct PlaneArgs {
   double dzM, dzP;   // |z_kO - z_kM|, |z_kP - z_kO|
   double inv_dx, inv_dy;
   int ray0;
+  int xcd_remap;     // give each XCD a contiguous range of (ray, node-block) tiles
   T ibound;          // Stokes I on the boundary plane of this hemisphere
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each with
+// its own L2.  Renumbering them so that XCD x receives a contiguous range of
+// tiles keeps the upwind rows shared by neighbouring tiles in one L2.
+__device__ inline void xcd_tile(int remap, int& bx, int& by) {
+  bx = blockIdx.x;
+  by = blockIdx.y;
+  if (!remap) return;
+  const int T = gridDim.x * gridDim.y;
+  const int L = blockIdx.y * gridDim.x + blockIdx.x;
+  const int x = L % 8, q = T / 8, r = T % 8;
+  const int Lp = (x < r) ? x * (q + 1) + L / 8 : r * (q + 1) + (x - r) * q + L / 8;
+  bx = Lp % gridDim.x;
+  by = Lp / gridDim.x;
+}
+
+constexpr int kMaxFreq = 4096;   // frequencies held in LDS by the sweep kernels
+
+#ifndef PORTA_PREFETCH_F32
+#define PORTA_PREFETCH_F32 0
+#endif
+#ifndef PORTA_PREFETCH_F64
+#define PORTA_PREFETCH_F64 0
+#endif
+// Whether the frequency loop fetches the upwind values one frequency ahead
+// (costs 16 registers of the sweep precision).
+template <class T>
+struct SweepTraits;
+template <>
+struct SweepTraits<float> {
+  static constexpr bool kPrefetch = PORTA_PREFETCH_F32;
+};
+template <>
+struct SweepTraits<double> {
+  static constexpr bool kPrefetch = PORTA_PREFETCH_F64;
+};
+
+template <class T>
+__device__ inline void load_upwind(const T* __restrict__ q, const Stencil& s, T v[4][4]) {
+  load4(q + 4 * (size_t)s.i00, v[0]);
+  load4(q + 4 * (size_t)s.i10, v[1]);
+  load4(q + 4 * (size_t)s.i01, v[2]);
+  load4(q + 4 * (size_t)s.i11, v[3]);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const int rb = blockIdx.y;
-  if (rb == 0 && a.jkq)
+  // per-frequency weights and profile, read from LDS inside the frequency loop so that
+  // no vector-memory wait (which on gfx9 also covers earlier stores) sits in the loop
+  extern __shared__ double s_tab[];
+  double* s_wn = s_tab;
+  T* s_phi = reinterpret_cast<T*>(s_tab + a.nfreq);
+  for (int t = threadIdx.x; t < a.nfreq; t += blockDim.x) {
+    s_wn[t] = a.wn[t];
+    s_phi[t] = a.phi[t];
+  }
+  __syncthreads();
+  int bx, rb;
+  xcd_tile(a.xcd_remap, bx, rb);
+  const int p = bx * blockDim.x + threadIdx.x;
+  const bool active = p < a.np;
+  const int pp = active ? p : 0;   // inactive lanes only take part in the barriers
+  if (active && rb == 0 && a.jkq)
     jreduce_point(a.jkq, a.jpart_prev, a.rays, a.ray0, gridDim.y, a.np, a.N, a.prev_off, p,
                   a.jpart_prev == nullptr, (double)a.ibound);
   const RayConsts& rc = a.rays[a.ray0 + rb];
-  const int i = p % a.nx, j = p / a.nx;
+  const int i = pp % a.nx, j = pp / a.nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   const size_t N = a.N;
 
@@ -220,9 +277,10 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
   const double dsM = a.dzM * inv_mu;
   const Stencil sM = make_stencil(i, j, a.nx, a.ny, -dsM * rc.sx * a.inv_dx,
                                   -dsM * rc.sy * a.inv_dy);
-  const size_t bM = (size_t)a.kM * a.np, bO = (size_t)a.kO * a.np + p;
+  const size_t bM = (size_t)a.kM * a.np, bO = (size_t)a.kO * a.np + pp;
   const double kapM = bil(a.kappa + bM, sM);
   const double kapO = (double)a.kappa[bO];
+  const double ikM = 1.0 / kapM, ikO = 1.0 / kapO;
   double epsM[6], epsO[6], etaM[6], etaO[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -240,8 +298,8 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
       em += rc.emis[s][c] * epsM[c];
       eo += rc.emis[s][c] * epsO[c];
     }
-    SM[s] = em / kapM;
-    SO[s] = eo / kapO;
+    SM[s] = em * ikM;
+    SO[s] = eo * ikO;
   }
   const double tau0M = 0.5 * (kapM + kapO) * dsM;   // line-centre tau_MO
 
@@ -253,6 +311,7 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
                                     dsP * rc.sy * a.inv_dy);
     const size_t bP = (size_t)a.kP * a.np;
     const double kapP = bil(a.kappa + bP, sP);
+    const double ikP = 1.0 / kapP;
     double epsP[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) epsP[c] = bil(a.emis + c * N + bP, sP);
@@ -263,7 +322,7 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
       double ep = 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) ep += rc.emis[s][c] * epsP[c];
-      cM[s] = besser_cm(SM[s], SO[s], ep / kapP, ratio);
+      cM[s] = besser_cm(SM[s], SO[s], ep * ikP, ratio);
     }
     lamfac = 1.0;
   } else {
@@ -274,10 +333,10 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
   }
 
   // frequency-independent pieces in the sweep precision
-  const T eMv[3] = {(T)(etaM[0] / kapM), (T)(etaM[1] / kapM), (T)(etaM[2] / kapM)};
-  const T rMv[3] = {(T)(etaM[3] / kapM), (T)(etaM[4] / kapM), (T)(etaM[5] / kapM)};
-  const T eOv[3] = {(T)(etaO[0] / kapO), (T)(etaO[1] / kapO), (T)(etaO[2] / kapO)};
-  const T rOv[3] = {(T)(etaO[3] / kapO), (T)(etaO[4] / kapO), (T)(etaO[5] / kapO)};
+  const T eMv[3] = {(T)(etaM[0] * ikM), (T)(etaM[1] * ikM), (T)(etaM[2] * ikM)};
+  const T rMv[3] = {(T)(etaM[3] * ikM), (T)(etaM[4] * ikM), (T)(etaM[5] * ikM)};
+  const T eOv[3] = {(T)(etaO[0] * ikO), (T)(etaO[1] * ikO), (T)(etaO[2] * ikO)};
+  const T rOv[3] = {(T)(etaO[3] * ikO), (T)(etaO[4] * ikO), (T)(etaO[5] * ikO)};
   T SMt[4], SOt[4], cMt[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -291,45 +350,62 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
 
   const size_t fstride = (size_t)a.np * 4;
   const T* ip = a.iprev ? a.iprev + (size_t)rb * a.nfreq * fstride : nullptr;
-  T* op = a.inext + (size_t)rb * a.nfreq * fstride + (size_t)p * 4;
+  T* op = a.inext + (size_t)rb * a.nfreq * fstride + (size_t)pp * 4;
   double jacc0 = 0.0, jacc1 = 0.0, jacc2 = 0.0, jacc3 = 0.0, lacc = 0.0;
 
-  for (int f = 0; f < a.nfreq; ++f) {
-    const T tau = tau0 * a.phi[f];
-    const Coefs<T> cf = coefficients(tau);
+  if (!active) return;   // no barrier follows
+
+  // one update (Eq. fsbez solved with Eq. kappa) at frequency f from the upwind
+  // corner values v (or the boundary value when there is no upwind plane)
+  auto update = [&](int f, const T (&v)[4][4]) {
     T IM[4];
     if (ip) {
-      const T* q = ip + (size_t)f * fstride;
-      T v00[4], v10[4], v01[4], v11[4];
-      load4(q + 4 * (size_t)sM.i00, v00);
-      load4(q + 4 * (size_t)sM.i10, v10);
-      load4(q + 4 * (size_t)sM.i01, v01);
-      load4(q + 4 * (size_t)sM.i11, v11);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) IM[s] = w00 * v00[s] + w10 * v10[s] + w01 * v01[s] + w11 * v11[s];
+      for (int s = 0; s < 4; ++s) IM[s] = w00 * v[0][s] + w10 * v[1][s] + w01 * v[2][s] + w11 * v[3][s];
     } else {
       IM[0] = a.ibound;
       IM[1] = IM[2] = IM[3] = T(0);
     }
-    // Eq. fsbez right-hand side
+    const T tau = tau0 * s_phi[f];
+    const Coefs<T> cf = coefficients(tau);
     T KI[4];
     kprime_apply(eMv, rMv, IM, KI);
     T b[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
       b[s] = cf.e * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
-    // Eq. kappa: (1 + psi'_O K'_O) I_O = b
     const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
     const T ro[3] = {cf.psiO * rOv[0], cf.psiO * rOv[1], cf.psiO * rOv[2]};
     T x[4];
     solve_stokes(eo, ro, b, x);
     store4(op + (size_t)f * fstride, x);
-    const double W = a.wn[f];
+    const double W = s_wn[f];
     jacc0 += W * (double)x[0];
     jacc1 += W * (double)x[1];
     jacc2 += W * (double)x[2];
     jacc3 += W * (double)x[3];
     lacc += W * (double)(cf.omO + lf * cf.omC);
+  };
+
+  if (SweepTraits<T>::kPrefetch) {
+    // two register sets for the upwind values: the loads of frequency f + 1 are in
+    // flight while frequency f is computed
+    T va[4][4] = {}, vb[4][4] = {};
+    if (ip) load_upwind(ip, sM, va);
+    for (int f = 0; f < a.nfreq; f += 2) {
+      const bool has1 = f + 1 < a.nfreq;
+      if (ip && has1) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vb);
+      update(f, va);
+      if (!has1) break;
+      if (ip && f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, va);
+      update(f + 1, vb);
+    }
+  } else {
+    T v[4][4] = {};
+    for (int f = 0; f < a.nfreq; ++f) {
+      if (ip) load_upwind(ip + (size_t)f * fstride, sM, v);
+      update(f, v);
+    }
   }
   if (a.jpart) {
     double* jp = a.jpart + (size_t)rb * 5 * a.np + p;

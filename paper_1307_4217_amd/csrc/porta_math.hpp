@@ -22,6 +22,17 @@ __host__ __device__ inline float exp_neg(float t) {
 }
 __host__ __device__ inline double exp_neg(double t) { return exp(-t); }
 
+// Reciprocal: the FP32 form is the hardware v_rcp_f32 (1 ulp), the FP64 form
+// an IEEE division.
+__host__ __device__ inline float recip(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ inline double recip(double x) { return 1.0 / x; }
+
 // ---------------------------------------------------------------------------
 // Coefficients of Eq. fsbez (Sect. 3.3):
 //   e = exp(-tau), psi'_M, psi'_O (linear K'I), omega_M, omega_O, omega_C
@@ -77,7 +88,7 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
     c.omO = series(tau, kOO);
     c.omC = series(tau, kOC);
   } else {
-    const float it = 1.0f / tau, it2 = it * it;
+    const float it = recip(tau), it2 = it * it;
     const float g = c.e + tau - 1.0f;               // e + tau - 1
     c.psiO = g * it;
     c.psiM = (1.0f - c.e * (1.0f + tau)) * it;
@@ -163,14 +174,14 @@ __host__ __device__ inline void binv(const T y[3], const T r[3], T inv_den, T ou
 
 template <class T>
 __host__ __device__ inline void solve_stokes(const T e[3], const T r[3], const T b[4], T x[4]) {
-  const T inv_den = T(1) / (T(1) + r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const T inv_den = recip(T(1) + r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   const T c[3] = {b[1] - b[0] * e[0], b[2] - b[0] * e[1], b[3] - b[0] * e[2]};
   T u[3], v[3];
   binv(c, r, inv_den, u);
   binv(e, r, inv_den, v);
   const T eu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
   const T ev = e[0] * v[0] + e[1] * v[1] + e[2] * v[2];
-  const T f = eu / (T(1) - ev);
+  const T f = eu * recip(T(1) - ev);
   x[1] = u[0] + f * v[0];
   x[2] = u[1] + f * v[1];
   x[3] = u[2] + f * v[2];

@@ -43,7 +43,7 @@ class Atom(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32)]
+    _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32)]
 
 
 class PortaError(RuntimeError):
@@ -140,8 +140,8 @@ class HostGrid:
                    quad.phi, quad.wfreq)
 
 
-def options(ray_batch=0, block=0):
-    return Options(int(ray_batch), int(block))
+def options(ray_batch=0, block=0, xcd_remap=-1):
+    return Options(int(ray_batch), int(block), int(xcd_remap))
 
 
 def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:
