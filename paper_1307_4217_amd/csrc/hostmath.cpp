@@ -57,4 +57,18 @@ void hm_hanle_solve(double a, double h, double bx, double by, double bz, const d
   for (int i = 0; i < 5; ++i) x5[i] = b[i];
 }
 
+double hm_besser_cm_grad(double yM, double yO, double yP, double ratio, double* d4) {
+  return porta::besser_cm_grad(yM, yO, yP, ratio, d4);
+}
+
+double hm_coef_tau_grad_f64(double tau, const double* g6) {
+  const porta::Coefs<double> c = porta::coefficients(tau);
+  return porta::coef_tau_grad(c, tau, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
+}
+
+float hm_coef_tau_grad_f32(float tau, const float* g6) {
+  const porta::Coefs<float> c = porta::coefficients(tau);
+  return porta::coef_tau_grad(c, tau, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
+}
+
 }  // extern "C"

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "../../include/porta.h"
+#include "porta_adjoint.hpp"
 #include "porta_kernels.hpp"
 
 namespace {
@@ -117,7 +118,10 @@ struct Layout {
   size_t end_tables;
   size_t stateA, stateB;   // sweep plane states
   size_t jpart;
-  size_t adj;              // adjoint region (see porta_adjoint.hpp)
+  // adjoint: checkpoints, recompute slots, Lambda ping-pong, per-ray partials, gradient
+  size_t ck, slots, lamA, lamB, go, gm, gp, grad;
+  size_t plane;            // bytes of one plane state of a ray batch
+  int nck, nslot;
   size_t total;
 };
 
@@ -153,11 +157,36 @@ Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const po
   return L;
 }
 
-// Adjoint workspace (filled in with the adjoint kernels).
+// Adjoint: floor((nz-1)/C) checkpoint planes (every C-th plane), C-1 slots for
+// the planes recomputed between two checkpoints, two planes of Lambda, the
+// per-(node, ray) partials of one plane and the FP64 gradient accumulator.
 Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int stride,
                       const porta_options* o) {
-  (void)stride;
-  return sweep_layout(g, q, prec, o);
+  Layout L = tables_layout(q, prec);
+  const size_t np = (size_t)g->nx * g->ny, N = np * g->nz;
+  const size_t nrb = (size_t)ray_batch(q, o);
+  L.plane = nrb * q->nfreq * np * 4 * elem(prec);
+  L.nck = (g->nz - 1) / stride;
+  L.nslot = stride - 1;
+  size_t off = L.end_tables;
+  L.ck = off;
+  off = align_up(off + (size_t)L.nck * L.plane);
+  L.slots = off;
+  off = align_up(off + (size_t)L.nslot * L.plane);
+  L.lamA = off;
+  off = align_up(off + L.plane);
+  L.lamB = off;
+  off = align_up(off + L.plane);
+  L.go = off;
+  off = align_up(off + nrb * 13 * np * sizeof(double));
+  L.gm = off;
+  off = align_up(off + nrb * 13 * np * sizeof(double));
+  L.gp = off;
+  off = align_up(off + nrb * 7 * np * sizeof(double));
+  L.grad = off;
+  off = align_up(off + 13 * N * sizeof(double));
+  L.total = off;
+  return L;
 }
 
 // Upload host doubles through kernel arguments (ordered on the stream).
@@ -280,6 +309,154 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
     }
   }
   return PORTA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the sweep of the upward rays
+// ---------------------------------------------------------------------------
+template <class T>
+int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* f, char* ws,
+                  const Layout& L, int k, const T* prev, T* next, int ray0, int nrb, int block,
+                  hipStream_t st) {
+  const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
+  PlaneArgs<T> a;
+  a.kappa = static_cast<const T*>(f->kappa);
+  a.prop = static_cast<const T*>(f->propmat);
+  a.emis = static_cast<const T*>(f->emis);
+  a.rays = reinterpret_cast<const RayConsts*>(ws + L.rays);
+  a.phi = reinterpret_cast<const T*>(ws + L.phiT);
+  a.wn = reinterpret_cast<const double*>(ws + L.wn);
+  a.iprev = prev;
+  a.inext = next;
+  a.jpart = nullptr;
+  a.jkq = nullptr;
+  a.jpart_prev = nullptr;
+  a.prev_off = 0;
+  a.N = (size_t)np * nz;
+  a.nx = nx;
+  a.ny = ny;
+  a.np = np;
+  a.nfreq = q->nfreq;
+  a.kO = k;
+  a.kM = k - 1;
+  a.kP = (k == nz - 1) ? -1 : k + 1;
+  a.dzM = std::fabs(g->z[k] - g->z[k - 1]);
+  a.dzP = (k == nz - 1) ? 0.0 : std::fabs(g->z[k + 1] - g->z[k]);
+  a.inv_dx = nx / g->lx;
+  a.inv_dy = ny / g->ly;
+  a.ray0 = ray0;
+  a.xcd_remap = 0;
+  a.ibound = (T)f->i_bottom;
+  const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
+  hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block), lds, st,
+                     a);
+  return check_launch("sweep_plane (adjoint recompute)");
+}
+
+template <class T>
+int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
+                 const porta_options* o, const T* seed, int C, T* gk, T* gpm, T* ge, char* ws,
+                 const Layout& L, hipStream_t st) {
+  int rc;
+  if ((rc = prepare_tables<T>(ws, L, q, f->w2, st))) return rc;
+  const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
+  const size_t N = (size_t)np * nz;
+  double* grad = reinterpret_cast<double*>(ws + L.grad);
+  if ((rc = fill(grad, 13 * N, 0.0, st))) return rc;
+  const int nh = q->nmu * q->nchi;
+  const int nrb_max = ray_batch(q, o);
+  const int block = (o && o->block > 0) ? o->block : 256;
+  if (block % 64 != 0 || block > 256) return fail(PORTA_EINVAL, "block must be 64, 128, 192 or 256");
+  const size_t pe = L.plane / sizeof(T);   // elements of one plane state
+  T* ck = reinterpret_cast<T*>(ws + L.ck);
+  T* slots = reinterpret_cast<T*>(ws + L.slots);
+  T* lam[2] = {reinterpret_cast<T*>(ws + L.lamA), reinterpret_cast<T*>(ws + L.lamB)};
+  // forward state of plane k: the boundary (nullptr), a checkpoint, or a recompute slot
+  auto plane = [&](int k) -> T* {
+    if (k == 0) return nullptr;
+    if (k % C == 0) return ck + (size_t)(k / C - 1) * pe;
+    return slots + (size_t)(k % C - 1) * pe;
+  };
+  const size_t lds_adj = (size_t)q->nfreq * sizeof(T);
+  for (int r0 = 0; r0 < nh; r0 += nrb_max) {
+    const int nrb = std::min(nrb_max, nh - r0);
+    // forward pass keeping every C-th plane
+    for (int k = 1; k < nz; ++k)
+      if ((rc = forward_plane<T>(g, q, f, ws, L, k, plane(k - 1), plane(k), r0, nrb, block, st)))
+        return rc;
+    // reverse pass, one segment between checkpoints at a time
+    const T* lam_next = nullptr;
+    int cur = 0;
+    for (int khi = nz - 1; khi >= 1;) {
+      const int s0 = C * ((khi - 1) / C);
+      for (int k = s0 + 1; k <= khi; ++k)
+        if (k % C != 0)
+          if ((rc = forward_plane<T>(g, q, f, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
+                                     st)))
+            return rc;
+      for (int k = khi; k > s0; --k) {
+        AdjArgs<T> a;
+        a.kappa = static_cast<const T*>(f->kappa);
+        a.prop = static_cast<const T*>(f->propmat);
+        a.emis = static_cast<const T*>(f->emis);
+        a.rays = reinterpret_cast<const RayConsts*>(ws + L.rays);
+        a.phi = reinterpret_cast<const T*>(ws + L.phiT);
+        a.iprev = plane(k - 1);
+        a.icur = plane(k);
+        a.lam_next = lam_next;
+        a.seed = seed + (size_t)r0 * q->nfreq * np * 4;
+        a.lam_cur = (k - 1 >= 1) ? lam[cur] : nullptr;
+        a.g_o = reinterpret_cast<double*>(ws + L.go);
+        a.g_m = reinterpret_cast<double*>(ws + L.gm);
+        a.g_p = reinterpret_cast<double*>(ws + L.gp);
+        a.N = N;
+        a.nx = nx;
+        a.ny = ny;
+        a.np = np;
+        a.nfreq = q->nfreq;
+        a.kO = k;
+        a.kM = k - 1;
+        a.kP = (k == nz - 1) ? -1 : k + 1;
+        a.dzM = std::fabs(g->z[k] - g->z[k - 1]);
+        a.dzP = (k == nz - 1) ? 0.0 : std::fabs(g->z[k + 1] - g->z[k]);
+        a.dzN = a.dzP;
+        a.inv_dx = nx / g->lx;
+        a.inv_dy = ny / g->ly;
+        a.ray0 = r0;
+        a.ibound = (T)f->i_bottom;
+        hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
+                           lds_adj, st, a);
+        if ((rc = check_launch("adjoint_plane"))) return rc;
+        GatherArgs b;
+        b.g_o = a.g_o;
+        b.g_m = a.g_m;
+        b.g_p = a.g_p;
+        b.rays = a.rays;
+        b.grad = grad;
+        b.N = N;
+        b.nx = nx;
+        b.ny = ny;
+        b.np = np;
+        b.kO = a.kO;
+        b.kM = a.kM;
+        b.kP = a.kP;
+        b.dzM = a.dzM;
+        b.dzP = a.dzP;
+        b.inv_dx = a.inv_dx;
+        b.inv_dy = a.inv_dy;
+        b.ray0 = r0;
+        b.nrb = nrb;
+        hipLaunchKernelGGL(k_adjoint_gather, dim3((np + 255) / 256), dim3(256), 0, st, b);
+        if ((rc = check_launch("adjoint_gather"))) return rc;
+        lam_next = a.lam_cur;
+        cur ^= 1;
+      }
+      khi = s0;
+    }
+  }
+  const size_t blocks = std::min<size_t>((N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_grad_out<T>, dim3((unsigned)blocks), dim3(256), 0, st, grad, N, gk, gpm, ge);
+  return check_launch("grad_out");
 }
 
 }  // namespace
@@ -449,7 +626,10 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!dl_ditop || !g_kappa || !g_propmat || !g_emis)
     return fail(PORTA_EINVAL, "seed and gradient arrays must not be NULL");
-  if (checkpoint_stride < 1) return fail(PORTA_EINVAL, "checkpoint_stride must be >= 1");
+  if (checkpoint_stride < 1 || checkpoint_stride > grid->nz)
+    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz");
+  if (opts && (opts->ray_batch < 0 || opts->block < 0))
+    return fail(PORTA_EINVAL, "options must be >= 0");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
@@ -457,8 +637,17 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   if (ws_bytes < L.total)
     return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 L.total);
-  return fail(PORTA_EUNSUPPORTED, "adjoint not available yet");
-  (void)stream;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  if (prec == PORTA_F64)
+    return adjoint_impl<double>(grid, quad, fields, opts, static_cast<const double*>(dl_ditop),
+                                checkpoint_stride, static_cast<double*>(g_kappa),
+                                static_cast<double*>(g_propmat), static_cast<double*>(g_emis), ws,
+                                L, st);
+  return adjoint_impl<float>(grid, quad, fields, opts, static_cast<const float*>(dl_ditop),
+                             checkpoint_stride, static_cast<float*>(g_kappa),
+                             static_cast<float*>(g_propmat), static_cast<float*>(g_emis), ws, L,
+                             st);
 }
 
 }  // extern "C"

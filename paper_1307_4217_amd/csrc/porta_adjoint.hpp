@@ -1,0 +1,328 @@
+// porta_adjoint.hpp -- reverse-mode derivative of the sweep of the upward rays
+// for a loss on the Stokes vectors at the top plane.
+//
+// Forward recurrence for node p on plane k (one ray, one frequency):
+//   I_M = sum_ab w_ab I_{k-1}[q_ab(p)]                       (bilinear at M)
+//   b   = (e - psi'_M K'_M) I_M + omega_M S_M + omega_O S_O + omega_C c_M
+//   (1 + psi'_O K'_O) I_O = b                                 (Eqs. fsbez, kappa)
+// with S, K', c_M and tau built from the interpolated transfer coefficients.
+// Going down from the top plane, the adjoint of I on plane k,
+//   lambda_k(q) = sum_ab w_ab Lambda_{k+1}(q - shift_ab)       (transposed stencil),
+// gives lambda_b = (1 + psi'_O K'_O)^-T lambda_k and
+//   Lambda_k = (e - psi'_M K'_M)^T lambda_b,
+// the adjoint of the interpolated upwind vector, which the next plane down
+// gathers again.  The frequency loop accumulates the partials of the
+// frequency-independent quantities (tau_MO at line centre, S_M, S_O, c_M, K'_M,
+// K'_O); they are then propagated through the BESSER control point, the
+// ratio of optical paths and the divisions by eta_I to the coefficients at O
+// (written directly) and at M and P (gathered through transposed stencils).
+#pragma once
+
+#include "porta_kernels.hpp"
+
+namespace porta {
+
+template <class T>
+struct AdjArgs {
+  const T* kappa;
+  const T* prop;
+  const T* emis;
+  const RayConsts* rays;
+  const T* phi;
+  const T* iprev;      // forward state of plane kM, or nullptr for the boundary plane
+  const T* icur;       // forward state of plane kO
+  const T* lam_next;   // Lambda of plane kO + 1, or nullptr when kO is the top plane
+  const T* seed;       // dL/dI on the top plane for this batch (used when lam_next is null)
+  T* lam_cur;          // Lambda of plane kO, or nullptr when plane kM is the boundary
+  double* g_o;         // [ray in batch][13][node]: coefficients at O
+  double* g_m;         // [ray in batch][13][node]: coefficients interpolated at M
+  double* g_p;         // [ray in batch][7][node]:  eta_I and eps interpolated at P
+  size_t N;
+  int nx, ny, np, nfreq;
+  int kO, kM, kP;
+  double dzM, dzP, dzN;   // dzN = |z_{kO+1} - z_kO| (plane above), 0 on the top plane
+  double inv_dx, inv_dy;
+  int ray0;
+  T ibound;
+};
+
+// Partials of b's K' I term: dL/d(e_Q, e_U, e_V, r_Q, r_U, r_V) of -psi lambda^T K' x.
+template <class T>
+__device__ inline void kprime_outer(T psi, const T l[4], const T x[4], double g[6]) {
+  g[0] -= (double)(psi * (l[0] * x[1] + l[1] * x[0]));
+  g[1] -= (double)(psi * (l[0] * x[2] + l[2] * x[0]));
+  g[2] -= (double)(psi * (l[0] * x[3] + l[3] * x[0]));
+  g[3] -= (double)(psi * (l[2] * x[3] - l[3] * x[2]));
+  g[4] -= (double)(psi * (l[3] * x[1] - l[1] * x[3]));
+  g[5] -= (double)(psi * (l[1] * x[2] - l[2] * x[1]));
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_adjoint_plane(const AdjArgs<T> a) {
+  extern __shared__ double s_tab[];
+  T* s_phi = reinterpret_cast<T*>(s_tab);
+  for (int t = threadIdx.x; t < a.nfreq; t += blockDim.x) s_phi[t] = a.phi[t];
+  __syncthreads();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const int rb = blockIdx.y;
+  const RayConsts& rc = a.rays[a.ray0 + rb];
+  PointSetup ps;
+  setup_point(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM, a.dzP,
+              a.inv_dx, a.inv_dy, rc, p, ps);
+  const int i = p % a.nx, j = p / a.nx;
+  const double inv_mu = 1.0 / fabs(rc.mu);
+  // nodes of the plane above whose upwind stencil contains p
+  Stencil tN{};
+  if (a.lam_next) {
+    const double dsN = a.dzN * inv_mu;
+    tN = make_tstencil(i, j, a.nx, a.ny, -dsN * rc.sx * a.inv_dx, -dsN * rc.sy * a.inv_dy);
+  }
+  const T eMv[3] = {(T)(ps.etaM[0] * ps.ikM), (T)(ps.etaM[1] * ps.ikM), (T)(ps.etaM[2] * ps.ikM)};
+  const T rMv[3] = {(T)(ps.etaM[3] * ps.ikM), (T)(ps.etaM[4] * ps.ikM), (T)(ps.etaM[5] * ps.ikM)};
+  const T eOv[3] = {(T)(ps.etaO[0] * ps.ikO), (T)(ps.etaO[1] * ps.ikO), (T)(ps.etaO[2] * ps.ikO)};
+  const T rOv[3] = {(T)(ps.etaO[3] * ps.ikO), (T)(ps.etaO[4] * ps.ikO), (T)(ps.etaO[5] * ps.ikO)};
+  const T rMn[3] = {-rMv[0], -rMv[1], -rMv[2]};
+  T SMt[4], SOt[4], cMt[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    SMt[s] = (T)ps.SM[s];
+    SOt[s] = (T)ps.SO[s];
+    cMt[s] = (T)ps.cM[s];
+  }
+  const T tau0 = (T)ps.tau0M;
+  const T w00 = (T)ps.sM.w00, w10 = (T)ps.sM.w10, w01 = (T)ps.sM.w01, w11 = (T)ps.sM.w11;
+  const T n00 = (T)tN.w00, n10 = (T)tN.w10, n01 = (T)tN.w01, n11 = (T)tN.w11;
+
+  const size_t fstride = (size_t)a.np * 4;
+  const size_t rstride = (size_t)a.nfreq * fstride;
+  const T* ip = a.iprev ? a.iprev + rb * rstride : nullptr;
+  const T* cp = a.icur + rb * rstride + (size_t)p * 4;
+  const T* lp = a.lam_next ? a.lam_next + rb * rstride : nullptr;
+  const T* sp = a.seed + rb * rstride + (size_t)p * 4;
+  T* lo = a.lam_cur ? a.lam_cur + rb * rstride + (size_t)p * 4 : nullptr;
+
+  double gT = 0.0, gSM[4] = {0, 0, 0, 0}, gSO[4] = {0, 0, 0, 0}, gCM[4] = {0, 0, 0, 0};
+  double gKM[6] = {0, 0, 0, 0, 0, 0}, gKO[6] = {0, 0, 0, 0, 0, 0};
+  for (int f = 0; f < a.nfreq; ++f) {
+    const size_t fo = (size_t)f * fstride;
+    T lam[4];
+    if (lp) {
+      T v00[4], v10[4], v01[4], v11[4];
+      load4(lp + fo + 4 * (size_t)tN.i00, v00);
+      load4(lp + fo + 4 * (size_t)tN.i10, v10);
+      load4(lp + fo + 4 * (size_t)tN.i01, v01);
+      load4(lp + fo + 4 * (size_t)tN.i11, v11);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) lam[s] = n00 * v00[s] + n10 * v10[s] + n01 * v01[s] + n11 * v11[s];
+    } else {
+      load4(sp + fo, lam);
+    }
+    T IM[4];
+    if (ip) {
+      T v00[4], v10[4], v01[4], v11[4];
+      load4(ip + fo + 4 * (size_t)ps.sM.i00, v00);
+      load4(ip + fo + 4 * (size_t)ps.sM.i10, v10);
+      load4(ip + fo + 4 * (size_t)ps.sM.i01, v01);
+      load4(ip + fo + 4 * (size_t)ps.sM.i11, v11);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) IM[s] = w00 * v00[s] + w10 * v10[s] + w01 * v01[s] + w11 * v11[s];
+    } else {
+      IM[0] = a.ibound;
+      IM[1] = IM[2] = IM[3] = T(0);
+    }
+    T IO[4];
+    load4(cp + fo, IO);
+    const T ph = s_phi[f];
+    const T tau = tau0 * ph;
+    const Coefs<T> cf = coefficients(tau);
+    // lambda_b = (1 + psi'_O K'_O)^-T lambda
+    const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
+    const T ron[3] = {-cf.psiO * rOv[0], -cf.psiO * rOv[1], -cf.psiO * rOv[2]};
+    T lb[4];
+    solve_stokes(eo, ron, lam, lb);
+    T KIM[4], KIO[4];
+    kprime_apply(eMv, rMv, IM, KIM);
+    kprime_apply(eOv, rOv, IO, KIO);
+    T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      gE += lb[s] * IM[s];
+      gPM -= lb[s] * KIM[s];
+      gPO -= lb[s] * KIO[s];
+      gOM += lb[s] * SMt[s];
+      gOO += lb[s] * SOt[s];
+      gOC += lb[s] * cMt[s];
+      gSM[s] += (double)(cf.omM * lb[s]);
+      gSO[s] += (double)(cf.omO * lb[s]);
+      gCM[s] += (double)(cf.omC * lb[s]);
+    }
+    gT += (double)(ph * coef_tau_grad(cf, tau, gE, gPM, gPO, gOM, gOO, gOC));
+    kprime_outer(cf.psiM, lb, IM, gKM);
+    kprime_outer(cf.psiO, lb, IO, gKO);
+    if (lo) {
+      // Lambda = (e - psi'_M K'_M)^T lambda_b
+      T KT[4];
+      kprime_apply(eMv, rMn, lb, KT);
+      T out[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[s] = cf.e * lb[s] - cf.psiM * KT[s];
+      store4(lo + fo, out);
+    }
+  }
+
+  // control points (branch of the forward evaluation)
+  double gSP[4] = {0, 0, 0, 0}, gR = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (ps.hasP) {
+      double d[4];
+      besser_cm_grad(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio, d);
+      gSM[s] += gCM[s] * d[0];
+      gSO[s] += gCM[s] * d[1];
+      gSP[s] += gCM[s] * d[2];
+      gR += gCM[s] * d[3];
+    } else {
+      gSM[s] += 0.5 * gCM[s];
+      gSO[s] += 0.5 * gCM[s];
+    }
+  }
+  // ratio = tau0M / tau0P, tau0M = (kapM + kapO) dsM / 2, tau0P = (kapO + kapP) dsP / 2
+  double gT0P = 0.0;
+  if (ps.hasP) {
+    gT += gR / ps.tau0P;
+    gT0P = -gR * ps.ratio / ps.tau0P;
+  }
+  double gkM = 0.5 * ps.dsM * gT;
+  double gkO = 0.5 * ps.dsM * gT + 0.5 * ps.dsP * gT0P;
+  double gkP = 0.5 * ps.dsP * gT0P;
+  // S_X = (emission table) eps_X / kap_X
+  double geM[6], geO[6], geP[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double m = 0.0, o = 0.0, q = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      m += gSM[s] * rc.emis[s][c];
+      o += gSO[s] * rc.emis[s][c];
+      q += gSP[s] * rc.emis[s][c];
+    }
+    geM[c] = m * ps.ikM;
+    geO[c] = o * ps.ikO;
+    geP[c] = q * ps.ikP;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    gkM -= gSM[s] * ps.SM[s] * ps.ikM;
+    gkO -= gSO[s] * ps.SO[s] * ps.ikO;
+    gkP -= gSP[s] * ps.SP[s] * ps.ikP;
+  }
+  // K'_X = eta_X / kap_X
+  double ghM[6], ghO[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    ghM[c] = gKM[c] * ps.ikM;
+    ghO[c] = gKO[c] * ps.ikO;
+    gkM -= gKM[c] * ps.etaM[c] * ps.ikM * ps.ikM;
+    gkO -= gKO[c] * ps.etaO[c] * ps.ikO * ps.ikO;
+  }
+  double* go = a.g_o + (size_t)rb * 13 * a.np + p;
+  double* gm = a.g_m + (size_t)rb * 13 * a.np + p;
+  const size_t np = (size_t)a.np;
+  go[0] = gkO;
+  gm[0] = gkM;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    go[(1 + c) * np] = ghO[c];
+    gm[(1 + c) * np] = ghM[c];
+    go[(7 + c) * np] = geO[c];
+    gm[(7 + c) * np] = geM[c];
+  }
+  if (ps.hasP) {
+    double* gp = a.g_p + (size_t)rb * 7 * a.np + p;
+    gp[0] = gkP;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gp[(1 + c) * np] = geP[c];
+  }
+}
+
+// Gather the per-(node, ray) partials of one plane onto the coefficient
+// gradients of planes kM, kO and kP (fixed ray order, one thread per node).
+struct GatherArgs {
+  const double* g_o;
+  const double* g_m;
+  const double* g_p;
+  const RayConsts* rays;
+  double* grad;       // [13][N]: kappa, propmat[6], emis[6]
+  size_t N;
+  int nx, ny, np;
+  int kO, kM, kP;
+  double dzM, dzP, inv_dx, inv_dy;
+  int ray0, nrb;
+};
+
+__global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.np) return;
+  const int i = q % a.nx, j = q / a.nx;
+  const size_t np = (size_t)a.np;
+  double accO[13], accM[13], accP[7];
+#pragma unroll
+  for (int c = 0; c < 13; ++c) accO[c] = accM[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) accP[c] = 0.0;
+  for (int rb = 0; rb < a.nrb; ++rb) {
+    const RayConsts& rc = a.rays[a.ray0 + rb];
+    const double inv_mu = 1.0 / fabs(rc.mu);
+    const double dsM = a.dzM * inv_mu;
+    const Stencil tM = make_tstencil(i, j, a.nx, a.ny, -dsM * rc.sx * a.inv_dx,
+                                     -dsM * rc.sy * a.inv_dy);
+    const double* go = a.g_o + (size_t)rb * 13 * np;
+    const double* gm = a.g_m + (size_t)rb * 13 * np;
+#pragma unroll
+    for (int c = 0; c < 13; ++c) {
+      const double* g = gm + c * np;
+      accO[c] += go[c * np + q];
+      accM[c] += tM.w00 * g[tM.i00] + tM.w10 * g[tM.i10] + tM.w01 * g[tM.i01] + tM.w11 * g[tM.i11];
+    }
+    if (a.kP >= 0) {
+      const double dsP = a.dzP * inv_mu;
+      const Stencil tP = make_tstencil(i, j, a.nx, a.ny, dsP * rc.sx * a.inv_dx,
+                                       dsP * rc.sy * a.inv_dy);
+      const double* gp = a.g_p + (size_t)rb * 7 * np;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        const double* g = gp + c * np;
+        accP[c] += tP.w00 * g[tP.i00] + tP.w10 * g[tP.i10] + tP.w01 * g[tP.i01] + tP.w11 * g[tP.i11];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 13; ++c) {
+    a.grad[c * a.N + (size_t)a.kO * np + q] += accO[c];
+    a.grad[c * a.N + (size_t)a.kM * np + q] += accM[c];
+  }
+  if (a.kP >= 0) {
+    a.grad[(size_t)a.kP * np + q] += accP[0];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.grad[(7 + c) * a.N + (size_t)a.kP * np + q] += accP[1 + c];
+  }
+}
+
+// Add the FP64 gradient accumulator to the caller's arrays.
+template <class T>
+__global__ void __launch_bounds__(256) k_grad_out(const double* __restrict__ grad, size_t N,
+                                                  T* __restrict__ gk, T* __restrict__ gp,
+                                                  T* __restrict__ ge) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (size_t)gridDim.x * blockDim.x) {
+    gk[p] += (T)grad[p];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      gp[c * N + p] += (T)grad[(1 + c) * N + p];
+      ge[c * N + p] += (T)grad[(7 + c) * N + p];
+    }
+  }
+}
+
+}  // namespace porta

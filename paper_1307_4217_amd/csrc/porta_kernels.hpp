@@ -125,6 +125,107 @@ __device__ inline double bil(const T* __restrict__ f, const Stencil& s) {
          s.w11 * (double)f[s.i11];
 }
 
+// Transposed stencil: the nodes (i', j') whose stencil for the same displacement
+// (u, v) contains node (i, j), with the weight that node received.  Used by the
+// adjoint to turn the scatter of the forward interpolation into a gather.
+__device__ inline Stencil make_tstencil(int i, int j, int nx, int ny, double u, double v) {
+  u -= nx * floor(u / nx);
+  v -= ny * floor(v / ny);
+  const double fu = floor(u), fv = floor(v);
+  const double tx = u - fu, ty = v - fv;
+  const int i0 = wrapi(i - (int)fu, nx), i1 = (i0 == 0) ? nx - 1 : i0 - 1;
+  const int j0 = wrapi(j - (int)fv, ny), j1 = (j0 == 0) ? ny - 1 : j0 - 1;
+  Stencil s;
+  s.i00 = j0 * nx + i0;
+  s.i10 = j0 * nx + i1;
+  s.i01 = j1 * nx + i0;
+  s.i11 = j1 * nx + i1;
+  s.w00 = (1.0 - tx) * (1.0 - ty);
+  s.w10 = tx * (1.0 - ty);
+  s.w01 = (1.0 - tx) * ty;
+  s.w11 = tx * ty;
+  return s;
+}
+
+// Frequency-independent part of the update of node p on plane kO for one ray:
+// transfer coefficients interpolated at M (plane kM) and P (plane kP, if any),
+// source vectors S = eps/eta_I at M, O, P, K' at M and O, the line-centre
+// optical paths and the BESSER control points (Sect. 3.1-3.3).
+struct PointSetup {
+  Stencil sM;
+  double dsM, dsP;
+  double kapM, kapO, kapP, ikM, ikO, ikP;
+  double epsM[6], epsO[6], epsP[6], etaM[6], etaO[6];
+  double SM[4], SO[4], SP[4], cM[4];
+  double tau0M, tau0P, ratio;
+  bool hasP;
+};
+
+template <class T>
+__device__ inline void setup_point(const T* __restrict__ kappa, const T* __restrict__ prop,
+                                   const T* __restrict__ emis, size_t N, int nx, int ny, int np,
+                                   int kO, int kM, int kP, double dzM, double dzP, double inv_dx,
+                                   double inv_dy, const RayConsts& rc, int p, PointSetup& ps) {
+  const int i = p % nx, j = p / nx;
+  const double inv_mu = 1.0 / fabs(rc.mu);
+  ps.dsM = dzM * inv_mu;
+  ps.sM = make_stencil(i, j, nx, ny, -ps.dsM * rc.sx * inv_dx, -ps.dsM * rc.sy * inv_dy);
+  const size_t bM = (size_t)kM * np, bO = (size_t)kO * np + p;
+  ps.kapM = bil(kappa + bM, ps.sM);
+  ps.kapO = (double)kappa[bO];
+  ps.ikM = 1.0 / ps.kapM;
+  ps.ikO = 1.0 / ps.kapO;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    ps.epsM[c] = bil(emis + c * N + bM, ps.sM);
+    ps.etaM[c] = bil(prop + c * N + bM, ps.sM);
+    ps.epsO[c] = (double)emis[c * N + bO];
+    ps.etaO[c] = (double)prop[c * N + bO];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double em = 0.0, eo = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      em += rc.emis[s][c] * ps.epsM[c];
+      eo += rc.emis[s][c] * ps.epsO[c];
+    }
+    ps.SM[s] = em * ps.ikM;
+    ps.SO[s] = eo * ps.ikO;
+  }
+  ps.tau0M = 0.5 * (ps.kapM + ps.kapO) * ps.dsM;   // line-centre tau_MO
+  ps.hasP = kP >= 0;
+  if (ps.hasP) {
+    ps.dsP = dzP * inv_mu;
+    const Stencil sP = make_stencil(i, j, nx, ny, ps.dsP * rc.sx * inv_dx, ps.dsP * rc.sy * inv_dy);
+    const size_t bP = (size_t)kP * np;
+    ps.kapP = bil(kappa + bP, sP);
+    ps.ikP = 1.0 / ps.kapP;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ps.epsP[c] = bil(emis + c * N + bP, sP);
+    ps.tau0P = 0.5 * (ps.kapO + ps.kapP) * ps.dsP;
+    ps.ratio = ps.tau0M / ps.tau0P;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double ep = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ep += rc.emis[s][c] * ps.epsP[c];
+      ps.SP[s] = ep * ps.ikP;
+      ps.cM[s] = besser_cm(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio);
+    }
+  } else {
+    // no downwind plane: linear control point
+    ps.dsP = ps.kapP = ps.ikP = ps.tau0P = ps.ratio = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      ps.SP[s] = 0.0;
+      ps.cM[s] = 0.5 * (ps.SM[s] + ps.SO[s]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ps.epsP[c] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Add the frequency-integrated Stokes vectors of a batch of rays on one plane
 // to J^K_Q (Eq. 1) and Lbar, in a fixed ray order (no atomics).  On the
@@ -269,68 +370,18 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
     jreduce_point(a.jkq, a.jpart_prev, a.rays, a.ray0, gridDim.y, a.np, a.N, a.prev_off, p,
                   a.jpart_prev == nullptr, (double)a.ibound);
   const RayConsts& rc = a.rays[a.ray0 + rb];
-  const int i = pp % a.nx, j = pp / a.nx;
-  const double inv_mu = 1.0 / fabs(rc.mu);
-  const size_t N = a.N;
-
-  // upwind point M on plane kM (Sect. 3.1)
-  const double dsM = a.dzM * inv_mu;
-  const Stencil sM = make_stencil(i, j, a.nx, a.ny, -dsM * rc.sx * a.inv_dx,
-                                  -dsM * rc.sy * a.inv_dy);
-  const size_t bM = (size_t)a.kM * a.np, bO = (size_t)a.kO * a.np + pp;
-  const double kapM = bil(a.kappa + bM, sM);
-  const double kapO = (double)a.kappa[bO];
-  const double ikM = 1.0 / kapM, ikO = 1.0 / kapO;
-  double epsM[6], epsO[6], etaM[6], etaO[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    epsM[c] = bil(a.emis + c * N + bM, sM);
-    etaM[c] = bil(a.prop + c * N + bM, sM);
-    epsO[c] = (double)a.emis[c * N + bO];
-    etaO[c] = (double)a.prop[c * N + bO];
-  }
-  double SM[4], SO[4], cM[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    double em = 0.0, eo = 0.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      em += rc.emis[s][c] * epsM[c];
-      eo += rc.emis[s][c] * epsO[c];
-    }
-    SM[s] = em * ikM;
-    SO[s] = eo * ikO;
-  }
-  const double tau0M = 0.5 * (kapM + kapO) * dsM;   // line-centre tau_MO
-
-  // downwind point P and the BESSER control points (Sect. 3.2)
-  double lamfac;
-  if (a.kP >= 0) {
-    const double dsP = a.dzP * inv_mu;
-    const Stencil sP = make_stencil(i, j, a.nx, a.ny, dsP * rc.sx * a.inv_dx,
-                                    dsP * rc.sy * a.inv_dy);
-    const size_t bP = (size_t)a.kP * a.np;
-    const double kapP = bil(a.kappa + bP, sP);
-    const double ikP = 1.0 / kapP;
-    double epsP[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) epsP[c] = bil(a.emis + c * N + bP, sP);
-    const double tau0P = 0.5 * (kapO + kapP) * dsP;
-    const double ratio = tau0M / tau0P;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double ep = 0.0;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) ep += rc.emis[s][c] * epsP[c];
-      cM[s] = besser_cm(SM[s], SO[s], ep * ikP, ratio);
-    }
-    lamfac = 1.0;
-  } else {
-    // no downwind plane: linear control point
-#pragma unroll
-    for (int s = 0; s < 4; ++s) cM[s] = 0.5 * (SM[s] + SO[s]);
-    lamfac = 0.5;
-  }
+  PointSetup ps;
+  setup_point(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM, a.dzP,
+              a.inv_dx, a.inv_dy, rc, pp, ps);
+  const Stencil& sM = ps.sM;
+  const double ikM = ps.ikM, ikO = ps.ikO;
+  const double* etaM = ps.etaM;
+  const double* etaO = ps.etaO;
+  const double* SM = ps.SM;
+  const double* SO = ps.SO;
+  const double* cM = ps.cM;
+  const double tau0M = ps.tau0M;
+  const double lamfac = ps.hasP ? 1.0 : 0.5;
 
   // frequency-independent pieces in the sweep precision
   const T eMv[3] = {(T)(etaM[0] * ikM), (T)(etaM[1] * ikM), (T)(etaM[2] * ikM)};

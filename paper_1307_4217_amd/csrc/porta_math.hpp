@@ -155,6 +155,50 @@ __host__ __device__ inline double besser_cm(double yM, double yO, double yP, dou
   return cM;
 }
 
+// BESSER control point together with its partial derivatives
+// d = (dc/dy_M, dc/dy_O, dc/dy_P, dc/dr), following the same branches.
+__host__ __device__ inline double besser_cm_grad(double yM, double yO, double yP, double r,
+                                                 double d[4]) {
+  const double dM = yO - yM, dP = yP - yO;
+  d[0] = d[1] = d[2] = d[3] = 0.0;
+  if (dM * dP <= 0.0) {
+    d[1] = 1.0;
+    return yO;
+  }
+  const double inv = 0.5 / (1.0 + r);
+  const double cM = yO - (r * r * dP + dM) * inv;
+  if ((cM - yM) * (cM - yO) > 0.0) {
+    d[0] = 1.0;
+    return yM;
+  }
+  const double cP = yO + (r * dP + dM / r) * inv;
+  if ((cP - yO) * (cP - yP) > 0.0) {
+    d[1] = 1.0 + r;
+    d[2] = -r;
+    d[3] = -dP;
+    return yO - r * dP;
+  }
+  d[0] = inv;
+  d[1] = 1.0 - (1.0 - r * r) * inv;
+  d[2] = -r * r * inv;
+  d[3] = -2.0 * (r * r * dP + 2.0 * r * dP - dM) * inv * inv;
+  return cM;
+}
+
+// dL/dtau from the adjoints of the six coefficients, with the derivatives
+// written through the coefficients themselves:
+//   de/dt = -e,                 dpsi'_M/dt = e - psi'_M/t,   dpsi'_O/dt = psi'_M/t,
+//   domega_M/dt = e - 2 omega_M/t,   domega_C/dt = 2 (psi'_M - omega_C)/t,
+//   domega_O/dt = 2 (omega_M + omega_C - psi'_M)/t   (from omega_M+omega_O+omega_C = 1-e).
+template <class T>
+__host__ __device__ inline T coef_tau_grad(const Coefs<T>& c, T tau, T gE, T gPM, T gPO, T gOM,
+                                           T gOO, T gOC) {
+  const T it = recip(tau);
+  const T pmt = c.psiM * it;
+  return -c.e * gE + (c.e - pmt) * gPM + pmt * gPO + (c.e - T(2) * c.omM * it) * gOM +
+         T(2) * (c.omM + c.omC - c.psiM) * it * gOO + T(2) * (c.psiM - c.omC) * it * gOC;
+}
+
 // ---------------------------------------------------------------------------
 // Solve (1 + K') x = b for a Stokes 4-vector, K' with the symmetric
 // dichroism block e = (e_Q, e_U, e_V) and the antisymmetric dispersion block

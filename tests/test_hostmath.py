@@ -134,3 +134,57 @@ def test_hanle_real_system_matches_complex_solve(hm):
         hm.hm_hanle_solve(a, h, *b, p(rhs), p(x))
         np.testing.assert_allclose(x, [S[2].real, S[3].real, S[3].imag, S[4].real, S[4].imag],
                                    rtol=1e-11, atol=1e-13)
+
+
+def test_besser_gradient_matches_finite_differences(hm):
+    hm.hm_besser_cm_grad.argtypes = [C.c_double] * 4 + [_dp]
+    hm.hm_besser_cm_grad.restype = C.c_double
+    rng = np.random.default_rng(5)
+    branches = set()
+    for _ in range(3000):
+        y = rng.normal(size=3)
+        if rng.uniform() < 0.7:
+            y = np.sort(y) * rng.choice([-1, 1])
+        r = float(np.exp(rng.uniform(-3, 3)))
+        d = np.zeros(4)
+        c0 = hm.hm_besser_cm_grad(*y, r, p(d))
+        assert c0 == hm.hm_besser_cm(*y, r)
+        h = 1e-7
+        args = list(y) + [r]
+        fd = []
+        ok = True
+        for k in range(4):
+            ap, am = list(args), list(args)
+            ap[k] += h * max(1.0, abs(args[k]))
+            am[k] -= h * max(1.0, abs(args[k]))
+            cp_, cm_ = hm.hm_besser_cm(*ap), hm.hm_besser_cm(*am)
+            dp_ = np.zeros(4)
+            dm_ = np.zeros(4)
+            hm.hm_besser_cm_grad(*ap, p(dp_))
+            hm.hm_besser_cm_grad(*am, p(dm_))
+            if not (np.allclose(dp_, d) and np.allclose(dm_, d)):
+                ok = False     # a branch boundary lies within the step
+                break
+            fd.append((cp_ - cm_) / (ap[k] - am[k]))
+        if ok:
+            branches.add(tuple(np.round(d, 12) == 0))
+            np.testing.assert_allclose(d, fd, rtol=1e-5, atol=1e-6)
+    assert len(branches) >= 4
+
+
+def test_coefficient_tau_derivatives(hm):
+    hm.hm_coef_tau_grad_f64.argtypes = [C.c_double, _dp]
+    hm.hm_coef_tau_grad_f64.restype = C.c_double
+    hm.hm_coef_tau_grad_f32.argtypes = [C.c_float, _fp]
+    hm.hm_coef_tau_grad_f32.restype = C.c_float
+    for tau in np.logspace(-6, 2, 80):
+        for k in range(6):
+            g = np.zeros(6)
+            g[k] = 1.0
+            got = hm.hm_coef_tau_grad_f64(tau, p(g))
+            h = 1e-5 * tau
+            fd = (coef(hm, tau + h)[k] - coef(hm, tau - h)[k]) / (2 * h)
+            # truncation ~ (h/tau)^2, rounding of the difference ~ ulp(value) / h
+            assert got == pytest.approx(fd, rel=1e-6, abs=4e-16 / h), (tau, k)
+            got32 = hm.hm_coef_tau_grad_f32(np.float32(tau), p(g.astype(np.float32)))
+            assert got32 == pytest.approx(got, rel=2e-4, abs=1e-6), (tau, k)
