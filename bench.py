@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the PORTA hot path on one MI355X.
 
-One step = one Jacobi iteration at the 256x256x128 precision instance
-(160 rays, 101 frequencies): the FP32 short-characteristics BESSER sweep of
-every ray and frequency with the fused FP64 J^K_Q / Lambda* integration,
-followed by the FP64 statistical-equilibrium update that rewrites the
-emissivities for the next iteration.  Inputs are seeded synthetic fields
-already resident in HBM.  Prints one JSON line on stdout.
+One step at the 256x256x128 precision instance (160 rays, 101 frequencies):
+the FP32 short-characteristics BESSER sweep of every ray and frequency with
+the fused FP64 J^K_Q / Lambda* integration, the FP64 statistical-equilibrium
+update that rewrites the emissivities for the next iteration, and the FP32
+reverse-sweep adjoint of an emergent-Stokes loss sum (I_top - target)^2
+(gradients with respect to eta_I, the propagation matrix and the
+emissivities; planes recomputed from checkpoints).  Inputs are seeded
+synthetic fields already resident in HBM.  Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -34,7 +36,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--ray-batch", type=int, default=0)
+    ap.add_argument("--ray-batch", type=int, default=40,
+                    help="rays swept together in the forward sweep and in the adjoint")
+    ap.add_argument("--checkpoint-stride", type=int, default=11)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-fp64-rate", action="store_true",
                     help="skip the extra FP64 sweep used for the FP32-vs-FP64 rate")
@@ -107,7 +112,7 @@ def main():
     hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
     opts = porta.options(ray_batch=args.ray_batch, block=args.block)
-    nrb = args.ray_batch if args.ray_batch > 0 else cfg.nmu * cfg.nchi
+    nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
     nbatches = -(-(cfg.nmu * cfg.nchi) // nrb)
     ws = torch.empty(porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts), dtype=torch.uint8,
                      device=dev)
@@ -116,6 +121,21 @@ def main():
     itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=tdt, device=dev)
     rc = torch.empty((), dtype=torch.float64, device=dev)
     log(f"workspace {ws.numel() / 1e9:.2f} GB, i_top {itop.numel() * elem / 1e9:.2f} GB")
+    adj = not args.no_adjoint
+    if adj:
+        # loss target: emergent Stokes vectors of a seeded perturbed atmosphere
+        tatm = inputs.perturbed_target_atmosphere(atm, seed=5)
+        target = torch.empty_like(itop)
+        porta.fs_sweep(hg, t(tatm.kappa, tdt), t(tatm.propmat, tdt), t(tatm.emis, tdt),
+                       atm.i_bottom, atm.w2, prec=prec, want_jkq=False, i_top=target, opts=opts,
+                       workspace=ws)
+        del tatm
+        ws_adj = torch.empty(porta.workspace_size(hg, prec, porta.WS_ADJOINT,
+                                                  args.checkpoint_stride, opts),
+                             dtype=torch.uint8, device=dev)
+        g_k, g_p, g_e = torch.empty_like(kappa), torch.empty_like(prop), torch.empty_like(emis)
+        seed_buf = torch.empty_like(itop)
+        log(f"adjoint workspace {ws_adj.numel() / 1e9:.2f} GB (stride {args.checkpoint_stride})")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     state = {"s_old": s_a, "s_new": s_b}
@@ -127,17 +147,28 @@ def main():
         del src, dst
 
     def step(times):
-        e0, e1, e2 = ev(), ev(), ev()
-        e0.record()
+        e = [ev() for _ in range(5)]
+        e[0].record()
         porta.fs_sweep(hg, kappa, prop, emis, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
                        i_top=itop, opts=opts, workspace=ws)
-        e1.record()
+        e[1].record()
         porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
                          bhat, kappa=kappa, emis_out=emis, prec=prec, s_new=state["s_new"], rc=rc,
                          workspace=ws_see)
-        e2.record()
+        e[2].record()
+        if adj:
+            # dL/dI_top of L = sum (I_top - target)^2, then the reverse sweep
+            torch.sub(itop, target, out=seed_buf).mul_(2.0)
+            e[3].record()
+            g_k.zero_(), g_p.zero_(), g_e.zero_()
+            porta.fs_adjoint(hg, kappa, prop, emis, atm.i_bottom, seed_buf, atm.w2, prec=prec,
+                             checkpoint_stride=args.checkpoint_stride, g_kappa=g_k,
+                             g_propmat=g_p, g_emis=g_e, opts=opts, workspace=ws_adj)
+        else:
+            e[3].record()
+        e[4].record()
         state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
-        times.append((e0, e1, e2))
+        times.append(e)
 
     for w in range(args.warmup):
         step([])
@@ -149,14 +180,18 @@ def main():
     for k in range(args.steps):
         step(times)
         torch.cuda.synchronize()
-        log(f"step {k + 1}/{args.steps}: sweep {times[-1][0].elapsed_time(times[-1][1]):.1f} ms, "
-            f"SEE {times[-1][1].elapsed_time(times[-1][2]):.2f} ms, R_c {rc.item():.3e}")
+        e = times[-1]
+        log(f"step {k + 1}/{args.steps}: sweep {e[0].elapsed_time(e[1]):.1f} ms, "
+            f"SEE {e[1].elapsed_time(e[2]):.2f} ms, adjoint {e[3].elapsed_time(e[4]):.1f} ms, "
+            f"R_c {rc.item():.3e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in times) / args.steps
-    see_ms = sum(b.elapsed_time(c) for _, b, c in times) / args.steps
+    sweep_ms = sum(e[0].elapsed_time(e[1]) for e in times) / args.steps
+    see_ms = sum(e[1].elapsed_time(e[2]) for e in times) / args.steps
+    adj_ms = sum(e[3].elapsed_time(e[4]) for e in times) / args.steps
     step_ms = wall * 1e3 / args.steps
-    value = cfg.updates * args.steps / wall
+    adj_updates = cfg.npoints * (cfg.nrays // 2) * cfg.nfreq if adj else 0
+    value = (cfg.updates + adj_updates) * args.steps / wall
 
     launches = 2 * (cfg.nz - 1) * nbatches
     lbytes, lupd = sweep_launch_bytes(cfg, nrb, elem)
@@ -169,9 +204,14 @@ def main():
                 "updates_per_launch": lupd}
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
              "sweep_updates_per_s": cfg.updates / (sweep_ms * 1e-3),
-             "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4)}
+             "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4),
+             "adjoint_ms": round(adj_ms, 2),
+             "adjoint_updates_per_s": (adj_updates / (adj_ms * 1e-3)) if adj else None,
+             "adjoint_over_forward_time": round(adj_ms / sweep_ms, 3) if adj else None}
     if not args.no_fp64_rate and prec == porta.F32:
         del ws
+        if adj:
+            del ws_adj
         torch.cuda.empty_cache()
         k64, p64, e64 = t(atm.kappa, torch.float64), t(atm.propmat, torch.float64), t(
             atm.emis, torch.float64)
@@ -199,7 +239,7 @@ def main():
         cpu = cpu_baseline(cfg, atm, q, args.cpu_pairs)
         log(f"CPU oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
     out = {
-        "metric": "point*ray*freq updates/s (one Jacobi iteration: sweep + J + SEE)",
+        "metric": "point*ray*freq updates/s (FP32 sweep + J + SEE, plus adjoint sweep)",
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -212,9 +252,12 @@ def main():
         "dtype": "f32" if prec == porta.F32 else "f64",
         "data": "synthetic (seeded two-level atmosphere with the paper's box geometry)",
         "config": {"workload": f"{cfg.nx}x{cfg.ny}x{cfg.nz} grid, {cfg.nrays} rays, "
-                               f"{cfg.nfreq} freqs, Jacobi step (sweep+J+SEE), adjoint not "
-                               "included", "updates_per_step": cfg.updates,
-                   "ray_batch": nrb, "parallelism": "single GPU"},
+                               f"{cfg.nfreq} freqs: Jacobi step (sweep+J+SEE)"
+                               + (" + adjoint of the emergent-Stokes loss" if adj else ""),
+                   "updates_per_step": cfg.updates + adj_updates,
+                   "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
+                   "ray_batch": nrb, "checkpoint_stride": args.checkpoint_stride,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": extra,

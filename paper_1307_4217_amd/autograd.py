@@ -1,0 +1,41 @@
+"""torch.autograd binding of the sweep and its hand-written adjoint.
+
+`emergent_stokes(...)` returns the Stokes vectors of the upward rays on the top
+plane, [nray_up][nfreq][ny][nx][4], as a differentiable function of the
+line-centre transfer coefficients (kappa, propmat, emis).  Its backward pass is
+porta_fs_adjoint: the reverse sweep with plane checkpointing, not torch's
+autograd of a traced program.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import porta
+
+
+class PortaSweep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kappa, propmat, emis, hg, i_bottom, w2, prec, checkpoint_stride, opts):
+        _, itop = porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec,
+                                 want_jkq=False, opts=opts)
+        ctx.save_for_backward(kappa, propmat, emis)
+        ctx.cfg = (hg, i_bottom, w2, prec, checkpoint_stride, opts)
+        return itop
+
+    @staticmethod
+    def backward(ctx, grad_itop):
+        kappa, propmat, emis = ctx.saved_tensors
+        hg, i_bottom, w2, prec, stride, opts = ctx.cfg
+        seed = grad_itop.to(porta.dtype_of(prec)).contiguous()
+        gk, gp, ge = porta.fs_adjoint(hg, kappa.detach(), propmat.detach(), emis.detach(),
+                                      i_bottom, seed, w2, prec=prec, checkpoint_stride=stride,
+                                      opts=opts)
+        return gk, gp, ge, None, None, None, None, None, None
+
+
+def emergent_stokes(hg, kappa, propmat, emis, i_bottom, w2=1.0, prec=porta.F32,
+                    checkpoint_stride=8, opts=None):
+    """Differentiable I_top; kappa [N], propmat [6][N], emis [6][N] on the GPU in the sweep
+    precision (float32 for F32, float64 for F64)."""
+    return PortaSweep.apply(kappa, propmat, emis, hg, float(i_bottom), float(w2), int(prec),
+                            int(checkpoint_stride), opts)

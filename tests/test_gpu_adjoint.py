@@ -221,3 +221,31 @@ def test_c4_fp32_adjoint_against_fd_and_oracle(orc):
     got = np.sum(gk * v[0]) + np.sum(gp * v[1]) + np.sum(ge * v[2])
     ref = oracle_directional(orc, atm, q, w, *v, pairs=pairs)
     assert got == pytest.approx(ref, rel=1e-4)
+
+
+def test_autograd_function_uses_the_adjoint(orc):
+    torch = require_gpu()
+    from paper_1307_4217_amd.autograd import emergent_stokes
+    atm, q = tiny_case(porta.F64, seed=21, nx=4, ny=4, nz=6)
+    case = Case(atm, q, porta.F64)
+    k = case.kappa.clone().requires_grad_(True)
+    pm = case.prop.clone().requires_grad_(True)
+    e = case.emis.clone().requires_grad_(True)
+    target = torch.zeros((case.hg.nray_up, case.hg.nfreq, atm.ny, atm.nx, 4),
+                         dtype=torch.float64, device="cuda")
+    itop = emergent_stokes(case.hg, k, pm, e, atm.i_bottom, atm.w2, prec=porta.F64,
+                           checkpoint_stride=2)
+    loss = ((itop - target) ** 2).sum()
+    loss.backward()
+    gk, gp, ge = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                  (2 * (itop - target)).detach(), atm.w2, prec=porta.F64,
+                                  checkpoint_stride=2)
+    torch.cuda.synchronize()
+    assert torch.equal(k.grad, gk) and torch.equal(pm.grad, gp) and torch.equal(e.grad, ge)
+    # the autograd gradient against complex-step derivatives of the oracle
+    rng = np.random.default_rng(22)
+    v = [rng.normal(size=atm.npoints), rng.normal(size=(6, atm.npoints)),
+         rng.normal(size=(6, atm.npoints))]
+    got = sum(float(np.sum(x.grad.cpu().numpy() * y)) for x, y in zip((k, pm, e), v))
+    w = (2 * (itop - target)).detach().cpu().numpy()
+    assert got == pytest.approx(oracle_directional(orc, atm, q, w, *v), rel=1e-10)

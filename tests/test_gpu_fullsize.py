@@ -1,0 +1,106 @@
+"""Full-size parity: the 256x256x128 (101 frequencies, 160 rays) and 128x128x96
+(41 frequencies, magnetic) instances on the GPU against the oracle on sampled
+(ray, frequency) pairs over the whole top surface, plus invariants of J at full
+size, and 50 Jacobi iterations at the small size."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from gpu_common import Case, compare_stokes, require_gpu, rounded, to_dev, up_rays
+from paper_1307_4217_amd import inputs, porta
+
+pytestmark = pytest.mark.gpu
+
+RAYS_C3 = [0, 9, 18, 27, 41, 52, 66, 79]     # upward rays spread over inclinations/azimuths
+FREQS_C3 = [50, 38]                          # line centre and a near-wing frequency
+
+
+def _sampled_oracle(orc, atm, q, rays, freqs):
+    op = orc.OracleProblem(atm, q)
+    return orc.fs_sweep(op, rays=rays, freqs=freqs, want_j=False)["itop"]
+
+
+def _j_invariants(jkq):
+    assert np.all(jkq[0] > 0)
+    lbar = jkq[9]
+    assert np.all(lbar >= 0) and np.all(lbar < 1)
+    # |J^2_Q| bounded by J^0_0 (anisotropy of a positive radiation field)
+    for c in (4, 5, 6, 7, 8):
+        assert np.all(np.abs(jkq[c]) <= 1.5 * jkq[0])
+
+
+@pytest.mark.parametrize("prec, tol_i, tol_p", [(porta.F32, 2e-5, 1e-7),
+                                                (porta.F64, 1e-10, 1e-12)])
+def test_c3_full_size_sampled_pairs(orc, prec, tol_i, tol_p):
+    torch = require_gpu()
+    cfg = inputs.CONFIGS["C3"]
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, prec)
+    jkq, itop = case.sweep()
+    ref = _sampled_oracle(orc, atm, q, RAYS_C3, FREQS_C3)
+    got = itop[RAYS_C3][:, FREQS_C3]
+    ei, ep = compare_stokes(got, ref, tol_i, tol_p, f"C3 {'f32' if prec else 'f64'}")
+    print(f"C3 {'FP32' if prec == porta.F32 else 'FP64'} sweep vs FP64 oracle on "
+          f"{len(RAYS_C3) * len(FREQS_C3)} (ray, freq) pairs x {cfg.nx * cfg.ny} top points: "
+          f"max rel err I {ei:.3e}, max abs err Q/I,U/I,V/I {ep:.3e}")
+    _j_invariants(jkq)
+    del case
+    torch.cuda.empty_cache()
+
+
+def test_c2_two_jacobi_iterations_full_size(orc):
+    """FP64 at 128x128x96 with Hanle rotation: the sweep of iterations 1 and 2 on
+    sampled pairs and the statistical-equilibrium update at every point."""
+    torch = require_gpu()
+    cfg = inputs.CONFIGS["C2"]
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, porta.F64)
+    S = to_dev(atm.source, torch.float64)
+    hanle, bhat = to_dev(atm.hanle, torch.float64), to_dev(atm.bhat, torch.float64)
+    rays, freqs = [0, 23, 57, 79], [20, 12]
+    emis_host = atm.emis
+    s_host = atm.source
+    for it in range(2):
+        jkq, itop = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                   atm.w2)
+        torch.cuda.synchronize()
+        ref = _sampled_oracle(orc, dataclasses.replace(atm, emis=emis_host), q, rays, freqs)
+        compare_stokes(itop.cpu().numpy()[rays][:, freqs], ref, 1e-10, 1e-12, f"C2 it {it + 1}")
+        jh = jkq.cpu().numpy()
+        _j_invariants(jh)
+        S, _, rc = porta.see_update(jkq, S, atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
+                                    bhat, kappa=case.kappa, emis_out=case.emis)
+        torch.cuda.synchronize()
+        s_ref, e_ref, rc_ref = orc.see_update(jh, s_host, atm)
+        np.testing.assert_allclose(S.cpu().numpy(), s_ref, rtol=1e-12, atol=1e-14)
+        assert rc.item() == pytest.approx(rc_ref, rel=1e-12)
+        s_host = S.cpu().numpy()
+        emis_host = case.emis.cpu().numpy()
+
+
+def test_fifty_jacobi_iterations_c1(orc):
+    """50 FP64 Jacobi iterations at 16x16x32 (Hanle rotation on), GPU and oracle in lockstep."""
+    torch = require_gpu()
+    from paper_1307_4217_amd.jacobi import JacobiSolver
+    cfg = inputs.CONFIGS["C1"]
+    atm = inputs.make_atmosphere(cfg, seed=3, magnetic=True)
+    q = inputs.make_quadrature(cfg)
+    solver = JacobiSolver(atm, q, porta.F64)
+    s_host, emis_host = atm.source.copy(), atm.emis.copy()
+    op = orc.OracleProblem(atm, q)
+    worst = 0.0
+    for it in range(50):
+        rc = solver.step().item()
+        J = orc.fs_sweep(op.with_fields(emis=emis_host), want_itop=False)["jkq"]
+        s_host, emis_host, rc_ref = orc.see_update(J, s_host, atm)
+        s_gpu = solver.source.cpu().numpy()
+        err = np.max(np.abs(s_gpu - s_host) / np.maximum(np.abs(s_host), 1e-3))
+        worst = max(worst, err)
+        assert err < 1e-10, (it, err)
+        assert rc == pytest.approx(rc_ref, rel=1e-8, abs=1e-15)
+    print(f"50 Jacobi iterations at C1: final R_c {rc:.3e}, worst rel diff of S {worst:.2e}")
