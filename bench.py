@@ -23,6 +23,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_c3_fp32.json")
 
 
 def log(*a):
@@ -59,6 +60,22 @@ def sweep_launch_bytes(cfg, nrb, elem):
     np_ = cfg.nx * cfg.ny
     updates = nrb * cfg.nfreq * np_
     return updates * 8 * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
+
+
+def measured_traffic(kernel, workload_matches):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None if
+    the kernel sources changed since they were taken (or the workload differs)."""
+    import hashlib
+    if not workload_matches or not os.path.exists(COUNTERS):
+        return None
+    rec = json.load(open(COUNTERS))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    k = rec["kernels"].get(kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, atm, q, pairs):
@@ -197,9 +214,11 @@ def main():
     lbytes, lupd = sweep_launch_bytes(cfg, nrb, elem)
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
+    kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}>"
+    traffic = measured_traffic(kname, cfg.name == "C3" and nrb == 40 and args.block in (0, 256))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_sweep_plane<{'float' if elem == 4 else 'double'}>",
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname,
                 "launch_ms": round(launch_ms, 4), "bytes_per_launch": lbytes,
                 "updates_per_launch": lupd}
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),

@@ -122,8 +122,8 @@ typedef struct {
 typedef struct {
   int32_t ray_batch;        /* rays swept together (0: a whole hemisphere) */
   int32_t block;            /* threads per block of the sweep kernel (0: 256) */
-  int32_t xcd_remap;        /* 1: hand each XCD a contiguous range of tiles;
-                               0 or -1 (default): hardware order */
+  int32_t xcd_remap;        /* R > 0: each XCD takes R consecutive tiles per round;
+                               0: hardware order; -1: default (8) */
 } porta_options;
 
 /* Bytes of device workspace needed by one call of the given kind (0 on invalid

@@ -101,6 +101,9 @@ int validate_interp(int interp) {
 
 size_t elem(int prec) { return prec == PORTA_F32 ? sizeof(float) : sizeof(double); }
 
+// Tiles per XCD per round of the plane kernels (measured best on MI355X: 8).
+int xcd_chunk(const porta_options* o) { return (o && o->xcd_remap >= 0) ? o->xcd_remap : 8; }
+
 int ray_batch(const porta_quad* q, const porta_options* o) {
   const int nh = q->nmu * q->nchi;
   int rb = (o && o->ray_batch > 0) ? o->ray_batch : nh;
@@ -291,7 +294,7 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
         a.inv_dx = nx / g->lx;
         a.inv_dy = ny / g->ly;
         a.ray0 = ray0;
-        a.xcd_remap = (o && o->xcd_remap >= 0) ? o->xcd_remap : 0;
+        a.xcd_remap = xcd_chunk(o);
         a.ibound = ibound;
         const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
         hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
@@ -315,9 +318,9 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
 // Adjoint of the sweep of the upward rays
 // ---------------------------------------------------------------------------
 template <class T>
-int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* f, char* ws,
-                  const Layout& L, int k, const T* prev, T* next, int ray0, int nrb, int block,
-                  hipStream_t st) {
+int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* f,
+                  const porta_options* o, char* ws, const Layout& L, int k, const T* prev, T* next,
+                  int ray0, int nrb, int block, hipStream_t st) {
   const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
   PlaneArgs<T> a;
   a.kappa = static_cast<const T*>(f->kappa);
@@ -345,7 +348,7 @@ int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* 
   a.inv_dx = nx / g->lx;
   a.inv_dy = ny / g->ly;
   a.ray0 = ray0;
-  a.xcd_remap = 0;
+  a.xcd_remap = xcd_chunk(o);
   a.ibound = (T)f->i_bottom;
   const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
   hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block), lds, st,
@@ -382,7 +385,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
     const int nrb = std::min(nrb_max, nh - r0);
     // forward pass keeping every C-th plane
     for (int k = 1; k < nz; ++k)
-      if ((rc = forward_plane<T>(g, q, f, ws, L, k, plane(k - 1), plane(k), r0, nrb, block, st)))
+      if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block, st)))
         return rc;
     // reverse pass, one segment between checkpoints at a time
     const T* lam_next = nullptr;
@@ -391,7 +394,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
       const int s0 = C * ((khi - 1) / C);
       for (int k = s0 + 1; k <= khi; ++k)
         if (k % C != 0)
-          if ((rc = forward_plane<T>(g, q, f, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
+          if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
                                      st)))
             return rc;
       for (int k = khi; k > s0; --k) {
@@ -423,6 +426,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.inv_dx = nx / g->lx;
         a.inv_dy = ny / g->ly;
         a.ray0 = r0;
+        a.xcd_remap = xcd_chunk(o);
         a.ibound = (T)f->i_bottom;
         hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
                            lds_adj, st, a);
@@ -513,8 +517,7 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
-  if (opts && (opts->ray_batch < 0 || opts->block < 0 || opts->xcd_remap < -1 ||
-               opts->xcd_remap > 1))
+  if (opts && (opts->ray_batch < 0 || opts->block < 0 || opts->xcd_remap < -1))
     return fail(PORTA_EINVAL, "options must be >= 0");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the sweep");

@@ -43,6 +43,7 @@ struct AdjArgs {
   double dzM, dzP, dzN;   // dzN = |z_{kO+1} - z_kO| (plane above), 0 on the top plane
   double inv_dx, inv_dy;
   int ray0;
+  int xcd_remap;       // tiles per XCD per round, see xcd_tile
   T ibound;
 };
 
@@ -63,9 +64,10 @@ __global__ void __launch_bounds__(256) k_adjoint_plane(const AdjArgs<T> a) {
   T* s_phi = reinterpret_cast<T*>(s_tab);
   for (int t = threadIdx.x; t < a.nfreq; t += blockDim.x) s_phi[t] = a.phi[t];
   __syncthreads();
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int bx, rb;
+  xcd_tile(a.xcd_remap, bx, rb);
+  const int p = bx * blockDim.x + threadIdx.x;
   if (p >= a.np) return;
-  const int rb = blockIdx.y;
   const RayConsts& rc = a.rays[a.ray0 + rb];
   PointSetup ps;
   setup_point(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM, a.dzP,

@@ -301,21 +301,27 @@ struct PlaneArgs {
   double dzM, dzP;   // |z_kO - z_kM|, |z_kP - z_kO|
   double inv_dx, inv_dy;
   int ray0;
-  int xcd_remap;     // give each XCD a contiguous range of (ray, node-block) tiles
+  int xcd_remap;     // tiles per XCD per round (0: hardware order), see xcd_tile
   T ibound;          // Stokes I on the boundary plane of this hemisphere
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each with
-// its own L2.  Renumbering them so that XCD x receives a contiguous range of
-// tiles keeps the upwind rows shared by neighbouring tiles in one L2.
-__device__ inline void xcd_tile(int remap, int& bx, int& by) {
+// its own L2.  With chunk R > 0 the tiles are renumbered so that every XCD takes
+// R consecutive tiles per round (neighbouring rows of one ray then share an L2)
+// while the eight XCDs still advance through the grid together.
+__device__ inline void xcd_tile(int chunk, int& bx, int& by) {
   bx = blockIdx.x;
   by = blockIdx.y;
-  if (!remap) return;
+  if (chunk <= 0) return;
   const int T = gridDim.x * gridDim.y;
   const int L = blockIdx.y * gridDim.x + blockIdx.x;
-  const int x = L % 8, q = T / 8, r = T % 8;
-  const int Lp = (x < r) ? x * (q + 1) + L / 8 : r * (q + 1) + (x - r) * q + L / 8;
+  const int round = 8 * chunk;
+  const int Tmain = (T / round) * round;
+  int Lp = L;
+  if (L < Tmain) {
+    const int x = L % 8, k = L / 8;
+    Lp = (k / chunk) * round + x * chunk + (k % chunk);
+  }
   bx = Lp % gridDim.x;
   by = Lp / gridDim.x;
 }
