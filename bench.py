@@ -147,15 +147,22 @@ def main():
                        atm.i_bottom, atm.w2, prec=prec, want_jkq=False, i_top=target, opts=opts,
                        workspace=ws)
         del tatm
-        ws_adj = torch.empty(porta.workspace_size(hg, prec, porta.WS_ADJOINT,
+        # the forward sweep of each step keeps the upward rays' checkpoint planes for the
+        # adjoint, which then only recomputes the planes between checkpoints
+        ckpt = torch.empty(porta.checkpoint_size(hg, prec, args.checkpoint_stride) + 256,
+                           dtype=torch.uint8, device=dev)
+        ws_adj = torch.empty(porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
                                                   args.checkpoint_stride, opts),
                              dtype=torch.uint8, device=dev)
         g_k, g_p, g_e = torch.empty_like(kappa), torch.empty_like(prop), torch.empty_like(emis)
         seed_buf = torch.empty_like(itop)
-        log(f"adjoint workspace {ws_adj.numel() / 1e9:.2f} GB (stride {args.checkpoint_stride})")
+        log(f"adjoint workspace {ws_adj.numel() / 1e9:.2f} GB, checkpoints "
+            f"{ckpt.numel() / 1e9:.2f} GB (stride {args.checkpoint_stride})")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    state = {"s_old": s_a, "s_new": s_b}
+    # the SEE writes the next emissivities into a second buffer, swapped in after the
+    # adjoint so that the adjoint differentiates the sweep that produced I_top
+    state = {"s_old": s_a, "s_new": s_b, "emis": emis, "emis_next": torch.empty_like(emis)}
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -165,26 +172,31 @@ def main():
 
     def step(times):
         e = [ev() for _ in range(5)]
+        emis_cur = state["emis"]
         e[0].record()
-        porta.fs_sweep(hg, kappa, prop, emis, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
-                       i_top=itop, opts=opts, workspace=ws)
+        porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
+                       i_top=itop, opts=opts, workspace=ws,
+                       checkpoints=ckpt if adj else None,
+                       checkpoint_stride=args.checkpoint_stride if adj else 0)
         e[1].record()
         porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
-                         bhat, kappa=kappa, emis_out=emis, prec=prec, s_new=state["s_new"], rc=rc,
-                         workspace=ws_see)
+                         bhat, kappa=kappa, emis_out=state["emis_next"], prec=prec,
+                         s_new=state["s_new"], rc=rc, workspace=ws_see)
         e[2].record()
         if adj:
             # dL/dI_top of L = sum (I_top - target)^2, then the reverse sweep
             torch.sub(itop, target, out=seed_buf).mul_(2.0)
             e[3].record()
             g_k.zero_(), g_p.zero_(), g_e.zero_()
-            porta.fs_adjoint(hg, kappa, prop, emis, atm.i_bottom, seed_buf, atm.w2, prec=prec,
+            porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, seed_buf, atm.w2, prec=prec,
                              checkpoint_stride=args.checkpoint_stride, g_kappa=g_k,
-                             g_propmat=g_p, g_emis=g_e, opts=opts, workspace=ws_adj)
+                             g_propmat=g_p, g_emis=g_e, opts=opts, workspace=ws_adj,
+                             checkpoints=ckpt)
         else:
             e[3].record()
         e[4].record()
         state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
+        state["emis"], state["emis_next"] = state["emis_next"], state["emis"]
         times.append(e)
 
     for w in range(args.warmup):
@@ -230,7 +242,7 @@ def main():
     if not args.no_fp64_rate and prec == porta.F32:
         del ws
         if adj:
-            del ws_adj
+            del ws_adj, ckpt
         torch.cuda.empty_cache()
         k64, p64, e64 = t(atm.kappa, torch.float64), t(atm.propmat, torch.float64), t(
             atm.emis, torch.float64)

@@ -74,7 +74,8 @@ typedef enum {
   PORTA_WS_SWEEP = 0,   /* porta_fs_sweep */
   PORTA_WS_ADJOINT = 1, /* porta_fs_adjoint */
   PORTA_WS_JKQ = 2,     /* porta_jkq_accumulate */
-  PORTA_WS_SEE = 3      /* porta_see_update */
+  PORTA_WS_SEE = 3,     /* porta_see_update */
+  PORTA_WS_ADJOINT_CKPT = 4 /* porta_fs_adjoint given checkpoints from porta_fs_sweep */
 } porta_ws_kind;
 
 /* Spatial grid (Sect. 3.1, Appendix A). */
@@ -128,9 +129,15 @@ typedef struct {
 
 /* Bytes of device workspace needed by one call of the given kind (0 on invalid
  * arguments).  `prec` selects the sweep precision; `checkpoint_stride` is
- * used by PORTA_WS_ADJOINT only. */
+ * used by the two adjoint kinds only. */
 size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int prec,
                             int kind, int checkpoint_stride, const porta_options* opts);
+
+/* Bytes of the checkpoint buffer that porta_fs_sweep fills for porta_fs_adjoint:
+ * the states of the upward rays on planes C, 2C, ... below the top plane,
+ * layout [(nz-2)/C][nmu*nchi][nfreq][ny][nx][4] in the sweep precision. */
+size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int prec,
+                             int checkpoint_stride);
 
 /*
  * Formal solution for every ray and frequency (Sect. 3; Eqs. fsint, fsbez,
@@ -142,11 +149,16 @@ size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int 
  *                   or added to (accumulate = 1)
  *   i_top         : device [nmu*nchi][nfreq][ny][nx][4] (sweep precision),
  *                   Stokes vectors of the upward rays at z[nz-1], or NULL
+ *   checkpoints   : device, porta_checkpoint_size() bytes, or NULL; filled with
+ *                   the upward rays' states every checkpoint_stride planes for a
+ *                   later porta_fs_adjoint of the same fields (no extra traffic:
+ *                   those planes are written there instead of the workspace)
  *   workspace     : device, >= porta_workspace_size(..., PORTA_WS_SWEEP, ...)
  */
 int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                    int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
-                   void* i_top, void* workspace, size_t ws_bytes, void* stream);
+                   void* i_top, void* checkpoints, int checkpoint_stride, void* workspace,
+                   size_t ws_bytes, void* stream);
 
 /*
  * Eq. 1 (and the Lambda* average) from a stored block of Stokes vectors:
@@ -181,12 +193,16 @@ int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
  * dL/dkappa, dL/dpropmat and dL/demis (each in the layout of its field, in
  * the sweep precision) to g_kappa [N], g_propmat [6][N], g_emis [6][N].
  * The intensity field is recomputed from plane checkpoints every
- * `checkpoint_stride` planes (>= 1) instead of being stored.
+ * `checkpoint_stride` planes (1..nz-1) instead of being stored.  With
+ * `checkpoints` NULL the call first sweeps the upward rays to make them
+ * (workspace kind PORTA_WS_ADJOINT); otherwise they are the ones porta_fs_sweep
+ * wrote for these fields with the same stride (kind PORTA_WS_ADJOINT_CKPT).
  */
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,
-                     int checkpoint_stride, void* g_kappa, void* g_propmat, void* g_emis,
-                     void* workspace, size_t ws_bytes, void* stream);
+                     const void* checkpoints, int checkpoint_stride, void* g_kappa,
+                     void* g_propmat, void* g_emis, void* workspace, size_t ws_bytes,
+                     void* stream);
 
 /* Text of a porta_status. */
 const char* porta_strerror(int status);

@@ -160,17 +160,21 @@ Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const po
   return L;
 }
 
-// Adjoint: floor((nz-1)/C) checkpoint planes (every C-th plane), C-1 slots for
-// the planes recomputed between two checkpoints, two planes of Lambda, the
+// Checkpoint planes are k = C, 2C, ... <= nz - 2 (the top plane is recomputed).
+int checkpoint_count(int nz, int C) { return nz >= 3 ? (nz - 2) / C : 0; }
+bool is_checkpoint(int k, int nz, int C) { return k >= 1 && k % C == 0 && k <= nz - 2; }
+
+// Adjoint: checkpoint planes (unless the caller brings them), C slots for the
+// planes recomputed between two checkpoints, two planes of Lambda, the
 // per-(node, ray) partials of one plane and the FP64 gradient accumulator.
 Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int stride,
-                      const porta_options* o) {
+                      const porta_options* o, bool own_checkpoints) {
   Layout L = tables_layout(q, prec);
   const size_t np = (size_t)g->nx * g->ny, N = np * g->nz;
   const size_t nrb = (size_t)ray_batch(q, o);
   L.plane = nrb * q->nfreq * np * 4 * elem(prec);
-  L.nck = (g->nz - 1) / stride;
-  L.nslot = stride - 1;
+  L.nck = own_checkpoints ? checkpoint_count(g->nz, stride) : 0;
+  L.nslot = stride;
   size_t off = L.end_tables;
   L.ck = off;
   off = align_up(off + (size_t)L.nck * L.plane);
@@ -190,6 +194,11 @@ Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int st
   off = align_up(off + 13 * N * sizeof(double));
   L.total = off;
   return L;
+}
+
+size_t checkpoint_bytes(const porta_grid* g, const porta_quad* q, int prec, int stride) {
+  return (size_t)checkpoint_count(g->nz, stride) * q->nmu * q->nchi * q->nfreq *
+         ((size_t)g->nx * g->ny) * 4 * elem(prec);
 }
 
 // Upload host doubles through kernel arguments (ordered on the stream).
@@ -231,8 +240,8 @@ int fill(double* p, size_t n, double v, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <class T>
 int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
-               const porta_options* o, double* jkq, int accumulate, T* itop, char* ws,
-               const Layout& L, hipStream_t st) {
+               const porta_options* o, double* jkq, int accumulate, T* itop, T* ckpt, int C,
+               char* ws, const Layout& L, hipStream_t st) {
   int rc;
   if ((rc = prepare_tables<T>(ws, L, q, f->w2, st))) return rc;
   const int nx = g->nx, ny = g->ny, nz = g->nz;
@@ -274,7 +283,13 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
         a.wn = wn;
         a.iprev = prev;
         const bool last = (step == nz - 1);
-        a.inext = (last && up && itop) ? itop + (size_t)r0 * q->nfreq * np * 4 : state[step & 1];
+        const size_t batch_off = (size_t)r0 * q->nfreq * np * 4;
+        if (last && up && itop)
+          a.inext = itop + batch_off;
+        else if (up && ckpt && is_checkpoint(k, nz, C))   // kept for the adjoint
+          a.inext = ckpt + (size_t)(k / C - 1) * nh * q->nfreq * np * 4 + batch_off;
+        else
+          a.inext = state[step & 1];
         // plane k writes partial sums into jpart[step & 1] while the first ray row of
         // blocks adds those of plane k - s (or the boundary plane) to J
         a.jpart = jpart[step & 1];
@@ -358,8 +373,8 @@ int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* 
 
 template <class T>
 int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
-                 const porta_options* o, const T* seed, int C, T* gk, T* gpm, T* ge, char* ws,
-                 const Layout& L, hipStream_t st) {
+                 const porta_options* o, const T* seed, const T* ext_ck, int C, T* gk, T* gpm,
+                 T* ge, char* ws, const Layout& L, hipStream_t st) {
   int rc;
   if ((rc = prepare_tables<T>(ws, L, q, f->w2, st))) return rc;
   const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
@@ -374,26 +389,35 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
   T* ck = reinterpret_cast<T*>(ws + L.ck);
   T* slots = reinterpret_cast<T*>(ws + L.slots);
   T* lam[2] = {reinterpret_cast<T*>(ws + L.lamA), reinterpret_cast<T*>(ws + L.lamB)};
-  // forward state of plane k: the boundary (nullptr), a checkpoint, or a recompute slot
+  // forward state of plane k of the current batch: the boundary (nullptr), a
+  // checkpoint (own or the caller's, rays contiguous in both), or a recompute slot
+  int r0 = 0;
   auto plane = [&](int k) -> T* {
     if (k == 0) return nullptr;
-    if (k % C == 0) return ck + (size_t)(k / C - 1) * pe;
-    return slots + (size_t)(k % C - 1) * pe;
+    if (is_checkpoint(k, nz, C)) {
+      if (ext_ck)
+        return const_cast<T*>(ext_ck) + (size_t)(k / C - 1) * nh * q->nfreq * np * 4 +
+               (size_t)r0 * q->nfreq * np * 4;
+      return ck + (size_t)(k / C - 1) * pe;
+    }
+    return slots + (size_t)((k - 1) % C) * pe;
   };
   const size_t lds_adj = (size_t)q->nfreq * sizeof(T);
-  for (int r0 = 0; r0 < nh; r0 += nrb_max) {
+  for (r0 = 0; r0 < nh; r0 += nrb_max) {
     const int nrb = std::min(nrb_max, nh - r0);
-    // forward pass keeping every C-th plane
-    for (int k = 1; k < nz; ++k)
-      if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block, st)))
-        return rc;
+    // forward pass keeping every C-th plane (unless the sweep already kept them)
+    if (!ext_ck)
+      for (int k = 1; k < nz; ++k)
+        if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
+                                   st)))
+          return rc;
     // reverse pass, one segment between checkpoints at a time
     const T* lam_next = nullptr;
     int cur = 0;
     for (int khi = nz - 1; khi >= 1;) {
       const int s0 = C * ((khi - 1) / C);
       for (int k = s0 + 1; k <= khi; ++k)
-        if (k % C != 0)
+        if (!is_checkpoint(k, nz, C))
           if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
                                      st)))
             return rc;
@@ -490,8 +514,12 @@ size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int 
       if (validate_grid(grid) || validate_quad(quad)) return 0;
       return sweep_layout(grid, quad, prec, opts).total;
     case PORTA_WS_ADJOINT:
-      if (validate_grid(grid) || validate_quad(quad) || checkpoint_stride < 1) return 0;
-      return adjoint_layout(grid, quad, prec, checkpoint_stride, opts).total;
+    case PORTA_WS_ADJOINT_CKPT:
+      if (validate_grid(grid) || validate_quad(quad) || checkpoint_stride < 1 ||
+          checkpoint_stride > grid->nz - 1)
+        return 0;
+      return adjoint_layout(grid, quad, prec, checkpoint_stride, opts, kind == PORTA_WS_ADJOINT)
+          .total;
     case PORTA_WS_JKQ:
       if (validate_quad(quad)) return 0;
       return tables_layout(quad, prec).total;
@@ -506,9 +534,20 @@ size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int 
   }
 }
 
+size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int prec,
+                             int checkpoint_stride) {
+  if (validate_prec(prec) || validate_grid(grid) || validate_quad(quad)) return 0;
+  if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1) {
+    fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
+    return 0;
+  }
+  return checkpoint_bytes(grid, quad, prec, checkpoint_stride);
+}
+
 int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                    int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
-                   void* i_top, void* workspace, size_t ws_bytes, void* stream) {
+                   void* i_top, void* checkpoints, int checkpoint_stride, void* workspace,
+                   size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
       (rc = validate_interp(interp)))
@@ -521,6 +560,8 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "options must be >= 0");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the sweep");
+  if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
+    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
   const Layout L = sweep_layout(grid, quad, prec, opts);
   if (ws_bytes < L.total)
@@ -530,9 +571,10 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
   char* ws = static_cast<char*>(workspace);
   if (prec == PORTA_F64)
     return sweep_impl<double>(grid, quad, fields, opts, jkq, accumulate,
-                              static_cast<double*>(i_top), ws, L, st);
+                              static_cast<double*>(i_top), static_cast<double*>(checkpoints),
+                              checkpoint_stride, ws, L, st);
   return sweep_impl<float>(grid, quad, fields, opts, jkq, accumulate, static_cast<float*>(i_top),
-                           ws, L, st);
+                           static_cast<float*>(checkpoints), checkpoint_stride, ws, L, st);
 }
 
 int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray0, int nray,
@@ -619,8 +661,9 @@ int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
 
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,
-                     int checkpoint_stride, void* g_kappa, void* g_propmat, void* g_emis,
-                     void* workspace, size_t ws_bytes, void* stream) {
+                     const void* checkpoints, int checkpoint_stride, void* g_kappa,
+                     void* g_propmat, void* g_emis, void* workspace, size_t ws_bytes,
+                     void* stream) {
   int rc;
   if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
       (rc = validate_interp(interp)))
@@ -629,14 +672,14 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!dl_ditop || !g_kappa || !g_propmat || !g_emis)
     return fail(PORTA_EINVAL, "seed and gradient arrays must not be NULL");
-  if (checkpoint_stride < 1 || checkpoint_stride > grid->nz)
-    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz");
+  if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1)
+    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (opts && (opts->ray_batch < 0 || opts->block < 0))
     return fail(PORTA_EINVAL, "options must be >= 0");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
-  const Layout L = adjoint_layout(grid, quad, prec, checkpoint_stride, opts);
+  const Layout L = adjoint_layout(grid, quad, prec, checkpoint_stride, opts, !checkpoints);
   if (ws_bytes < L.total)
     return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 L.total);
@@ -644,11 +687,11 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   char* ws = static_cast<char*>(workspace);
   if (prec == PORTA_F64)
     return adjoint_impl<double>(grid, quad, fields, opts, static_cast<const double*>(dl_ditop),
-                                checkpoint_stride, static_cast<double*>(g_kappa),
+                                static_cast<const double*>(checkpoints), checkpoint_stride, static_cast<double*>(g_kappa),
                                 static_cast<double*>(g_propmat), static_cast<double*>(g_emis), ws,
                                 L, st);
   return adjoint_impl<float>(grid, quad, fields, opts, static_cast<const float*>(dl_ditop),
-                             checkpoint_stride, static_cast<float*>(g_kappa),
+                             static_cast<const float*>(checkpoints), checkpoint_stride, static_cast<float*>(g_kappa),
                              static_cast<float*>(g_propmat), static_cast<float*>(g_emis), ws, L,
                              st);
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libporta.so")
 
 F64, F32 = 0, 1
 BILINEAR, BEZIER2D = 0, 1
-WS_SWEEP, WS_ADJOINT, WS_JKQ, WS_SEE = 0, 1, 2, 3
+WS_SWEEP, WS_ADJOINT, WS_JKQ, WS_SEE, WS_ADJOINT_CKPT = 0, 1, 2, 3, 4
 
 _dp = C.POINTER(C.c_double)
 
@@ -71,14 +71,17 @@ def lib():
             L.porta_workspace_size.restype = sz
             L.porta_fs_sweep.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
                                          C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
-                                         vp, sz, vp]
+                                         vp, C.c_int, vp, sz, vp]
+            L.porta_checkpoint_size.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int,
+                                                C.c_int]
+            L.porta_checkpoint_size.restype = sz
             L.porta_jkq_accumulate.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int, C.c_int,
                                                C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, sz, vp]
             L.porta_see_update.argtypes = [C.c_int64, vp, C.POINTER(Atom), vp, vp, vp, vp,
                                            C.c_int, vp, vp, sz, vp]
             L.porta_fs_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
-                                           C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
-                                           vp, vp, vp, sz, vp]
+                                           C.c_int, C.c_int, C.POINTER(Options), vp, vp, C.c_int,
+                                           vp, vp, vp, vp, sz, vp]
             L.porta_strerror.argtypes = [C.c_int]
             L.porta_strerror.restype = C.c_char_p
             L.porta_last_error.restype = C.c_char_p
@@ -87,7 +90,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("porta_workspace_size", "porta_fs_sweep", "porta_jkq_accumulate",
+EXPORTED = ("porta_workspace_size", "porta_checkpoint_size", "porta_fs_sweep",
+            "porta_jkq_accumulate",
             "porta_see_update", "porta_fs_adjoint", "porta_strerror", "porta_last_error",
             "porta_version")
 
@@ -152,6 +156,13 @@ def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> 
     return int(n)
 
 
+def checkpoint_size(hg: HostGrid, prec, checkpoint_stride) -> int:
+    """Bytes of the checkpoint buffer (0 also when no plane is a checkpoint; an invalid
+    stride is reported by fs_sweep / fs_adjoint)."""
+    return int(lib().porta_checkpoint_size(C.byref(hg.grid), C.byref(hg.quad), int(prec),
+                                           int(checkpoint_stride)))
+
+
 def _workspace(nbytes, device):
     import torch
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -164,8 +175,10 @@ def dtype_of(prec):
 
 def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, interp=BILINEAR,
              jkq=None, accumulate=False, i_top=None, want_jkq=True, want_itop=True,
-             opts=None, workspace=None, stream=None):
-    """porta_fs_sweep.  Returns (jkq [10][N] float64, i_top [nray_up][nfreq][ny][nx][4])."""
+             opts=None, workspace=None, stream=None, checkpoints=None, checkpoint_stride=0):
+    """porta_fs_sweep.  Returns (jkq [10][N] float64, i_top [nray_up][nfreq][ny][nx][4]).
+    With `checkpoints` (a device buffer of checkpoint_size() bytes) the states of the
+    upward rays every `checkpoint_stride` planes are kept for fs_adjoint."""
     import torch
     dev = kappa.device
     if want_jkq and jkq is None:
@@ -179,8 +192,9 @@ def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, int
     st = lib().porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), int(prec),
                               int(interp), C.byref(opts) if opts else None,
                               _ptr(jkq) if want_jkq else None, int(bool(accumulate)),
-                              _ptr(i_top) if want_itop else None, _ptr(workspace),
-                              workspace.numel(), _stream(stream))
+                              _ptr(i_top) if want_itop else None, _ptr(checkpoints),
+                              int(checkpoint_stride), _ptr(workspace), workspace.numel(),
+                              _stream(stream))
     _check("porta_fs_sweep", st)
     return (jkq if want_jkq else None), (i_top if want_itop else None)
 
@@ -227,8 +241,9 @@ def see_update(jkq, s_old, eps_c, delta2, w2, planck, hanle=None, bhat=None, kap
 
 def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, prec=F64,
                interp=BILINEAR, checkpoint_stride=8, g_kappa=None, g_propmat=None, g_emis=None,
-               opts=None, workspace=None, stream=None):
-    """porta_fs_adjoint; gradients are added to g_* (allocated as zeros if None)."""
+               opts=None, workspace=None, stream=None, checkpoints=None):
+    """porta_fs_adjoint; gradients are added to g_* (allocated as zeros if None).
+    `checkpoints`: the buffer fs_sweep filled with the same stride, or None."""
     import torch
     dev = kappa.device
     if g_kappa is None:
@@ -238,11 +253,13 @@ def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, p
     if g_emis is None:
         g_emis = torch.zeros_like(emis)
     if workspace is None:
-        workspace = _workspace(workspace_size(hg, prec, WS_ADJOINT, checkpoint_stride, opts), dev)
+        kind = WS_ADJOINT if checkpoints is None else WS_ADJOINT_CKPT
+        workspace = _workspace(workspace_size(hg, prec, kind, checkpoint_stride, opts), dev)
     f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))
     st = lib().porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), int(prec),
                                 int(interp), C.byref(opts) if opts else None, _ptr(dl_ditop),
-                                int(checkpoint_stride), _ptr(g_kappa), _ptr(g_propmat),
+                                _ptr(checkpoints), int(checkpoint_stride), _ptr(g_kappa),
+                                _ptr(g_propmat),
                                 _ptr(g_emis), _ptr(workspace), workspace.numel(), _stream(stream))
     _check("porta_fs_adjoint", st)
     return g_kappa, g_propmat, g_emis

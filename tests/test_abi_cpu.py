@@ -41,7 +41,7 @@ def call_sweep(hg, prec=porta.F64, interp=porta.BILINEAR, ws_bytes=None, fields=
     f = porta.Fields(dummy.ctypes.data if fields else None, dummy.ctypes.data,
                      dummy.ctypes.data, 1.0, 1.0)
     return L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), prec, interp, None,
-                            None, 0, None, dummy.ctypes.data if ws else None,
+                            None, 0, None, None, 0, dummy.ctypes.data if ws else None,
                             0 if ws_bytes is None else ws_bytes, None)
 
 
@@ -111,7 +111,16 @@ def test_other_entry_points_validate():
                                   dummy.ctypes.data, None, 0, dummy.ctypes.data,
                                   dummy.ctypes.data, 1 << 20, None) == -1
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
-    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None,
-                              dummy.ctypes.data, 0, dummy.ctypes.data, dummy.ctypes.data,
-                              dummy.ctypes.data, dummy.ctypes.data, 1 << 30, None) == -1
+    for stride in (0, 32):   # must be in 1..nz-1
+        assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None,
+                                  dummy.ctypes.data, None, stride, dummy.ctypes.data,
+                                  dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
+                                  1 << 40, None) == -1
+    # a checkpoint buffer needs a valid stride
+    assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None, None, 0,
+                            None, dummy.ctypes.data, 0, dummy.ctypes.data, 1 << 40, None) == -1
+    assert porta.checkpoint_size(hg, porta.F32, 4) == (30 // 4) * 40 * 21 * 256 * 16
+    assert porta.checkpoint_size(hg, porta.F64, 31) == 0
+    assert (porta.workspace_size(hg, porta.F32, porta.WS_ADJOINT_CKPT, 4)
+            < porta.workspace_size(hg, porta.F32, porta.WS_ADJOINT, 4))
     assert porta.lib().porta_strerror(-3) == b"workspace too small"

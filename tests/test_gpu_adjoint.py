@@ -57,7 +57,7 @@ def tiny_case(prec, seed=11, nx=4, ny=3, nz=5):
     return atm, inputs.make_quadrature(cfg)
 
 
-@pytest.mark.parametrize("stride", [1, 2, 5])
+@pytest.mark.parametrize("stride", [1, 2, 4])
 def test_adjoint_fp64_every_component_matches_complex_step(orc, stride):
     atm, q = tiny_case(porta.F64)
     case = Case(atm, q, porta.F64)
@@ -107,7 +107,7 @@ def test_adjoint_ragged_batches_and_strides(orc):
     atm, q = tiny_case(porta.F64, seed=12, nx=5, ny=3, nz=7)
     case = Case(atm, q, porta.F64)
     w = seed_for(case, np.random.default_rng(3))
-    base = np.concatenate([g.reshape(-1) for g in gpu_grad(case, w, stride=7)])
+    base = np.concatenate([g.reshape(-1) for g in gpu_grad(case, w, stride=6)])
     for stride, rb, blk in ((1, 3, 64), (3, 5, 128), (2, 0, 192)):
         g = gpu_grad(case, w, stride=stride, opts=porta.options(ray_batch=rb, block=blk))
         np.testing.assert_allclose(np.concatenate([x.reshape(-1) for x in g]), base, rtol=1e-12,
@@ -249,3 +249,33 @@ def test_autograd_function_uses_the_adjoint(orc):
     got = sum(float(np.sum(x.grad.cpu().numpy() * y)) for x, y in zip((k, pm, e), v))
     w = (2 * (itop - target)).detach().cpu().numpy()
     assert got == pytest.approx(oracle_directional(orc, atm, q, w, *v), rel=1e-10)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+@pytest.mark.parametrize("stride, rb_fwd, rb_adj", [(2, 0, 3), (3, 5, 0), (1, 2, 7), (6, 0, 0)])
+def test_adjoint_with_checkpoints_from_the_sweep(prec, stride, rb_fwd, rb_adj):
+    """Checkpoints written by porta_fs_sweep (any ray batch) give the same gradient, bitwise,
+    as the adjoint making its own."""
+    torch = require_gpu()
+    atm, q = tiny_case(prec, seed=31, nx=5, ny=4, nz=7)
+    case = Case(atm, q, prec)
+    w = to_dev(seed_for(case, np.random.default_rng(8)), case.dt)
+    n = porta.checkpoint_size(case.hg, prec, stride)
+    ck = torch.full((max(n, 256),), 255, dtype=torch.uint8, device="cuda")
+    jkq, itop = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                               prec=prec, checkpoints=ck, checkpoint_stride=stride,
+                               opts=porta.options(ray_batch=rb_fwd))
+    ref_j, ref_t = case.sweep()
+    torch.cuda.synchronize()
+    # I_top is independent of the ray batching; J only up to its summation order
+    assert np.array_equal(itop.cpu().numpy(), ref_t)
+    np.testing.assert_allclose(jkq.cpu().numpy(), ref_j, rtol=1e-13, atol=1e-15)
+    own = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
+                           prec=prec, checkpoint_stride=stride,
+                           opts=porta.options(ray_batch=rb_adj))
+    ext = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
+                           prec=prec, checkpoint_stride=stride, checkpoints=ck,
+                           opts=porta.options(ray_batch=rb_adj))
+    torch.cuda.synchronize()
+    for a, b in zip(own, ext):
+        assert torch.equal(a, b)
