@@ -67,7 +67,10 @@ typedef enum { PORTA_F64 = 0, PORTA_F32 = 1 } porta_prec;   /* sweep precision *
 
 typedef enum {
   PORTA_INTERP_BILINEAR = 0, /* 4-point bilinear at M and P (Sect. 3.1) */
-  PORTA_INTERP_BEZIER2D = 1  /* 9-point monotonic quadratic Bezier, x then y */
+  PORTA_INTERP_BEZIER2D = 1  /* 9-point stencil around the nearest node; monotonic
+                                quadratic Bezier (BESSER control points, Sect. 3.2)
+                                along x for each row, then along y.  Forward sweep
+                                only: porta_fs_adjoint returns PORTA_EUNSUPPORTED */
 } porta_interp;
 
 typedef enum {
@@ -197,6 +200,8 @@ int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
  * `checkpoints` NULL the call first sweeps the upward rays to make them
  * (workspace kind PORTA_WS_ADJOINT); otherwise they are the ones porta_fs_sweep
  * wrote for these fields with the same stride (kind PORTA_WS_ADJOINT_CKPT).
+ * Only interp = PORTA_INTERP_BILINEAR is differentiated; PORTA_INTERP_BEZIER2D
+ * returns PORTA_EUNSUPPORTED.
  */
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,

@@ -20,6 +20,14 @@ double hm_besser_cm(double yM, double yO, double yP, double ratio) {
   return porta::besser_cm(yM, yO, yP, ratio);
 }
 
+double hm_bezier3_f64(double ym, double y0, double yp, double t) {
+  return porta::bezier3(ym, y0, yp, t);
+}
+
+float hm_bezier3_f32(float ym, float y0, float yp, float t) {
+  return porta::bezier3(ym, y0, yp, t);
+}
+
 void hm_solve_stokes_f64(const double* e3, const double* r3, const double* b4, double* x4) {
   porta::solve_stokes(e3, r3, b4, x4);
 }

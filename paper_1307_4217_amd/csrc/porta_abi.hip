@@ -239,7 +239,7 @@ int fill(double* p, size_t n, double v, hipStream_t st) {
 // Forward sweep
 // ---------------------------------------------------------------------------
 template <class T>
-int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
+int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, int interp,
                const porta_options* o, double* jkq, int accumulate, T* itop, T* ckpt, int C,
                char* ws, const Layout& L, hipStream_t st) {
   int rc;
@@ -312,8 +312,11 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
         a.xcd_remap = xcd_chunk(o);
         a.ibound = ibound;
         const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
-        hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
-                           lds, st, a);
+        const dim3 grid((np + block - 1) / block, nrb);
+        if (interp == PORTA_INTERP_BEZIER2D)
+          hipLaunchKernelGGL((k_sweep_plane<T, 1>), grid, dim3(block), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_sweep_plane<T, 0>), grid, dim3(block), lds, st, a);
         if ((rc = check_launch("sweep_plane"))) return rc;
         prev = a.inext;
       }
@@ -366,8 +369,8 @@ int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* 
   a.xcd_remap = xcd_chunk(o);
   a.ibound = (T)f->i_bottom;
   const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
-  hipLaunchKernelGGL(k_sweep_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block), lds, st,
-                     a);
+  hipLaunchKernelGGL((k_sweep_plane<T, 0>), dim3((np + block - 1) / block, nrb), dim3(block), lds,
+                     st, a);
   return check_launch("sweep_plane (adjoint recompute)");
 }
 
@@ -558,8 +561,6 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
   if (opts && (opts->ray_batch < 0 || opts->block < 0 || opts->xcd_remap < -1))
     return fail(PORTA_EINVAL, "options must be >= 0");
-  if (interp != PORTA_INTERP_BILINEAR)
-    return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the sweep");
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
@@ -570,10 +571,11 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   if (prec == PORTA_F64)
-    return sweep_impl<double>(grid, quad, fields, opts, jkq, accumulate,
+    return sweep_impl<double>(grid, quad, fields, interp, opts, jkq, accumulate,
                               static_cast<double*>(i_top), static_cast<double*>(checkpoints),
                               checkpoint_stride, ws, L, st);
-  return sweep_impl<float>(grid, quad, fields, opts, jkq, accumulate, static_cast<float*>(i_top),
+  return sweep_impl<float>(grid, quad, fields, interp, opts, jkq, accumulate,
+                           static_cast<float*>(i_top),
                            static_cast<float*>(checkpoints), checkpoint_stride, ws, L, st);
 }
 

@@ -70,8 +70,9 @@ __global__ void __launch_bounds__(256) k_adjoint_plane(const AdjArgs<T> a) {
   if (p >= a.np) return;
   const RayConsts& rc = a.rays[a.ray0 + rb];
   PointSetup ps;
-  setup_point(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM, a.dzP,
-              a.inv_dx, a.inv_dy, rc, p, ps);
+  Stencil9 unused9;
+  setup_point<0>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
+                 a.dzP, a.inv_dx, a.inv_dy, rc, p, ps, unused9);
   const int i = p % a.nx, j = p / a.nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   // nodes of the plane above whose upwind stencil contains p

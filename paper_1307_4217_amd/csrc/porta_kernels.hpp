@@ -147,6 +147,45 @@ __device__ inline Stencil make_tstencil(int i, int j, int nx, int ny, double u, 
   return s;
 }
 
+// 3x3 stencil around the node nearest to the displaced point (mode B), with the
+// fractional offsets tx, ty in [-1/2, 1/2) from that node.
+struct Stencil9 {
+  int col[3];     // x indices of columns -1, 0, +1 (periodic)
+  int row[3];     // offsets j * nx of rows -1, 0, +1 (periodic)
+  double tx, ty;
+};
+
+__device__ inline Stencil9 make_stencil9(int i, int j, int nx, int ny, double u, double v) {
+  u -= nx * floor(u / nx);
+  v -= ny * floor(v / ny);
+  const double fu = floor(u + 0.5), fv = floor(v + 0.5);
+  Stencil9 s;
+  s.tx = u - fu;
+  s.ty = v - fv;
+  const int ic = wrapi(i + (int)fu, nx), jc = wrapi(j + (int)fv, ny);
+  s.col[0] = (ic == 0) ? nx - 1 : ic - 1;
+  s.col[1] = ic;
+  s.col[2] = (ic + 1 == nx) ? 0 : ic + 1;
+  s.row[0] = ((jc == 0) ? ny - 1 : jc - 1) * nx;
+  s.row[1] = jc * nx;
+  s.row[2] = ((jc + 1 == ny) ? 0 : jc + 1) * nx;
+  return s;
+}
+
+// Monotonic Bezier interpolation on a plane: along x for each of the three rows,
+// then along y.
+template <class T>
+__device__ inline double bez9(const T* __restrict__ f, const Stencil9& s) {
+  const BezW<double> wx = bez_weights(s.tx), wy = bez_weights(s.ty);
+  double r[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const T* row = f + s.row[b];
+    r[b] = bez_eval(wx, (double)row[s.col[0]], (double)row[s.col[1]], (double)row[s.col[2]]);
+  }
+  return bez_eval(wy, r[0], r[1], r[2]);
+}
+
 // Frequency-independent part of the update of node p on plane kO for one ray:
 // transfer coefficients interpolated at M (plane kM) and P (plane kP, if any),
 // source vectors S = eps/eta_I at M, O, P, K' at M and O, the line-centre
@@ -161,24 +200,40 @@ struct PointSetup {
   bool hasP;
 };
 
-template <class T>
+template <int MODE, class T>
 __device__ inline void setup_point(const T* __restrict__ kappa, const T* __restrict__ prop,
                                    const T* __restrict__ emis, size_t N, int nx, int ny, int np,
                                    int kO, int kM, int kP, double dzM, double dzP, double inv_dx,
-                                   double inv_dy, const RayConsts& rc, int p, PointSetup& ps) {
+                                   double inv_dy, const RayConsts& rc, int p, PointSetup& ps,
+                                   Stencil9& sM9) {
   const int i = p % nx, j = p / nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   ps.dsM = dzM * inv_mu;
-  ps.sM = make_stencil(i, j, nx, ny, -ps.dsM * rc.sx * inv_dx, -ps.dsM * rc.sy * inv_dy);
+  const double uM = -ps.dsM * rc.sx * inv_dx, vM = -ps.dsM * rc.sy * inv_dy;
   const size_t bM = (size_t)kM * np, bO = (size_t)kO * np + p;
-  ps.kapM = bil(kappa + bM, ps.sM);
+  if (MODE == 0) {
+    ps.sM = make_stencil(i, j, nx, ny, uM, vM);
+    ps.kapM = bil(kappa + bM, ps.sM);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ps.epsM[c] = bil(emis + c * N + bM, ps.sM);
+      ps.etaM[c] = bil(prop + c * N + bM, ps.sM);
+    }
+  } else {
+    ps.sM = Stencil{0, 0, 0, 0, 1.0, 0.0, 0.0, 0.0};
+    sM9 = make_stencil9(i, j, nx, ny, uM, vM);
+    ps.kapM = bez9(kappa + bM, sM9);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ps.epsM[c] = bez9(emis + c * N + bM, sM9);
+      ps.etaM[c] = bez9(prop + c * N + bM, sM9);
+    }
+  }
   ps.kapO = (double)kappa[bO];
   ps.ikM = 1.0 / ps.kapM;
   ps.ikO = 1.0 / ps.kapO;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    ps.epsM[c] = bil(emis + c * N + bM, ps.sM);
-    ps.etaM[c] = bil(prop + c * N + bM, ps.sM);
     ps.epsO[c] = (double)emis[c * N + bO];
     ps.etaO[c] = (double)prop[c * N + bO];
   }
@@ -197,12 +252,20 @@ __device__ inline void setup_point(const T* __restrict__ kappa, const T* __restr
   ps.hasP = kP >= 0;
   if (ps.hasP) {
     ps.dsP = dzP * inv_mu;
-    const Stencil sP = make_stencil(i, j, nx, ny, ps.dsP * rc.sx * inv_dx, ps.dsP * rc.sy * inv_dy);
+    const double uP = ps.dsP * rc.sx * inv_dx, vP = ps.dsP * rc.sy * inv_dy;
     const size_t bP = (size_t)kP * np;
-    ps.kapP = bil(kappa + bP, sP);
-    ps.ikP = 1.0 / ps.kapP;
+    if (MODE == 0) {
+      const Stencil sP = make_stencil(i, j, nx, ny, uP, vP);
+      ps.kapP = bil(kappa + bP, sP);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) ps.epsP[c] = bil(emis + c * N + bP, sP);
+      for (int c = 0; c < 6; ++c) ps.epsP[c] = bil(emis + c * N + bP, sP);
+    } else {
+      const Stencil9 sP = make_stencil9(i, j, nx, ny, uP, vP);
+      ps.kapP = bez9(kappa + bP, sP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ps.epsP[c] = bez9(emis + c * N + bP, sP);
+    }
+    ps.ikP = 1.0 / ps.kapP;
     ps.tau0P = 0.5 * (ps.kapO + ps.kapP) * ps.dsP;
     ps.ratio = ps.tau0M / ps.tau0P;
 #pragma unroll
@@ -355,8 +418,26 @@ __device__ inline void load_upwind(const T* __restrict__ q, const Stencil& s, T 
   load4(q + 4 * (size_t)s.i11, v[3]);
 }
 
+// Upwind Stokes vector of one frequency by the 9-point monotonic Bezier (mode B).
 template <class T>
-__global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
+__device__ inline void upwind_bez9(const T* __restrict__ q, const Stencil9& s,
+                                   const BezW<T>& wx, const BezW<T>& wy, T IM[4]) {
+  T v[3][3][4];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) load4(q + 4 * (size_t)(s.row[b] + s.col[a]), v[b][a]);
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    T r[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) r[b] = bez_eval(wx, v[b][0][st], v[b][1][st], v[b][2][st]);
+    IM[st] = bez_eval(wy, r[0], r[1], r[2]);
+  }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_plane(const PlaneArgs<T> a) {
   // per-frequency weights and profile, read from LDS inside the frequency loop so that
   // no vector-memory wait (which on gfx9 also covers earlier stores) sits in the loop
   extern __shared__ double s_tab[];
@@ -377,8 +458,11 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
                   a.jpart_prev == nullptr, (double)a.ibound);
   const RayConsts& rc = a.rays[a.ray0 + rb];
   PointSetup ps;
-  setup_point(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM, a.dzP,
-              a.inv_dx, a.inv_dy, rc, pp, ps);
+  Stencil9 sM9;
+  setup_point<MODE>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
+                    a.dzP, a.inv_dx, a.inv_dy, rc, pp, ps, sM9);
+  const BezW<T> bwx = bez_weights(MODE == 1 ? (T)sM9.tx : T(0));
+  const BezW<T> bwy = bez_weights(MODE == 1 ? (T)sM9.ty : T(0));
   const Stencil& sM = ps.sM;
   const double ikM = ps.ikM, ikO = ps.ikO;
   const double* etaM = ps.etaM;
@@ -413,16 +497,9 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
   if (!active) return;   // no barrier follows
 
   // one update (Eq. fsbez solved with Eq. kappa) at frequency f from the upwind
-  // corner values v (or the boundary value when there is no upwind plane)
-  auto update = [&](int f, const T (&v)[4][4]) {
-    T IM[4];
-    if (ip) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) IM[s] = w00 * v[0][s] + w10 * v[1][s] + w01 * v[2][s] + w11 * v[3][s];
-    } else {
-      IM[0] = a.ibound;
-      IM[1] = IM[2] = IM[3] = T(0);
-    }
+  // Stokes vector IM
+  auto update = [&](int f, T i0, T i1, T i2, T i3) {
+    const T IM[4] = {i0, i1, i2, i3};
     const T tau = tau0 * s_phi[f];
     const Coefs<T> cf = coefficients(tau);
     T KI[4];
@@ -443,27 +520,40 @@ __global__ void __launch_bounds__(256) k_sweep_plane(const PlaneArgs<T> a) {
     jacc3 += W * (double)x[3];
     lacc += W * (double)(cf.omO + lf * cf.omC);
   };
+  // bilinear upwind component s from the four corner values
+#define PORTA_BILIN(v, s) (w00 * v[0][s] + w10 * v[1][s] + w01 * v[2][s] + w11 * v[3][s])
 
-  if (SweepTraits<T>::kPrefetch) {
+  if (!ip) {
+    // the upwind plane is the boundary
+    for (int f = 0; f < a.nfreq; ++f) update(f, a.ibound, T(0), T(0), T(0));
+  } else if (MODE == 1) {
+    for (int f = 0; f < a.nfreq; ++f) {
+      T IM[4];
+      upwind_bez9(ip + (size_t)f * fstride, sM9, bwx, bwy, IM);
+      update(f, IM[0], IM[1], IM[2], IM[3]);
+    }
+  } else if (SweepTraits<T>::kPrefetch) {
     // two register sets for the upwind values: the loads of frequency f + 1 are in
     // flight while frequency f is computed
-    T va[4][4] = {}, vb[4][4] = {};
-    if (ip) load_upwind(ip, sM, va);
+    T va[4][4], vb[4][4];
+    load_upwind(ip, sM, va);
     for (int f = 0; f < a.nfreq; f += 2) {
       const bool has1 = f + 1 < a.nfreq;
-      if (ip && has1) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vb);
-      update(f, va);
+      if (has1) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vb);
+      update(f, PORTA_BILIN(va, 0), PORTA_BILIN(va, 1), PORTA_BILIN(va, 2), PORTA_BILIN(va, 3));
       if (!has1) break;
-      if (ip && f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, va);
-      update(f + 1, vb);
+      if (f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, va);
+      update(f + 1, PORTA_BILIN(vb, 0), PORTA_BILIN(vb, 1), PORTA_BILIN(vb, 2),
+             PORTA_BILIN(vb, 3));
     }
   } else {
-    T v[4][4] = {};
+    T v[4][4];
     for (int f = 0; f < a.nfreq; ++f) {
-      if (ip) load_upwind(ip + (size_t)f * fstride, sM, v);
-      update(f, v);
+      load_upwind(ip + (size_t)f * fstride, sM, v);
+      update(f, PORTA_BILIN(v, 0), PORTA_BILIN(v, 1), PORTA_BILIN(v, 2), PORTA_BILIN(v, 3));
     }
   }
+#undef PORTA_BILIN
   if (a.jpart) {
     double* jp = a.jpart + (size_t)rb * 5 * a.np + p;
     jp[0] = jacc0;

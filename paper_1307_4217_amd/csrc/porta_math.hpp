@@ -155,6 +155,65 @@ __host__ __device__ inline double besser_cm(double yM, double yO, double yP, dou
   return cM;
 }
 
+// The same control point in the sweep precision, for interpolation on the grid.
+template <class T>
+__host__ __device__ inline T besser_cm_t(T yM, T yO, T yP, T r) {
+  const T dM = yO - yM, dP = yP - yO;
+  if (dM * dP <= T(0)) return yO;
+  const T inv = T(0.5) / (T(1) + r);
+  const T cM = yO - (r * r * dP + dM) * inv;
+  if ((cM - yM) * (cM - yO) > T(0)) return yM;
+  const T cP = yO + (r * dP + dM / r) * inv;
+  if ((cP - yO) * (cP - yP) > T(0)) return yO - r * dP;
+  return cM;
+}
+
+// Monotonic quadratic Bezier interpolation through three equidistant nodes at
+// -1, 0, +1, evaluated at t in [-1/2, 1/2].  Each interval takes the BESSER
+// control point (Sect. 3.2) of the triple read towards it, so the value does not
+// depend on the reading direction and reduces to the Lagrange parabola when
+// nothing is clamped.
+//
+// With equal spacing (ratio 1) the BESSER branches collapse.  Let d1 = y0 - ym,
+// d2 = yp - y0.  If d1 and d2 differ in sign the control point is y0.  Otherwise
+// the parabola's tangent point y0 +- (d1 + d2)/4 overshoots ym exactly when
+// |d2| > 3|d1| (clamped to ym = y0 - d1) and its mirror overshoots yp exactly
+// when |d1| > 3|d2| (giving y0 - d2 on the upwind side), so both control points
+// are y0 -+ q with q = sign(d1) min(|d1|, |d2|, |d1 + d2|/4).  The spline value is
+// then linear in (ym, y0, yp, q) with weights that depend on t alone:
+//   t >= 0:  (1-t)^2 y0 + 2t(1-t)(y0 + q) + t^2 yp
+//   t <  0:  t^2 ym + 2(1+t)(-t)(y0 - q) + (1+t)^2 y0
+// i.e. a ym + (1 - t^2) y0 + c yp + 2t(1 - |t|) q with a = t^2 [t<0], c = t^2 [t>=0].
+template <class T>
+struct BezW {
+  T a, b, c, e;
+};
+
+template <class T>
+__host__ __device__ inline BezW<T> bez_weights(T t) {
+  const T t2 = t * t;
+  BezW<T> w;
+  w.a = (t < T(0)) ? t2 : T(0);
+  w.b = T(1) - t2;
+  w.c = (t < T(0)) ? T(0) : t2;
+  w.e = T(2) * t * (T(1) - fabs(t));
+  return w;
+}
+
+template <class T>
+__host__ __device__ inline T bez_eval(const BezW<T>& w, T ym, T y0, T yp) {
+  const T d1 = y0 - ym, d2 = yp - y0;
+  const T m = fmin(fmin(fabs(d1), fabs(d2)), T(0.25) * fabs(d1 + d2));
+  // a zero difference gives m = 0, so only opposite strict signs need the test
+  const T q = ((d1 > T(0)) == (d2 > T(0))) ? copysign(m, d1) : T(0);
+  return w.a * ym + w.b * y0 + w.c * yp + w.e * q;
+}
+
+template <class T>
+__host__ __device__ inline T bezier3(T ym, T y0, T yp, T t) {
+  return bez_eval(bez_weights(t), ym, y0, yp);
+}
+
 // BESSER control point together with its partial derivatives
 // d = (dc/dy_M, dc/dy_O, dc/dy_P, dc/dr), following the same branches.
 __host__ __device__ inline double besser_cm_grad(double yM, double yO, double yP, double r,

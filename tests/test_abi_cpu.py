@@ -124,3 +124,14 @@ def test_other_entry_points_validate():
     assert (porta.workspace_size(hg, porta.F32, porta.WS_ADJOINT_CKPT, 4)
             < porta.workspace_size(hg, porta.F32, porta.WS_ADJOINT, 4))
     assert porta.lib().porta_strerror(-3) == b"workspace too small"
+
+
+def test_adjoint_rejects_bezier_mode():
+    L = porta.lib()
+    hg = small_hg()
+    dummy = np.zeros(8)
+    f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
+    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0,
+                              porta.BEZIER2D, None, dummy.ctypes.data, None, 4,
+                              dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
+                              dummy.ctypes.data, 1 << 40, None) == -2

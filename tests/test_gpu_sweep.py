@@ -167,3 +167,42 @@ def test_jacobi_iterations_c1_match_oracle(orc):
         s_host, emis_host, rc_ref = orc.see_update(ref["jkq"], s_host, atm)
         np.testing.assert_allclose(S.cpu().numpy(), s_host, rtol=1e-10, atol=1e-12)
         assert rc.item() == pytest.approx(rc_ref, rel=1e-8)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_bezier2d_mode_matches_oracle(orc, prec):
+    """Mode B (9-point monotonic Bezier at M and P) on the 16x16x32 instance and a ragged
+    plane, against the oracle's interpolation mode 1.
+
+    Single precision: the clamps act on each Stokes component and multipole separately, so
+    at a few outputs the emergent Q/I, U/I, V/I respond to input rounding about a hundred
+    times more than in the bilinear mode (the oracle itself moves Q/I by 1.7e-7 at this
+    case when its emissivities take one single-precision rounding).  The 1e-7 bound holds
+    for 99.9% of the outputs; the rest are capped at 1e-6."""
+    import torch
+    for cfg, seed in ((inputs.CONFIGS["C1"], 0), (inputs.Config("rag", 7, 5, 9, 2, 3, 5, True), 4)):
+        atm = inputs.make_atmosphere(cfg, seed=seed)
+        if cfg.name == "rag":
+            atm = dataclasses.replace(atm, lx=530.0, ly=410.0)
+        if prec == porta.F32:
+            atm = rounded(atm, np.float32)
+        q = inputs.make_quadrature(cfg)
+        ref = orc.fs_sweep(orc.OracleProblem(atm, q, interp=1))
+        jkq, itop = Case(atm, q, prec).sweep(interp=porta.BEZIER2D)
+        want = up_rays(ref["itop"], q)
+        what = f"bezier2d {cfg.name}"
+        if prec == porta.F64:
+            compare_stokes(itop, want, 1e-10, 1e-12, what)
+            compare_jkq(jkq, ref["jkq"], 1e-10, what)
+        else:
+            rel = np.abs(itop[..., 0] - want[..., 0]) / np.abs(want[..., 0])
+            assert rel.max() <= 2e-5, f"{what} Stokes I max rel err {rel.max():.3e}"
+            for s_, name in ((1, "Q/I"), (2, "U/I"), (3, "V/I")):
+                d = np.abs(itop[..., s_] / itop[..., 0] - want[..., s_] / want[..., 0])
+                print(f"{what} {name}: max {d.max():.3e}, 99.9% {np.quantile(d, 0.999):.3e}")
+                assert np.quantile(d, 0.999) <= 1e-7 and d.max() <= 1e-6, f"{what} {name}"
+            compare_jkq(jkq, ref["jkq"], 2e-5, what)
+        # and it is a different interpolation from the bilinear one
+        _, it_bl = Case(atm, q, prec).sweep()
+        assert np.abs(it_bl - itop).max() > 1e-6
+        torch.cuda.synchronize()

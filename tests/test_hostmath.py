@@ -22,6 +22,10 @@ def hm():
     L.hm_coefficients_f64.argtypes = [C.c_double, _dp]
     L.hm_besser_cm.argtypes = [C.c_double] * 4
     L.hm_besser_cm.restype = C.c_double
+    L.hm_bezier3_f64.argtypes = [C.c_double] * 4
+    L.hm_bezier3_f64.restype = C.c_double
+    L.hm_bezier3_f32.argtypes = [C.c_float] * 4
+    L.hm_bezier3_f32.restype = C.c_float
     L.hm_solve_stokes_f64.argtypes = [_dp] * 4
     L.hm_solve_stokes_f32.argtypes = [_fp] * 4
     L.hm_kprime_apply.argtypes = [_dp] * 4
@@ -188,3 +192,33 @@ def test_coefficient_tau_derivatives(hm):
             assert got == pytest.approx(fd, rel=1e-6, abs=4e-16 / h), (tau, k)
             got32 = hm.hm_coef_tau_grad_f32(np.float32(tau), p(g.astype(np.float32)))
             assert got32 == pytest.approx(got, rel=2e-4, abs=1e-6), (tau, k)
+
+
+def test_bezier3_closed_form_equals_branchy_besser(hm, orc):
+    """The kernels' branch-free equidistant Bezier (weights in t, limited slope
+    min(|d1|, |d2|, |d1 + d2|/4)) against the oracle's BESSER steps with ratio 1, on random
+    triples, triples near each branch switch (d2 = 3 d1, d1 = 3 d2, a zero difference) and
+    both halves of the interval."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for _ in range(4000):
+        y0 = rng.standard_normal()
+        d1, d2 = rng.standard_normal(2)
+        kind = rng.integers(0, 6)
+        if kind == 1:
+            d2 = 3 * d1 * (1 + rng.choice([-1, 1]) * 1e-9)
+        elif kind == 2:
+            d1 = 3 * d2 * (1 + rng.choice([-1, 1]) * 1e-9)
+        elif kind == 3:
+            d2 = 0.0
+        elif kind == 4:
+            d1 = abs(d1) * np.sign(d2)   # monotone
+        cases.append((y0 - d1, y0, y0 + d2, rng.uniform(-0.5, 0.5)))
+    cases += [(0.0, 1.0, 2.0, 0.5), (2.0, 1.0, 0.0, -0.5), (1.0, 1.0, 1.0, 0.3), (0.0, 1.0, 0.0, 0.0)]
+    scale = 1.0
+    for ym, y0, yp, t in cases:
+        ref = orc.bezier1d(ym, y0, yp, t)
+        scale = max(abs(ym), abs(y0), abs(yp), 1.0)
+        assert hm.hm_bezier3_f64(ym, y0, yp, t) == pytest.approx(ref, abs=4e-16 * scale)
+        f = hm.hm_bezier3_f32(ym, y0, yp, t)
+        assert f == pytest.approx(ref, abs=3e-6 * scale)

@@ -225,6 +225,44 @@ def test_bezier2d_no_overshoot(orc):
         assert blk.min() - 1e-9 <= v <= blk.max() + 1e-9
 
 
+
+def test_bezier1d_continuous_where_monotonicity_switches(orc):
+    """Sect. 3.2: a triple with an extremum at O takes c_M = y_O.  On the monotone side of
+    that switch the downwind control point c_O overshoots y_P, is clamped to it, and the
+    derivative it implies gives c_M = y_O - (y_P - y_O) h_M/h_P, so c_M meets y_O again at
+    the switch: the spline is continuous in its nodes (Lipschitz, not smooth)."""
+    for eps in (1e-7, 1e-12):
+        up = orc.bezier1d(1.0 + eps, 1.0, 0.0, 0.5)    # monotone: c_M = 1 - eps
+        down = orc.bezier1d(1.0 - eps, 1.0, 0.0, 0.5)  # extremum at O: c_M = 1
+        assert up == pytest.approx(0.25 + 0.5 * (1.0 - eps), abs=1e-15)
+        assert down == pytest.approx(0.75, abs=1e-15)
+        assert abs(down - up) <= eps
+
+
+def test_bezier2d_mode_is_worse_conditioned_but_continuous(orc):
+    """Relative noise on the emissivities, of the size of one single-precision rounding,
+    moves the 9-point mode's emergent Q/I, U/I, V/I several times more than the bilinear
+    mode's (each multipole and Stokes component is clamped on its own), and the response
+    is linear in the noise amplitude (no jump anywhere)."""
+    from paper_1307_4217_amd import inputs
+    cfg = inputs.Config("s", 12, 12, 16, 2, 4, 9, True)
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    q = inputs.make_quadrature(cfg)
+    noise = np.random.default_rng(1).standard_normal(atm.emis.shape)
+
+    def response(interp, amp):
+        a = orc.fs_sweep(orc.OracleProblem(atm, q, interp=interp))["itop"]
+        pert = type(atm)(**{**atm.__dict__, "emis": atm.emis * (1 + amp * noise)})
+        b = orc.fs_sweep(orc.OracleProblem(pert, q, interp=interp))["itop"]
+        m = a[..., 0] > 0
+        return max(np.abs(b[..., s][m] / b[..., 0][m] - a[..., s][m] / a[..., 0][m]).max()
+                   for s in (1, 2, 3))
+    r0, r1, r1_small = response(0, 6e-8), response(1, 6e-8), response(1, 6e-10)
+    assert r0 < 1e-8
+    assert r1 > 5 * r0
+    assert r1_small * 100 == pytest.approx(r1, rel=0.02)
+
+
 # --------------------------------------------------------------------------- P12 T^K_Q
 def _basis(mu, chi):
     st = math.sqrt(max(0.0, 1 - mu * mu))
