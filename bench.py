@@ -226,7 +226,7 @@ def main():
     lbytes, lupd = sweep_launch_bytes(cfg, nrb, elem)
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
-    kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}>"
+    kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
     traffic = measured_traffic(kname, cfg.name == "C3" and nrb == 40 and args.block in (0, 256))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
