@@ -60,7 +60,10 @@ def lib():
             L.oracle_jkq_accumulate.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, C.c_int,
                                                 C.c_int, _dp, _dp, _dp]
             L.oracle_see_update.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double,
-                                            C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+                                            C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp,
+                                            _dp, _dp]
+            L.oracle_see_operator.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double,
+                                              C.c_double, _dp, _dp, _dp]
             L.oracle_coefficients.argtypes = [C.c_double, _dp]
             L.oracle_besser_cm.argtypes = [C.c_double] * 5
             L.oracle_besser_cm.restype = C.c_double
@@ -204,8 +207,9 @@ def jkq_accumulate(op: OracleProblem, ray0, f0, stokes, lam=None, jkq=None):
     return jkq
 
 
-def see_update(jkq, s_old, atm, kappa=None):
-    """One Jacobi update of the two-level SEE; returns (s_new, emis_new, rc)."""
+def see_update(jkq, s_old, atm, kappa=None, rhs=None):
+    """One Jacobi update of the two-level SEE; returns (s_new, emis_new, rc).
+    rhs [6][N] replaces the right-hand side (eps B, 0, ...) when given."""
     L = lib()
     jkq = _f64(jkq)
     s_old = _f64(s_old)
@@ -215,16 +219,33 @@ def see_update(jkq, s_old, atm, kappa=None):
     kap = _f64(atm.kappa if kappa is None else kappa)
     hanle = _f64(atm.hanle)
     bhat = _f64(atm.bhat)
+    rhs = _f64(rhs)
     rc = C.c_double(0.0)
     nul = C.cast(None, _dp)
+    opt = lambda a: _d(a) if a is not None else nul
     st = L.oracle_see_update(n, _d(jkq), _d(s_old), float(atm.eps_c), float(atm.delta2),
-                             float(atm.w2), float(atm.planck),
-                             _d(hanle) if hanle is not None else nul,
-                             _d(bhat) if bhat is not None else nul, _d(kap), _d(s_new),
-                             _d(emis_new), C.byref(rc))
+                             float(atm.w2), float(atm.planck), opt(hanle), opt(bhat), opt(rhs),
+                             _d(kap), _d(s_new), _d(emis_new), C.byref(rc))
     if st != 0:
         raise ValueError("oracle_see_update rejected its inputs")
     return s_new, emis_new, rc.value
+
+
+def see_operator(jkq, s, atm):
+    """L(rho) rho of the two-level SEE (left-hand side of Eq. nonlte), [6][N]."""
+    L = lib()
+    jkq = _f64(jkq)
+    s = _f64(s)
+    out = np.zeros_like(s)
+    hanle = _f64(atm.hanle)
+    bhat = _f64(atm.bhat)
+    nul = C.cast(None, _dp)
+    st = L.oracle_see_operator(s.shape[1], _d(jkq), _d(s), float(atm.eps_c), float(atm.delta2),
+                               float(atm.w2), _d(hanle) if hanle is not None else nul,
+                               _d(bhat) if bhat is not None else nul, _d(out))
+    if st != 0:
+        raise ValueError("oracle_see_operator rejected its inputs")
+    return out
 
 
 def coefficients(tau: float) -> np.ndarray:

@@ -727,57 +727,99 @@ int oracle_jkq_accumulate(const oracle_problem* pb, int ray0, int nray, int f0, 
   return 0;
 }
 
-/* One Jacobi update of the two-level (J_l = 0 -> J_u = 1) statistical
- * equilibrium at every point.  s_old / s_new are [6][N] in the order
- * S00, S20, Re S21, Im S21, Re S22, Im S22.
+/* The two-level (J_l = 0 -> J_u = 1) statistical equilibrium written as
+ * L(rho) rho = f (Sect. 2, Eq. nonlte), with the source-function multipoles
+ * S^K_Q standing for the unknowns, stored [6][N] in the order
+ * S00, S20, Re S21, Im S21, Re S22, Im S22:
+ *   K = 0:  S00 - (1-eps) J00                                     = f_0
+ *   K = 2:  [1 + delta (1-eps)] S2_Q + i (1-eps) H sum_Q' Kmat_QQ'(b) S2_Q'
+ *              - (1-eps) w2 conj(J2_Q)                             = f2_Q   (Q = -2..2)
+ * with Kmat the matrix of b.J in the rank-2 representation; f = (eps B, 0, ...)
+ * for the problem itself, another right-hand side on the coarse grids of the
+ * multigrid iteration (Sect. 6, Eq. mgcsfy).  Components with Q < 0 follow from
+ * X_{-Q} = (-1)^Q conj(X_Q) for S, J and f alike. */
+namespace {
+
+struct SeeAtom {
+  double eps_c, delta2, w2, planck;
+  const double* hanle;
+  const double* bhat;
+};
+
+/* Five K = 2 components Q = -2..2 from the three stored Q >= 0 ones. */
+void unfold_k2(double x0, double re1, double im1, double re2, double im2, cd out[5]) {
+  out[2] = cd(x0, 0.0);
+  out[3] = cd(re1, im1);
+  out[4] = cd(re2, im2);
+  out[1] = -std::conj(out[3]);
+  out[0] = std::conj(out[4]);
+}
+
+/* The 5x5 matrix acting on S2_Q at point p. */
+void k2_matrix(const SeeAtom& at, size_t N, size_t p, cd A[5][5]) {
+  const double H = at.hanle ? at.hanle[p] : 0.0;
+  const double bx = at.bhat ? at.bhat[0 * N + p] : 0.0, by = at.bhat ? at.bhat[1 * N + p] : 0.0,
+               bz = at.bhat ? at.bhat[2 * N + p] : 1.0;
+  const double om = 1.0 - at.eps_c;
+  for (int a = 0; a < 5; ++a)
+    for (int c = 0; c < 5; ++c) A[a][c] = 0.0;
+  for (int qi = 0; qi < 5; ++qi) {
+    const int Q = qi - 2;
+    A[qi][qi] += 1.0 + at.delta2 * om;
+    A[qi][qi] += cd(0.0, om * H) * cd(bz * Q, 0.0);   // b_z Q on the diagonal
+  }
+  for (int qpi = 0; qpi < 5; ++qpi) {
+    const int Qp = qpi - 2;
+    if (Qp + 1 <= 2) {  // <Q'+1| b.J |Q'>
+      const cd v = 0.5 * cd(bx, -by) * std::sqrt(6.0 - Qp * (Qp + 1.0));
+      A[qpi + 1][qpi] += cd(0.0, om * H) * v;
+    }
+    if (Qp - 1 >= -2) {  // <Q'-1| b.J |Q'>
+      const cd v = 0.5 * cd(bx, by) * std::sqrt(6.0 - Qp * (Qp - 1.0));
+      A[qpi - 1][qpi] += cd(0.0, om * H) * v;
+    }
+  }
+}
+
+void f_at(const SeeAtom& at, const double* rhs, size_t N, size_t p, double& f0, cd f2[5]) {
+  if (rhs) {
+    f0 = rhs[p];
+    unfold_k2(rhs[1 * N + p], rhs[2 * N + p], rhs[3 * N + p], rhs[4 * N + p], rhs[5 * N + p], f2);
+  } else {
+    f0 = at.eps_c * at.planck;
+    for (int q = 0; q < 5; ++q) f2[q] = 0.0;
+  }
+}
+
+}  // namespace
+
+/* One Jacobi update at every point:
  *   K = 0 (Jacobi with Lambda-bar):
- *     S00 <- [(1-eps)(J00 - Lbar S00_old) + eps B] / [1 - (1-eps) Lbar]
- *   K = 2 (Lambda iteration with Hanle rotation), Q = -2..2:
- *     [1 + delta (1-eps)] S2_Q + i (1-eps) H sum_Q' Kmat_QQ'(b) S2_Q' = (1-eps) w2 conj(J2_Q)
- *     with Kmat the matrix of b.J in the rank-2 representation.
- * emis_new (= kappa * S_new) may be NULL; rc = max |dS00| / |S00_new|. */
+ *     S00 <- [(1-eps)(J00 - Lbar S00_old) + f_0] / [1 - (1-eps) Lbar]
+ *   K = 2 (Lambda iteration with Hanle rotation): solve the K = 2 equations above
+ *     for S2 with J2 from the last formal solution.
+ * rhs [6][N] or NULL for (eps B, 0, ...).  emis_new (= kappa * S_new) may be NULL;
+ * rc = max |dS00| / |S00_new|. */
 int oracle_see_update(int n, const double* jkq, const double* s_old, double eps_c, double delta2,
                       double w2, double planck, const double* hanle, const double* bhat,
-                      const double* kappa, double* s_new, double* emis_new, double* rc) {
+                      const double* rhs, const double* kappa, double* s_new, double* emis_new,
+                      double* rc) {
   if (n < 0 || !jkq || !s_old || !s_new) return -1;
   const size_t N = (size_t)n;
+  const SeeAtom at{eps_c, delta2, w2, planck, hanle, bhat};
   double rmax = 0.0;
   for (size_t p = 0; p < N; ++p) {
     const double J00 = jkq[0 * N + p], Lb = jkq[9 * N + p];
     const double so = s_old[p];
-    const double s00 = ((1.0 - eps_c) * (J00 - Lb * so) + eps_c * planck) / (1.0 - (1.0 - eps_c) * Lb);
-    /* J^2_Q for Q = -2..2 from the stored Q >= 0 components */
+    double f0;
+    cd f2[5];
+    f_at(at, rhs, N, p, f0, f2);
+    const double s00 = ((1.0 - eps_c) * (J00 - Lb * so) + f0) / (1.0 - (1.0 - eps_c) * Lb);
     cd J2[5];
-    J2[2] = cd(jkq[4 * N + p], 0.0);
-    J2[3] = cd(jkq[5 * N + p], jkq[6 * N + p]);
-    J2[4] = cd(jkq[7 * N + p], jkq[8 * N + p]);
-    J2[1] = -std::conj(J2[3]);
-    J2[0] = std::conj(J2[4]);
-    const double H = hanle ? hanle[p] : 0.0;
-    const double bx = bhat ? bhat[0 * N + p] : 0.0, by = bhat ? bhat[1 * N + p] : 0.0,
-                 bz = bhat ? bhat[2 * N + p] : 1.0;
-    cd A[5][5], rhs[5], x[5];
-    for (int a = 0; a < 5; ++a)
-      for (int c = 0; c < 5; ++c) A[a][c] = 0.0;
-    for (int qi = 0; qi < 5; ++qi) {
-      const int Q = qi - 2;
-      A[qi][qi] += 1.0 + delta2 * (1.0 - eps_c);
-      /* b.J: diagonal b_z Q; raising and lowering parts */
-      cd kd(bz * Q, 0.0);
-      A[qi][qi] += cd(0.0, (1.0 - eps_c) * H) * kd;
-      rhs[qi] = (1.0 - eps_c) * w2 * std::conj(J2[qi]);
-    }
-    for (int qpi = 0; qpi < 5; ++qpi) {
-      const int Qp = qpi - 2;
-      if (Qp + 1 <= 2) {  // <Q'+1| b.J |Q'>
-        const cd v = 0.5 * cd(bx, -by) * std::sqrt(6.0 - Qp * (Qp + 1.0));
-        A[qpi + 1][qpi] += cd(0.0, (1.0 - eps_c) * H) * v;
-      }
-      if (Qp - 1 >= -2) {  // <Q'-1| b.J |Q'>
-        const cd v = 0.5 * cd(bx, by) * std::sqrt(6.0 - Qp * (Qp - 1.0));
-        A[qpi - 1][qpi] += cd(0.0, (1.0 - eps_c) * H) * v;
-      }
-    }
+    unfold_k2(jkq[4 * N + p], jkq[5 * N + p], jkq[6 * N + p], jkq[7 * N + p], jkq[8 * N + p], J2);
+    cd A[5][5], b[5], x[5];
+    k2_matrix(at, N, p, A);
+    for (int qi = 0; qi < 5; ++qi) b[qi] = (1.0 - eps_c) * w2 * std::conj(J2[qi]) + f2[qi];
     /* complex Gaussian elimination with partial pivoting */
     for (int c = 0; c < 5; ++c) {
       int piv = c;
@@ -785,16 +827,16 @@ int oracle_see_update(int n, const double* jkq, const double* s_old, double eps_
         if (std::abs(A[r][c]) > std::abs(A[piv][c])) piv = r;
       if (piv != c) {
         for (int k = 0; k < 5; ++k) std::swap(A[c][k], A[piv][k]);
-        std::swap(rhs[c], rhs[piv]);
+        std::swap(b[c], b[piv]);
       }
       for (int r = c + 1; r < 5; ++r) {
         const cd fct = A[r][c] / A[c][c];
         for (int k = c; k < 5; ++k) A[r][k] -= fct * A[c][k];
-        rhs[r] -= fct * rhs[c];
+        b[r] -= fct * b[c];
       }
     }
     for (int r = 4; r >= 0; --r) {
-      cd sacc = rhs[r];
+      cd sacc = b[r];
       for (int k = r + 1; k < 5; ++k) sacc -= A[r][k] * x[k];
       x[r] = sacc / A[r][r];
     }
@@ -810,6 +852,33 @@ int oracle_see_update(int n, const double* jkq, const double* s_old, double eps_
     if (rel > rmax) rmax = rel;
   }
   if (rc) *rc = rmax;
+  return 0;
+}
+
+/* The left-hand side L(rho) rho of the equations above at every point, [6][N],
+ * for the multipoles s and the radiation field jkq of their formal solution. */
+int oracle_see_operator(int n, const double* jkq, const double* s, double eps_c, double delta2,
+                        double w2, const double* hanle, const double* bhat, double* out) {
+  if (n < 0 || !jkq || !s || !out) return -1;
+  const size_t N = (size_t)n;
+  const SeeAtom at{eps_c, delta2, w2, 0.0, hanle, bhat};
+  for (size_t p = 0; p < N; ++p) {
+    out[p] = s[p] - (1.0 - eps_c) * jkq[p];
+    cd S2[5], J2[5], A[5][5];
+    unfold_k2(s[1 * N + p], s[2 * N + p], s[3 * N + p], s[4 * N + p], s[5 * N + p], S2);
+    unfold_k2(jkq[4 * N + p], jkq[5 * N + p], jkq[6 * N + p], jkq[7 * N + p], jkq[8 * N + p], J2);
+    k2_matrix(at, N, p, A);
+    cd y[5];
+    for (int a = 0; a < 5; ++a) {
+      y[a] = -(1.0 - eps_c) * w2 * std::conj(J2[a]);
+      for (int c = 0; c < 5; ++c) y[a] += A[a][c] * S2[c];
+    }
+    out[1 * N + p] = y[2].real();
+    out[2 * N + p] = y[3].real();
+    out[3 * N + p] = y[3].imag();
+    out[4 * N + p] = y[4].real();
+    out[5 * N + p] = y[4].imag();
+  }
   return 0;
 }
 
