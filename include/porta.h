@@ -176,19 +176,83 @@ int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray
 
 /*
  * One Jacobi update of the two-level statistical equilibrium at every point
- * (Sect. 2 Eq. nonlte; Jacobi iteration of Sect. 5):
- *   S00 <- [(1-eps)(J00 - Lbar S00_old) + eps B] / [1 - (1-eps) Lbar]
+ * (Sect. 2 Eq. nonlte; Jacobi iteration of Sect. 5), for L(rho) rho = f with the
+ * right-hand side f = rhs, or f = (eps_c B, 0, 0, 0, 0, 0) when rhs is NULL:
+ *   S00 <- [(1-eps)(J00 - Lbar S00_old) + f_0] / [1 - (1-eps) Lbar]
  *   [1 + delta (1-eps)] S2_Q + i (1-eps) H_u sum_Q' <Q|b.J|Q'> S2_Q'
- *        = (1-eps) w2 conj(J2_Q)                        (Q = -2..2)
+ *        = (1-eps) w2 conj(J2_Q) + f2_Q                   (Q = -2..2)
+ *   rhs          : device [6][N] FP64 (S00, S20, Re S21, Im S21, Re S22, Im S22 rows
+ *                  of f; Q < 0 follows from f_-Q = (-1)^Q conj(f_Q)) or NULL
  *   s_old, s_new : device [6][N] FP64 source-function multipoles S^K_Q
  *   kappa        : device [N] (sweep precision), used for emis_out only
  *   emis_out     : device [6][N] (sweep precision) = kappa * S_new, or NULL
  *   rc_out       : device FP64 scalar, max_p |S00_new - S00_old| / |S00_new|,
  *                  or NULL (the convergence measure R_c of Sect. 5.3)
+ *   workspace    : device, >= porta_workspace_size(..., PORTA_WS_SEE, ...) when
+ *                  rc_out is given
  */
 int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
-                     const double* s_old, double* s_new, const void* kappa, void* emis_out,
-                     int prec, double* rc_out, void* workspace, size_t ws_bytes, void* stream);
+                     const double* rhs, const double* s_old, double* s_new, const void* kappa,
+                     void* emis_out, int prec, double* rc_out, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * The statistical-equilibrium operator of the two-level atom applied to its own
+ * unknowns, L(rho) rho of Sect. 2 Eq. nonlte (left-hand sides above, with J from
+ * the formal solution of these s), combined as
+ *   out = base + sign * L(rho) rho,   base = [6][N] FP64 or, if NULL, (eps_c B, 0, ...).
+ * sign = -1 gives the residual r = f - L(rho) rho of Sect. 6.1 Eq. resid; sign = +1
+ * with base = R(r) gives the coarse-grid right-hand side of Eq. mgcsfy.
+ *   jkq : device [10][N] FP64 (Lbar unused); s, out : device [6][N] FP64.
+ * out may not alias s or jkq; it may alias base.
+ */
+int porta_see_operator(int64_t npoints, const double* jkq, const porta_atom* atom,
+                       const double* s, const double* base, double sign, double* out,
+                       void* stream);
+
+/*
+ * Grid transfer of the multigrid iteration (Sect. 6.1-6.2).  The coarser grid keeps
+ * every second node along each axis: coarse node (i, j, k) is fine node (2i, 2j, 2k).
+ * The fine grid (nx, ny, nz) needs even nx, ny >= 2 (periodic; coarse nx/2, ny/2)
+ * and odd nz >= 3 (coarse (nz+1)/2); otherwise PORTA_EINVAL.  Fields are
+ * [ncomp][points] with x fastest, 1 <= ncomp <= 64.
+ *
+ * porta_mg_restrict: coarse = R(fine), at each coarse node the mean of the 3^3 fine
+ *   nodes around it weighted w(dx) w(dy) w(dz), w(0) = 1, w(+-1) = 1/2 (the adjoint
+ *   of tri-linear prolongation), over the nodes that exist (2 x 3^2 on a z boundary),
+ *   divided by the sum of those weights.  FP64.  If kappa_coarse (device [Nc], sweep
+ *   precision prec) is given, emis_coarse = kappa_coarse * coarse is written too
+ *   ([ncomp][Nc], sweep precision); both or neither.
+ */
+int porta_mg_restrict(int nx, int ny, int nz, int ncomp, const double* fine, double* coarse,
+                      const void* kappa_coarse, void* emis_coarse, int prec, void* stream);
+
+/*
+ * porta_mg_prolong: fine += P(coarse_a - coarse_b) (coarse_b may be NULL), P the
+ *   tri-linear prolongation of Sect. 6.2: a fine node on a coarse node takes its value,
+ *   one on a coarse line or plane the linear or bilinear mean, the others the
+ *   tri-linear mean of 8 coarse nodes.  FP64.  With kappa (device [Nf], precision
+ *   prec), emis = kappa * fine is written too ([ncomp][Nf]); both or neither.
+ */
+int porta_mg_prolong(int nx, int ny, int nz, int ncomp, const double* coarse_a,
+                     const double* coarse_b, double* fine, const void* kappa, void* emis,
+                     int prec, void* stream);
+
+/*
+ * porta_mg_inject: coarse = fine sampled at the coarse nodes, for model fields
+ *   (opacities, propagation matrix, magnetic field) of a coarser grid; elements of
+ *   elem_bytes = 4 or 8 bytes.
+ */
+int porta_mg_inject(int nx, int ny, int nz, int ncomp, int elem_bytes, const void* fine,
+                    void* coarse, void* stream);
+
+/*
+ * R_c between two iterates: rc_out (device FP64 scalar) = max_p |a_p - b_p| / |a_p|
+ * over the first npoints entries (S00 rows of two [6][N] arrays).  workspace as for
+ * porta_see_update.
+ */
+int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, double* rc_out,
+                     void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Reverse-mode derivative of a scalar loss L(i_top) through the sweep of the

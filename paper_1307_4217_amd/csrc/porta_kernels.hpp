@@ -603,6 +603,7 @@ __global__ void __launch_bounds__(256)
 template <class T>
 struct SeeArgs {
   const double* jkq;
+  const double* rhs;     // [6][N] replacing (eps_c B, 0, ...), or nullptr
   const double* s_old;
   double* s_new;
   const double* hanle;   // or nullptr
@@ -624,10 +625,16 @@ __global__ void __launch_bounds__(256) k_see(const SeeArgs<T> a) {
     const double oe = 1.0 - a.eps_c;
     const double J00 = a.jkq[p], Lb = a.jkq[9 * N + p];
     const double so = a.s_old[p];
-    const double s00 = (oe * (J00 - Lb * so) + a.eps_c * a.planck) / (1.0 - oe * Lb);
+    const double f0 = a.rhs ? a.rhs[p] : a.eps_c * a.planck;
+    const double s00 = (oe * (J00 - Lb * so) + f0) / (1.0 - oe * Lb);
     const double c = oe * a.w2;
+    // rows: Re, Re, Im, Re, Im of the K = 2 equations for Q = 0, 1, 1, 2, 2
     double x[5] = {c * a.jkq[4 * N + p], c * a.jkq[5 * N + p], -c * a.jkq[6 * N + p],
                    c * a.jkq[7 * N + p], -c * a.jkq[8 * N + p]};
+    if (a.rhs) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) x[q] += a.rhs[(q + 1) * N + p];
+    }
     const double ad = 1.0 + a.delta2 * oe;
     const double h = a.hanle ? oe * a.hanle[p] : 0.0;
     if (h != 0.0) {

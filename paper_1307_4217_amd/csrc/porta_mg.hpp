@@ -1,0 +1,201 @@
+// Kernels of the non-linear multigrid iteration (Sect. 6): the statistical-equilibrium
+// operator L(rho) rho, restriction, prolongation and injection between a grid and the
+// next coarser one, and the maximum relative change between two iterates.
+//
+// Grids: coarse node (i, j, k) is fine node (2i, 2j, 2k); x and y are periodic
+// (n_x, n_y even, coarse n_x / 2), z is not (n_z odd, coarse (n_z + 1) / 2).  Fields
+// are [c][N] with x fastest.
+#pragma once
+
+#include "porta_kernels.hpp"
+
+namespace porta {
+
+// ---------------------------------------------------------------------------
+// out = base + sign * L(rho) rho at every point, where (Sect. 2, Eq. nonlte, two-level
+// atom, S^K_Q standing for rho):
+//   K = 0:  S00 - (1-eps) J00
+//   K = 2:  [1 + delta (1-eps)] S2_Q + i (1-eps) H sum_Q' <Q|b.J|Q'> S2_Q' - (1-eps) w2 conj(J2_Q)
+// in the real rows (Q = 0, Re/Im Q = 1, Re/Im Q = 2) of the Jacobi update; base is
+// an array [6][N] or, when absent, (eps_c B, 0, ...).
+// ---------------------------------------------------------------------------
+struct SeeOpArgs {
+  const double* jkq;
+  const double* s;
+  const double* base;   // or nullptr
+  double* out;
+  const double* hanle;  // or nullptr
+  const double* bhat;   // or nullptr
+  size_t N;
+  double sign, eps_c, delta2, w2, planck;
+};
+
+__global__ void __launch_bounds__(256) k_see_operator(const SeeOpArgs a) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.N) return;
+  const size_t N = a.N;
+  const double oe = 1.0 - a.eps_c;
+  const double c = oe * a.w2;
+  double s2[5], y[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s2[q] = a.s[(q + 1) * N + p];
+  const double ad = 1.0 + a.delta2 * oe;
+  const double h = a.hanle ? oe * a.hanle[p] : 0.0;
+  if (h != 0.0) {
+    const double bx = a.bhat ? a.bhat[p] : 0.0;
+    const double by = a.bhat ? a.bhat[N + p] : 0.0;
+    const double bz = a.bhat ? a.bhat[2 * N + p] : 1.0;
+    double A[5][5];
+    hanle_system(ad, h, bx, by, bz, A);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) acc += A[r][k] * s2[k];
+      y[r] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) y[q] = ad * s2[q];
+  }
+  y[0] -= c * a.jkq[4 * N + p];
+  y[1] -= c * a.jkq[5 * N + p];
+  y[2] += c * a.jkq[6 * N + p];
+  y[3] -= c * a.jkq[7 * N + p];
+  y[4] += c * a.jkq[8 * N + p];
+  const double l0 = a.s[p] - oe * a.jkq[p];
+  a.out[p] = (a.base ? a.base[p] : a.eps_c * a.planck) + a.sign * l0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+    a.out[(q + 1) * N + p] = (a.base ? a.base[(q + 1) * N + p] : 0.0) + a.sign * y[q];
+}
+
+// ---------------------------------------------------------------------------
+// Restriction (Sect. 6.2): thread = coarse node; the weighted mean of the 3^3 fine
+// nodes around it with weights w(dx) w(dy) w(dz), w(0) = 1, w(+-1) = 1/2 (the adjoint
+// of tri-linear prolongation), over the nodes that exist (2 x 3^2 at a z boundary),
+// for ncomp components.  Optionally also emis = kappa_c * out in the sweep precision.
+// ---------------------------------------------------------------------------
+template <class T>
+struct RestrictArgs {
+  const double* f;
+  double* out;
+  const T* kappa_c;  // or nullptr
+  T* emis_c;         // or nullptr
+  int nx, ny, nz, ncomp;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_restrict(const RestrictArgs<T> a) {
+  const int nxc = a.nx / 2, nyc = a.ny / 2, nzc = (a.nz + 1) / 2;
+  const size_t Nc = (size_t)nxc * nyc * nzc, Nf = (size_t)a.nx * a.ny * a.nz;
+  const size_t pc = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pc >= Nc) return;
+  const int ic = (int)(pc % nxc), jc = (int)((pc / nxc) % nyc), kc = (int)(pc / ((size_t)nxc * nyc));
+  int col[3], row[3];
+  const double w[3] = {0.5, 1.0, 0.5};
+  for (int d = 0; d < 3; ++d) {
+    col[d] = wrapi(2 * ic + d - 1, a.nx);
+    row[d] = wrapi(2 * jc + d - 1, a.ny);
+  }
+  const int dz0 = (kc == 0) ? 1 : 0, dz1 = (kc == nzc - 1) ? 1 : 2;
+  const double wz = (dz0 == 0 && dz1 == 2) ? 2.0 : 1.5;
+  const double inv = 1.0 / (4.0 * wz);
+  for (int c = 0; c < a.ncomp; ++c) {
+    const double* fc = a.f + (size_t)c * Nf;
+    double acc = 0.0;
+    for (int dz = dz0; dz <= dz1; ++dz) {
+      const double* plane = fc + (size_t)(2 * kc + dz - 1) * a.nx * a.ny;
+      double ap = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const double* r = plane + (size_t)row[dy] * a.nx;
+        ap += w[dy] * (0.5 * r[col[0]] + r[col[1]] + 0.5 * r[col[2]]);
+      }
+      acc += w[dz] * ap;
+    }
+    const double v = acc * inv;
+    a.out[(size_t)c * Nc + pc] = v;
+    if (a.emis_c) a.emis_c[(size_t)c * Nc + pc] = (T)((double)a.kappa_c[pc] * v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tri-linear prolongation of a coarse difference (Sect. 6.2): thread = fine node;
+// fine += P(a - b) (b may be absent), where a fine node on a coarse node takes its
+// value, one on a coarse line or plane the linear or bilinear mean, the rest the
+// tri-linear mean of 8 coarse nodes.  Optionally emis = kappa * fine.
+// ---------------------------------------------------------------------------
+template <class T>
+struct ProlongArgs {
+  const double* ca;
+  const double* cb;   // or nullptr
+  double* fine;
+  const T* kappa;     // or nullptr
+  T* emis;            // or nullptr
+  int nx, ny, nz, ncomp;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_prolong(const ProlongArgs<T> a) {
+  const int nxc = a.nx / 2, nyc = a.ny / 2, nzc = (a.nz + 1) / 2;
+  const size_t Nc = (size_t)nxc * nyc * nzc, Nf = (size_t)a.nx * a.ny * a.nz;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Nf) return;
+  const int i = (int)(p % a.nx), j = (int)((p / a.nx) % a.ny), k = (int)(p / ((size_t)a.nx * a.ny));
+  // two coarse indices and weights per axis (the second weight 0 on coarse nodes)
+  const int x0 = i >> 1, x1 = (x0 + 1 == nxc) ? 0 : x0 + 1;
+  const int y0 = j >> 1, y1 = (y0 + 1 == nyc) ? 0 : y0 + 1;
+  const int z0 = k >> 1, z1 = (k & 1) ? z0 + 1 : z0;
+  const double wx1 = (i & 1) ? 0.5 : 0.0, wy1 = (j & 1) ? 0.5 : 0.0, wz1 = (k & 1) ? 0.5 : 0.0;
+  const double wx[2] = {1.0 - wx1, wx1}, wy[2] = {1.0 - wy1, wy1}, wz[2] = {1.0 - wz1, wz1};
+  const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+  for (int c = 0; c < a.ncomp; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const double w = wz[dz] * wy[dy] * wx[dx];
+          if (w == 0.0) continue;
+          const size_t q = (size_t)c * Nc + ((size_t)zs[dz] * nyc + ys[dy]) * nxc + xs[dx];
+          acc += w * (a.cb ? a.ca[q] - a.cb[q] : a.ca[q]);
+        }
+    const size_t o = (size_t)c * Nf + p;
+    const double v = a.fine[o] + acc;
+    a.fine[o] = v;
+    if (a.emis) a.emis[o] = (T)((double)a.kappa[p] * v);
+  }
+}
+
+// Values of a fine field at the coarse nodes, ncomp components of E.
+template <class E>
+__global__ void __launch_bounds__(256) k_inject(const E* __restrict__ f, E* __restrict__ out,
+                                                int nx, int ny, int nz, int ncomp) {
+  const int nxc = nx / 2, nyc = ny / 2, nzc = (nz + 1) / 2;
+  const size_t Nc = (size_t)nxc * nyc * nzc, Nf = (size_t)nx * ny * nz;
+  const size_t pc = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pc >= Nc) return;
+  const int ic = (int)(pc % nxc), jc = (int)((pc / nxc) % nyc), kc = (int)(pc / ((size_t)nxc * nyc));
+  const size_t pf = ((size_t)(2 * kc) * ny + 2 * jc) * nx + 2 * ic;
+  for (int c = 0; c < ncomp; ++c) out[(size_t)c * Nc + pc] = f[(size_t)c * Nf + pf];
+}
+
+// Per-block maximum of |a - b| / |a| over the first component (R_c between iterates).
+__global__ void __launch_bounds__(256) k_rel_change(const double* __restrict__ a,
+                                                    const double* __restrict__ b, size_t N,
+                                                    double* __restrict__ blockmax) {
+  __shared__ double red[256];
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  red[threadIdx.x] = (p < N) ? fabs(a[p] - b[p]) / fabs(a[p]) : 0.0;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
+}
+
+}  // namespace porta

@@ -77,8 +77,15 @@ def lib():
             L.porta_checkpoint_size.restype = sz
             L.porta_jkq_accumulate.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int, C.c_int,
                                                C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, sz, vp]
-            L.porta_see_update.argtypes = [C.c_int64, vp, C.POINTER(Atom), vp, vp, vp, vp,
+            L.porta_see_update.argtypes = [C.c_int64, vp, C.POINTER(Atom), vp, vp, vp, vp, vp,
                                            C.c_int, vp, vp, sz, vp]
+            L.porta_see_operator.argtypes = [C.c_int64, vp, C.POINTER(Atom), vp, vp, C.c_double,
+                                             vp, vp]
+            ci = C.c_int
+            L.porta_mg_restrict.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, vp]
+            L.porta_mg_prolong.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, vp]
+            L.porta_mg_inject.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp]
+            L.porta_rel_change.argtypes = [C.c_int64, vp, vp, vp, vp, sz, vp]
             L.porta_fs_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
                                            C.c_int, C.c_int, C.POINTER(Options), vp, vp, C.c_int,
                                            vp, vp, vp, vp, sz, vp]
@@ -91,9 +98,9 @@ def lib():
 
 
 EXPORTED = ("porta_workspace_size", "porta_checkpoint_size", "porta_fs_sweep",
-            "porta_jkq_accumulate",
-            "porta_see_update", "porta_fs_adjoint", "porta_strerror", "porta_last_error",
-            "porta_version")
+            "porta_jkq_accumulate", "porta_see_update", "porta_see_operator",
+            "porta_mg_restrict", "porta_mg_prolong", "porta_mg_inject", "porta_rel_change",
+            "porta_fs_adjoint", "porta_strerror", "porta_last_error", "porta_version")
 
 
 def _check(fn, status):
@@ -219,8 +226,9 @@ def jkq_accumulate(hg: HostGrid, ray0, f0, stokes, lambda_star=None, jkq=None, p
 
 def see_update(jkq, s_old, eps_c, delta2, w2, planck, hanle=None, bhat=None, kappa=None,
                emis_out=None, prec=F64, want_rc=True, s_new=None, rc=None, workspace=None,
-               stream=None):
-    """porta_see_update.  Returns (s_new [6][N], emis_out or None, rc device scalar or None)."""
+               stream=None, rhs=None):
+    """porta_see_update.  Returns (s_new [6][N], emis_out or None, rc device scalar or None).
+    rhs [6][N] FP64 replaces the right-hand side (eps_c B, 0, ...) when given."""
     import torch
     dev = jkq.device
     n = s_old.shape[1]
@@ -231,12 +239,79 @@ def see_update(jkq, s_old, eps_c, delta2, w2, planck, hanle=None, bhat=None, kap
     if workspace is None:
         workspace = _workspace(8 * ((n + 255) // 256), dev)
     atom = Atom(float(eps_c), float(delta2), float(w2), float(planck), _ptr(hanle), _ptr(bhat))
-    st = lib().porta_see_update(int(n), _ptr(jkq), C.byref(atom), _ptr(s_old), _ptr(s_new),
-                                _ptr(kappa), _ptr(emis_out), int(prec),
+    st = lib().porta_see_update(int(n), _ptr(jkq), C.byref(atom), _ptr(rhs), _ptr(s_old),
+                                _ptr(s_new), _ptr(kappa), _ptr(emis_out), int(prec),
                                 _ptr(rc) if want_rc else None, _ptr(workspace),
                                 workspace.numel(), _stream(stream))
     _check("porta_see_update", st)
     return s_new, emis_out, (rc if want_rc else None)
+
+
+def see_operator(jkq, s, eps_c, delta2, w2, planck, hanle=None, bhat=None, base=None,
+                 sign=1.0, out=None, stream=None):
+    """porta_see_operator: out = base + sign * L(rho) rho (base None: (eps_c B, 0, ...))."""
+    import torch
+    if out is None:
+        out = torch.empty_like(s)
+    atom = Atom(float(eps_c), float(delta2), float(w2), float(planck), _ptr(hanle), _ptr(bhat))
+    st = lib().porta_see_operator(int(s.shape[1]), _ptr(jkq), C.byref(atom), _ptr(s),
+                                  _ptr(base), float(sign), _ptr(out), _stream(stream))
+    _check("porta_see_operator", st)
+    return out
+
+
+def coarse_dims(nx, ny, nz):
+    return nx // 2, ny // 2, (nz + 1) // 2
+
+
+def mg_restrict(fine, nx, ny, nz, out=None, kappa_c=None, emis_c=None, prec=F64, stream=None):
+    """porta_mg_restrict of a [k][nx*ny*nz] FP64 field; returns the coarse [k][Nc]."""
+    import torch
+    k = fine.shape[0]
+    nxc, nyc, nzc = coarse_dims(nx, ny, nz)
+    if out is None:
+        out = torch.empty((k, nxc * nyc * nzc), dtype=torch.float64, device=fine.device)
+    st = lib().porta_mg_restrict(int(nx), int(ny), int(nz), int(k), _ptr(fine), _ptr(out),
+                                 _ptr(kappa_c), _ptr(emis_c), int(prec), _stream(stream))
+    _check("porta_mg_restrict", st)
+    return out
+
+
+def mg_prolong(fine, nx, ny, nz, coarse_a, coarse_b=None, kappa=None, emis=None, prec=F64,
+               stream=None):
+    """porta_mg_prolong: fine += P(coarse_a - coarse_b), in place; returns fine."""
+    st = lib().porta_mg_prolong(int(nx), int(ny), int(nz), int(fine.shape[0]), _ptr(coarse_a),
+                                _ptr(coarse_b), _ptr(fine), _ptr(kappa), _ptr(emis), int(prec),
+                                _stream(stream))
+    _check("porta_mg_prolong", st)
+    return fine
+
+
+def mg_inject(fine, nx, ny, nz, stream=None):
+    """porta_mg_inject of a [k][N] (or [N]) float32/float64 tensor."""
+    import torch
+    shape = fine.shape
+    f2 = fine.reshape(-1, shape[-1])
+    nxc, nyc, nzc = coarse_dims(nx, ny, nz)
+    out = torch.empty((f2.shape[0], nxc * nyc * nzc), dtype=fine.dtype, device=fine.device)
+    st = lib().porta_mg_inject(int(nx), int(ny), int(nz), int(f2.shape[0]),
+                               int(fine.element_size()), _ptr(f2), _ptr(out), _stream(stream))
+    _check("porta_mg_inject", st)
+    return out.reshape(shape[:-1] + (out.shape[-1],))
+
+
+def rel_change(s_new, s_old, rc=None, workspace=None, stream=None):
+    """porta_rel_change of the S00 rows; returns a device FP64 scalar."""
+    import torch
+    n = s_new.shape[-1]
+    if rc is None:
+        rc = torch.empty((), dtype=torch.float64, device=s_new.device)
+    if workspace is None:
+        workspace = _workspace(8 * ((n + 255) // 256), s_new.device)
+    st = lib().porta_rel_change(int(n), _ptr(s_new), _ptr(s_old), _ptr(rc), _ptr(workspace),
+                                workspace.numel(), _stream(stream))
+    _check("porta_rel_change", st)
+    return rc
 
 
 def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, prec=F64,

@@ -96,12 +96,12 @@ def test_other_entry_points_validate():
     hg = small_hg()
     dummy = np.zeros(8)
     a = porta.Atom(1.5, 0.0, 1.0, 1.0, None, None)
-    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), None, dummy.ctypes.data,
                               dummy.ctypes.data, None, None, 0, None, None, 0, None) == -1
     a = porta.Atom(0.1, 0.0, 1.0, 1.0, None, None)
-    assert L.porta_see_update(0, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+    assert L.porta_see_update(0, dummy.ctypes.data, C.byref(a), None, dummy.ctypes.data,
                               dummy.ctypes.data, None, None, 0, None, None, 0, None) == -1
-    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), dummy.ctypes.data,
+    assert L.porta_see_update(10, dummy.ctypes.data, C.byref(a), None, dummy.ctypes.data,
                               dummy.ctypes.data, None, None, 0, dummy.ctypes.data,
                               dummy.ctypes.data, 1, None) == -3
     assert L.porta_jkq_accumulate(C.byref(hg.grid), C.byref(hg.quad), 70, 20, 0, 1,
@@ -135,3 +135,28 @@ def test_adjoint_rejects_bezier_mode():
                               porta.BEZIER2D, None, dummy.ctypes.data, None, 4,
                               dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
                               dummy.ctypes.data, 1 << 40, None) == -2
+
+
+def test_multigrid_entry_points_validate():
+    """Shape and argument checks of the multigrid calls (no kernel launch)."""
+    L = porta.lib()
+    d = np.zeros(8).ctypes.data
+    a = porta.Atom(0.1, 0.0, 1.0, 1.0, None, None)
+    bad = porta.Atom(-0.1, 0.0, 1.0, 1.0, None, None)
+    assert L.porta_see_operator(0, d, C.byref(a), d, None, -1.0, d, None) == -1
+    assert L.porta_see_operator(10, d, C.byref(bad), d, None, -1.0, d, None) == -1
+    assert L.porta_see_operator(10, None, C.byref(a), d, None, -1.0, d, None) == -1
+    assert L.porta_see_operator(10, d, C.byref(a), d, None, float("nan"), d, None) == -1
+    # odd nx, even nz, too small, bad ncomp, bad precision, kappa without emis
+    for nx, ny, nz, k, prec in ((5, 4, 5, 1, 0), (4, 4, 6, 1, 0), (4, 4, 1, 1, 0), (0, 4, 5, 1, 0),
+                                (4, 4, 5, 0, 0), (4, 4, 5, 65, 0), (4, 4, 5, 1, 7)):
+        assert L.porta_mg_restrict(nx, ny, nz, k, d, d, None, None, prec, None) == -1
+        assert L.porta_mg_prolong(nx, ny, nz, k, d, None, d, None, None, prec, None) == -1
+    assert L.porta_mg_restrict(4, 4, 5, 1, d, d, d, None, 0, None) == -1
+    assert L.porta_mg_prolong(4, 4, 5, 1, d, None, d, None, d, 0, None) == -1
+    assert L.porta_mg_restrict(4, 4, 5, 1, None, d, None, None, 0, None) == -1
+    assert L.porta_mg_prolong(4, 4, 5, 1, None, None, d, None, None, 0, None) == -1
+    assert L.porta_mg_inject(4, 4, 5, 1, 2, d, d, None) == -1
+    assert L.porta_mg_inject(4, 4, 4, 1, 8, d, d, None) == -1
+    assert L.porta_rel_change(10, d, d, d, d, 4, None) == -3
+    assert L.porta_rel_change(10, d, None, d, d, 1 << 20, None) == -1
