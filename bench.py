@@ -62,20 +62,77 @@ def sweep_launch_bytes(cfg, nrb, elem):
     return updates * 8 * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
 
 
+KERNEL_SYMBOLS = {
+    "k_sweep_plane<float, 0>": "_ZN5porta13k_sweep_planeIfLi0EEEvNS_9PlaneArgsIT_EE",
+    "k_sweep_plane<double, 0>": "_ZN5porta13k_sweep_planeIdLi0EEEvNS_9PlaneArgsIT_EE",
+    "k_adjoint_plane<float>": "_ZN5porta15k_adjoint_planeIfEEvNS_7AdjArgsIT_EE",
+}
+
+
+def _amdgcn_code_objects(data):
+    """The gfx950 ELF images inside the offload bundles of a host shared library."""
+    import struct
+    out, i, magic = [], 0, b"__CLANG_OFFLOAD_BUNDLE__"
+    while (i := data.find(magic, i)) >= 0:
+        n = struct.unpack_from("<Q", data, i + 24)[0]
+        off = i + 32
+        for _ in range(n):
+            o, sz, tl = struct.unpack_from("<QQQ", data, off)
+            triple = data[off + 24:off + 24 + tl]
+            off += 24 + tl
+            if b"amdgcn" in triple and sz:
+                out.append(data[i + o:i + o + sz])
+        i += len(magic)
+    return out
+
+
+def _elf_symbol_bytes(elf, name):
+    """Bytes of a sized symbol of an ELF64 image (its machine code for a kernel)."""
+    import struct
+    shoff = struct.unpack_from("<Q", elf, 0x28)[0]
+    shentsize, shnum = struct.unpack_from("<HH", elf, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", elf, shoff + k * shentsize) for k in range(shnum)]
+    want = name.encode()
+    for sec in secs:
+        if sec[1] != 2:                      # SHT_SYMTAB
+            continue
+        strtab = secs[sec[6]]
+        for k in range(sec[5] // 24):
+            st_name, _, _, shndx, value, size = struct.unpack_from("<IBBHQQ", elf, sec[4] + 24 * k)
+            a = strtab[4] + st_name
+            if size and elf[a:elf.index(b"\0", a)] == want:
+                home = secs[shndx]
+                fo = home[4] + (value - home[3])
+                return elf[fo:fo + size]
+    return None
+
+
+def kernel_code_sha256(kernel, lib_path=None):
+    """SHA-256 of a kernel's gfx950 machine code in the built library, or None."""
+    import hashlib
+    from paper_1307_4217_amd import porta
+    sym = KERNEL_SYMBOLS.get(kernel)
+    path = lib_path or porta.LIB_PATH
+    if sym is None or not os.path.exists(path):
+        return None
+    for co in _amdgcn_code_objects(open(path, "rb").read()):
+        b = _elf_symbol_bytes(co, sym)
+        if b is not None:
+            return hashlib.sha256(b).hexdigest()
+    return None
+
+
 def measured_traffic(kernel, workload_matches):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None if
-    the kernel sources changed since they were taken (or the workload differs)."""
-    import hashlib
+    the kernel's machine code differs from the one the counters were taken on (or the
+    workload differs)."""
     if not workload_matches or not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
-    h = hashlib.sha256()
-    for f in rec["source_files"]:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
-        return None
     k = rec["kernels"].get(kernel)
-    return None if k is None else k["traffic_bytes_per_launch"]
+    if k is None or k.get("code_sha256") != kernel_code_sha256(kernel):
+        return None
+    return k["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, atm, q, pairs):

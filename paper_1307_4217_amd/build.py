@@ -29,7 +29,7 @@ def _run(cmd, verbose):
 
 
 def build_library(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "porta_abi.hip")]
+    srcs = [os.path.join(CSRC, "porta_abi.hip"), os.path.join(CSRC, "porta_see_mg.hip")]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), *DEVICE_FLAGS,

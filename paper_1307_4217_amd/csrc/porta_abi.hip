@@ -11,12 +11,11 @@
 
 #include "../../include/porta.h"
 #include "porta_adjoint.hpp"
+#include "porta_host.hpp"
 #include "porta_kernels.hpp"
-#include "porta_mg.hpp"
 
-namespace {
-
-using namespace porta;
+namespace porta {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -35,6 +34,19 @@ int check_launch(const char* what) {
   if (e != hipSuccess) return fail(PORTA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
   return PORTA_OK;
 }
+
+int validate_prec(int prec) {
+  if (prec != PORTA_F64 && prec != PORTA_F32) return fail(PORTA_EINVAL, "unknown precision %d", prec);
+  return PORTA_OK;
+}
+
+}  // namespace host
+}  // namespace porta
+
+namespace {
+
+using namespace porta;
+using namespace porta::host;
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -86,11 +98,6 @@ int validate_quad(const porta_quad* q) {
     sf += q->wfreq[j] * q->phi[j];
   }
   if (!(sf > 0.0)) return fail(PORTA_EINVAL, "sum of wfreq * phi must be > 0");
-  return PORTA_OK;
-}
-
-int validate_prec(int prec) {
-  if (prec != PORTA_F64 && prec != PORTA_F32) return fail(PORTA_EINVAL, "unknown precision %d", prec);
   return PORTA_OK;
 }
 
@@ -491,26 +498,6 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
   return check_launch("grad_out");
 }
 
-int validate_atom(const porta_atom* atom) {
-  if (!(atom->eps_c >= 0.0 && atom->eps_c <= 1.0))
-    return fail(PORTA_EINVAL, "eps_c must be in [0, 1]");
-  if (!(atom->delta2 >= 0.0) || !std::isfinite(atom->delta2) || !std::isfinite(atom->w2) ||
-      !std::isfinite(atom->planck))
-    return fail(PORTA_EINVAL, "atom parameters must be finite (delta2 >= 0)");
-  return PORTA_OK;
-}
-
-int validate_coarsening(int nx, int ny, int nz, int ncomp) {
-  if (nx < 2 || ny < 2 || nz < 3 || nx % 2 || ny % 2 || nz % 2 == 0)
-    return fail(PORTA_EINVAL, "coarsening needs even nx, ny >= 2 and odd nz >= 3 (got %d %d %d)",
-                nx, ny, nz);
-  if ((double)nx * ny * nz * 10.0 >= 9.0e18 || (double)nx * ny >= 2147483647.0)
-    return fail(PORTA_EINVAL, "grid too large");
-  if (ncomp < 1 || ncomp > 64) return fail(PORTA_EINVAL, "ncomp must be in 1..64");
-  return PORTA_OK;
-}
-
-inline unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
@@ -640,46 +627,6 @@ int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray
   return check_launch("jkq_accumulate");
 }
 
-int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
-                     const double* rhs, const double* s_old, double* s_new, const void* kappa,
-                     void* emis_out, int prec, double* rc_out, void* workspace, size_t ws_bytes,
-                     void* stream) {
-  int rc;
-  if ((rc = validate_prec(prec))) return rc;
-  if (npoints < 1 || npoints > (int64_t)1 << 40) return fail(PORTA_EINVAL, "npoints out of range");
-  if (!jkq || !atom || !s_old || !s_new) return fail(PORTA_EINVAL, "NULL argument");
-  if (emis_out && !kappa) return fail(PORTA_EINVAL, "emis_out needs kappa");
-  if ((rc = validate_atom(atom))) return rc;
-  const size_t N = (size_t)npoints;
-  const unsigned nb = (unsigned)((N + 255) / 256);
-  double* blockmax = nullptr;
-  if (rc_out) {
-    if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
-    if (ws_bytes < sizeof(double) * nb)
-      return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
-                  ws_bytes, sizeof(double) * nb);
-    blockmax = static_cast<double*>(workspace);
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (prec == PORTA_F64) {
-    SeeArgs<double> a{jkq, rhs, s_old, s_new, atom->hanle, atom->bhat,
-                      static_cast<const double*>(kappa), static_cast<double*>(emis_out),
-                      blockmax, N, atom->eps_c, atom->delta2, atom->w2, atom->planck};
-    hipLaunchKernelGGL(k_see<double>, dim3(nb), dim3(256), 0, st, a);
-  } else {
-    SeeArgs<float> a{jkq, rhs, s_old, s_new, atom->hanle, atom->bhat,
-                     static_cast<const float*>(kappa), static_cast<float*>(emis_out),
-                     blockmax, N, atom->eps_c, atom->delta2, atom->w2, atom->planck};
-    hipLaunchKernelGGL(k_see<float>, dim3(nb), dim3(256), 0, st, a);
-  }
-  if ((rc = check_launch("see"))) return rc;
-  if (rc_out) {
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, blockmax, (int)nb, rc_out);
-    if ((rc = check_launch("see_rc"))) return rc;
-  }
-  return PORTA_OK;
-}
-
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,
                      const void* checkpoints, int checkpoint_stride, void* g_kappa,
@@ -715,103 +662,6 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
                              static_cast<const float*>(checkpoints), checkpoint_stride, static_cast<float*>(g_kappa),
                              static_cast<float*>(g_propmat), static_cast<float*>(g_emis), ws, L,
                              st);
-}
-
-int porta_see_operator(int64_t npoints, const double* jkq, const porta_atom* atom,
-                       const double* s, const double* base, double sign, double* out,
-                       void* stream) {
-  int rc;
-  if (npoints < 1 || npoints > (int64_t)1 << 40) return fail(PORTA_EINVAL, "npoints out of range");
-  if (!jkq || !atom || !s || !out) return fail(PORTA_EINVAL, "NULL argument");
-  if ((rc = validate_atom(atom))) return rc;
-  if (!std::isfinite(sign)) return fail(PORTA_EINVAL, "sign must be finite");
-  const size_t N = (size_t)npoints;
-  SeeOpArgs a{jkq, s, base, out, atom->hanle, atom->bhat, N, sign,
-              atom->eps_c, atom->delta2, atom->w2, atom->planck};
-  hipLaunchKernelGGL(k_see_operator, dim3(blocks_for(N)), dim3(256), 0,
-                     reinterpret_cast<hipStream_t>(stream), a);
-  return check_launch("see_operator");
-}
-
-int porta_mg_restrict(int nx, int ny, int nz, int ncomp, const double* fine, double* coarse,
-                      const void* kappa_coarse, void* emis_coarse, int prec, void* stream) {
-  int rc;
-  if ((rc = validate_coarsening(nx, ny, nz, ncomp)) || (rc = validate_prec(prec))) return rc;
-  if (!fine || !coarse) return fail(PORTA_EINVAL, "NULL argument");
-  if ((emis_coarse == nullptr) != (kappa_coarse == nullptr))
-    return fail(PORTA_EINVAL, "kappa_coarse and emis_coarse go together");
-  const size_t Nc = (size_t)(nx / 2) * (ny / 2) * ((nz + 1) / 2);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (prec == PORTA_F64) {
-    RestrictArgs<double> a{fine, coarse, static_cast<const double*>(kappa_coarse),
-                           static_cast<double*>(emis_coarse), nx, ny, nz, ncomp};
-    hipLaunchKernelGGL(k_restrict<double>, dim3(blocks_for(Nc)), dim3(256), 0, st, a);
-  } else {
-    RestrictArgs<float> a{fine, coarse, static_cast<const float*>(kappa_coarse),
-                          static_cast<float*>(emis_coarse), nx, ny, nz, ncomp};
-    hipLaunchKernelGGL(k_restrict<float>, dim3(blocks_for(Nc)), dim3(256), 0, st, a);
-  }
-  return check_launch("mg_restrict");
-}
-
-int porta_mg_prolong(int nx, int ny, int nz, int ncomp, const double* coarse_a,
-                     const double* coarse_b, double* fine, const void* kappa, void* emis,
-                     int prec, void* stream) {
-  int rc;
-  if ((rc = validate_coarsening(nx, ny, nz, ncomp)) || (rc = validate_prec(prec))) return rc;
-  if (!coarse_a || !fine) return fail(PORTA_EINVAL, "NULL argument");
-  if ((emis == nullptr) != (kappa == nullptr))
-    return fail(PORTA_EINVAL, "kappa and emis go together");
-  const size_t Nf = (size_t)nx * ny * nz;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (prec == PORTA_F64) {
-    ProlongArgs<double> a{coarse_a, coarse_b, fine, static_cast<const double*>(kappa),
-                          static_cast<double*>(emis), nx, ny, nz, ncomp};
-    hipLaunchKernelGGL(k_prolong<double>, dim3(blocks_for(Nf)), dim3(256), 0, st, a);
-  } else {
-    ProlongArgs<float> a{coarse_a, coarse_b, fine, static_cast<const float*>(kappa),
-                         static_cast<float*>(emis), nx, ny, nz, ncomp};
-    hipLaunchKernelGGL(k_prolong<float>, dim3(blocks_for(Nf)), dim3(256), 0, st, a);
-  }
-  return check_launch("mg_prolong");
-}
-
-int porta_mg_inject(int nx, int ny, int nz, int ncomp, int elem_bytes, const void* fine,
-                    void* coarse, void* stream) {
-  int rc;
-  if ((rc = validate_coarsening(nx, ny, nz, ncomp))) return rc;
-  if (!fine || !coarse) return fail(PORTA_EINVAL, "NULL argument");
-  const size_t Nc = (size_t)(nx / 2) * (ny / 2) * ((nz + 1) / 2);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (elem_bytes == 8)
-    hipLaunchKernelGGL(k_inject<double>, dim3(blocks_for(Nc)), dim3(256), 0, st,
-                       static_cast<const double*>(fine), static_cast<double*>(coarse), nx, ny,
-                       nz, ncomp);
-  else if (elem_bytes == 4)
-    hipLaunchKernelGGL(k_inject<float>, dim3(blocks_for(Nc)), dim3(256), 0, st,
-                       static_cast<const float*>(fine), static_cast<float*>(coarse), nx, ny, nz,
-                       ncomp);
-  else
-    return fail(PORTA_EINVAL, "elem_bytes must be 4 or 8");
-  return check_launch("mg_inject");
-}
-
-int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, double* rc_out,
-                     void* workspace, size_t ws_bytes, void* stream) {
-  int rc;
-  if (npoints < 1 || npoints > (int64_t)1 << 40) return fail(PORTA_EINVAL, "npoints out of range");
-  if (!s_new || !s_old || !rc_out || !workspace) return fail(PORTA_EINVAL, "NULL argument");
-  const size_t N = (size_t)npoints;
-  const unsigned nb = blocks_for(N);
-  if (ws_bytes < sizeof(double) * nb)
-    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
-                sizeof(double) * nb);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  double* blockmax = static_cast<double*>(workspace);
-  hipLaunchKernelGGL(k_rel_change, dim3(nb), dim3(256), 0, st, s_new, s_old, N, blockmax);
-  if ((rc = check_launch("rel_change"))) return rc;
-  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, blockmax, (int)nb, rc_out);
-  return check_launch("rel_change_final");
 }
 
 }  // extern "C"

@@ -7,9 +7,17 @@
 // are [c][N] with x fastest.
 #pragma once
 
-#include "porta_kernels.hpp"
+#include <hip/hip_runtime.h>
+
+#include "porta_math.hpp"
 
 namespace porta {
+
+// Periodic index in [0, n).
+__device__ inline int wrap_index(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
 
 // ---------------------------------------------------------------------------
 // out = base + sign * L(rho) rho at every point, where (Sect. 2, Eq. nonlte, two-level
@@ -95,8 +103,8 @@ __global__ void __launch_bounds__(256) k_restrict(const RestrictArgs<T> a) {
   int col[3], row[3];
   const double w[3] = {0.5, 1.0, 0.5};
   for (int d = 0; d < 3; ++d) {
-    col[d] = wrapi(2 * ic + d - 1, a.nx);
-    row[d] = wrapi(2 * jc + d - 1, a.ny);
+    col[d] = wrap_index(2 * ic + d - 1, a.nx);
+    row[d] = wrap_index(2 * jc + d - 1, a.ny);
   }
   const int dz0 = (kc == 0) ? 1 : 0, dz1 = (kc == nzc - 1) ? 1 : 2;
   const double wz = (dz0 == 0 && dz1 == 2) ? 2.0 : 1.5;

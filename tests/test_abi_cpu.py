@@ -160,3 +160,13 @@ def test_multigrid_entry_points_validate():
     assert L.porta_mg_inject(4, 4, 4, 1, 8, d, d, None) == -1
     assert L.porta_rel_change(10, d, d, d, d, 4, None) == -3
     assert L.porta_rel_change(10, d, None, d, d, 1 << 20, None) == -1
+
+
+def test_kernel_code_digest_found_in_built_library():
+    """The benchmark keys its committed HBM counters to the machine code of the kernel."""
+    import re
+    import bench
+    for k in ("k_sweep_plane<float, 0>", "k_adjoint_plane<float>"):
+        d = bench.kernel_code_sha256(k)
+        assert d is not None and re.fullmatch(r"[0-9a-f]{64}", d)
+    assert bench.kernel_code_sha256("no such kernel") is None
