@@ -247,6 +247,14 @@ int porta_mg_inject(int nx, int ny, int nz, int ncomp, int elem_bytes, const voi
                     void* coarse, void* stream);
 
 /*
+ * Emissivities from source-function multipoles, eps^K_Q = kappa S^K_Q (Sect. 2):
+ *   kappa : device [N] (precision prec); s : device [ncomp][N] FP64;
+ *   emis  : device [ncomp][N] (precision prec), overwritten.  1 <= ncomp <= 64.
+ */
+int porta_emissivity(int64_t npoints, int ncomp, const void* kappa, const double* s,
+                     void* emis, int prec, void* stream);
+
+/*
  * R_c between two iterates: rc_out (device FP64 scalar) = max_p |a_p - b_p| / |a_p|
  * over the first npoints entries (S00 rows of two [6][N] arrays).  workspace as for
  * porta_see_update.

@@ -191,6 +191,17 @@ __global__ void __launch_bounds__(256) k_inject(const E* __restrict__ f, E* __re
   for (int c = 0; c < ncomp; ++c) out[(size_t)c * Nc + pc] = f[(size_t)c * Nf + pf];
 }
 
+// emis = kappa * s for ncomp components (s FP64 [ncomp][N], kappa and emis in T).
+template <class T>
+__global__ void __launch_bounds__(256) k_emissivity(const T* __restrict__ kappa,
+                                                    const double* __restrict__ s,
+                                                    T* __restrict__ emis, size_t N, int ncomp) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double k = (double)kappa[p];
+  for (int c = 0; c < ncomp; ++c) emis[(size_t)c * N + p] = (T)(k * s[(size_t)c * N + p]);
+}
+
 // Per-block maximum of |a - b| / |a| over the first component (R_c between iterates).
 __global__ void __launch_bounds__(256) k_rel_change(const double* __restrict__ a,
                                                     const double* __restrict__ b, size_t N,

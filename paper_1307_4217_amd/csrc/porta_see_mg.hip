@@ -177,4 +177,22 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
   return check_launch("rel_change_final");
 }
 
+int porta_emissivity(int64_t npoints, int ncomp, const void* kappa, const double* s,
+                     void* emis, int prec, void* stream) {
+  int rc;
+  if ((rc = validate_prec(prec))) return rc;
+  if (npoints < 1 || npoints > (int64_t)1 << 40) return fail(PORTA_EINVAL, "npoints out of range");
+  if (ncomp < 1 || ncomp > 64) return fail(PORTA_EINVAL, "ncomp must be in 1..64");
+  if (!kappa || !s || !emis) return fail(PORTA_EINVAL, "NULL argument");
+  const size_t N = (size_t)npoints;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == PORTA_F64)
+    hipLaunchKernelGGL(k_emissivity<double>, dim3(blocks_for(N)), dim3(256), 0, st,
+                       static_cast<const double*>(kappa), s, static_cast<double*>(emis), N, ncomp);
+  else
+    hipLaunchKernelGGL(k_emissivity<float>, dim3(blocks_for(N)), dim3(256), 0, st,
+                       static_cast<const float*>(kappa), s, static_cast<float*>(emis), N, ncomp);
+  return check_launch("emissivity");
+}
+
 }  // extern "C"

@@ -83,37 +83,60 @@ def _atom_args(atm):
 
 
 class MultigridSolver:
-    """Hierarchy of `nlevels` grids over the atmosphere `atm` (finest first)."""
+    """Hierarchy of `nlevels` grids over the atmosphere `atm` (finest first).  The formal
+    solutions run in `prec`; set_precision() switches between FP32 and FP64 sweeps
+    keeping the current iterate (J, the SEE and the transfers are FP64 either way)."""
 
     def __init__(self, atm, quad, nlevels=2, prec=porta.F64, device="cuda:0", opts=None,
                  nu1=2, nu2=4, ncoarse=20):
         import torch
         self.torch = torch
+        self.atm, self.quad, self.nlevels, self.opts = atm, quad, nlevels, opts
         self.nu1, self.nu2, self.ncoarse = nu1, nu2, ncoarse
-        dev = torch.device(device)
+        self.dev = torch.device(device)
+        self.levels = []
+        self._build_levels(prec)
+        fine = self.levels[0]
+        fine.S.copy_(torch.as_tensor(np.ascontiguousarray(atm.source), dtype=torch.float64,
+                                     device=self.dev))
+        porta.emissivity(fine.kappa, fine.S, emis=fine.emis)
+        self.S_prev = torch.empty_like(fine.S)
+        self.rc = torch.empty((), dtype=torch.float64, device=self.dev)
+        self.cycles = 0
+
+    def _build_levels(self, prec):
+        torch, atm, quad, dev = self.torch, self.atm, self.quad, self.dev
         dt = porta.dtype_of(prec)
         t = lambda a, d: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=d,
                                                                   device=dev)
         atom = _atom_args(atm)
         hg = porta.HostGrid.from_inputs(atm, quad)
-        fine = Level(hg, t(atm.kappa, dt), t(atm.propmat, dt), t(atm.hanle, torch.float64),
-                     t(atm.bhat, torch.float64), atom, atm.i_bottom, prec, opts, dev)
-        fine.S.copy_(t(atm.source, torch.float64))
-        fine.emis.copy_(t(atm.kappa[None, :] * atm.source, dt))
-        self.levels = [fine]
+        levels = [Level(hg, t(atm.kappa, dt), t(atm.propmat, dt), t(atm.hanle, torch.float64),
+                        t(atm.bhat, torch.float64), atom, atm.i_bottom, prec, self.opts, dev)]
         z = np.asarray(atm.z, dtype=np.float64)
-        for _ in range(nlevels - 1):
-            up = self.levels[-1]
+        for _ in range(self.nlevels - 1):
+            up = levels[-1]
             nx, ny, nz = up.dims
             z = z[::2]
             hgc = porta.HostGrid(nx // 2, ny // 2, (nz + 1) // 2, atm.lx, atm.ly, z, quad.mu,
                                  quad.wmu, quad.nchi, quad.phi, quad.wfreq)
             inj = lambda a: None if a is None else porta.mg_inject(a, nx, ny, nz)
-            self.levels.append(Level(hgc, inj(up.kappa), inj(up.propmat), inj(up.hanle),
-                                     inj(up.bhat), atom, atm.i_bottom, prec, opts, dev))
-        self.S_prev = torch.empty_like(fine.S)
-        self.rc = torch.empty((), dtype=torch.float64, device=dev)
-        self.cycles = 0
+            levels.append(Level(hgc, inj(up.kappa), inj(up.propmat), inj(up.hanle),
+                                inj(up.bhat), atom, atm.i_bottom, prec, self.opts, dev))
+        self.levels = levels
+        self.prec = prec
+
+    def set_precision(self, prec):
+        """Continue with formal solutions in `prec` from the current iterate."""
+        if prec == self.prec:
+            return
+        S = self.levels[0].S.clone()
+        self.levels = []
+        self.torch.cuda.empty_cache()
+        self._build_levels(prec)
+        fine = self.levels[0]
+        fine.S.copy_(S)
+        porta.emissivity(fine.kappa, fine.S, emis=fine.emis)
 
     @property
     def source(self):
@@ -174,6 +197,8 @@ def main(argv=None):
     ap.add_argument("--jacobi", type=int, default=0, help="also run this many Jacobi iterations")
     ap.add_argument("--ncoarse", type=int, default=20)
     ap.add_argument("--prec", default="f64", choices=["f32", "f64"])
+    ap.add_argument("--fp32-until", type=float, default=0.0,
+                    help="sweep in FP32 until R_c drops below this value, then in FP64")
     ap.add_argument("--with-propmat", action="store_true",
                     help="keep the random dichroism/dispersion terms of the synthetic model")
     args = ap.parse_args(argv)
@@ -183,6 +208,8 @@ def main(argv=None):
         atm = dataclasses.replace(atm, propmat=0 * atm.propmat)
     q = inputs.make_quadrature(cfg)
     prec = porta.F64 if args.prec == "f64" else porta.F32
+    if args.fp32_until > 0:
+        prec = porta.F32
     import torch
     solver = MultigridSolver(atm, q, args.levels, prec, ncoarse=args.ncoarse)
     work = solver.fine_sweeps_per_cycle()
@@ -190,7 +217,10 @@ def main(argv=None):
     for c in range(args.cycles):
         rc = float(solver.vcycle().item())
         print(json.dumps({"cycle": c + 1, "R_c": rc, "fine_sweeps": round(work * (c + 1), 2),
+                          "sweep_prec": "f32" if solver.prec == porta.F32 else "f64",
                           "elapsed_s": round(time.perf_counter() - t0, 3)}), flush=True)
+        if args.fp32_until > 0 and rc < args.fp32_until:
+            solver.set_precision(porta.F64)
     mg_s = time.perf_counter() - t0
     out = {"grid": [args.nx, args.nx, args.nz], "levels": args.levels, "cycles": args.cycles,
            "rays": cfg.nrays, "freqs": args.nfreq, "prec": args.prec, "mg_seconds": round(mg_s, 3),

@@ -86,6 +86,7 @@ def lib():
             L.porta_mg_prolong.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, vp]
             L.porta_mg_inject.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp]
             L.porta_rel_change.argtypes = [C.c_int64, vp, vp, vp, vp, sz, vp]
+            L.porta_emissivity.argtypes = [C.c_int64, ci, vp, vp, vp, ci, vp]
             L.porta_fs_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
                                            C.c_int, C.c_int, C.POINTER(Options), vp, vp, C.c_int,
                                            vp, vp, vp, vp, sz, vp]
@@ -100,6 +101,7 @@ def lib():
 EXPORTED = ("porta_workspace_size", "porta_checkpoint_size", "porta_fs_sweep",
             "porta_jkq_accumulate", "porta_see_update", "porta_see_operator",
             "porta_mg_restrict", "porta_mg_prolong", "porta_mg_inject", "porta_rel_change",
+            "porta_emissivity",
             "porta_fs_adjoint", "porta_strerror", "porta_last_error", "porta_version")
 
 
@@ -298,6 +300,18 @@ def mg_inject(fine, nx, ny, nz, stream=None):
                                int(fine.element_size()), _ptr(f2), _ptr(out), _stream(stream))
     _check("porta_mg_inject", st)
     return out.reshape(shape[:-1] + (out.shape[-1],))
+
+
+def emissivity(kappa, s, emis=None, stream=None):
+    """porta_emissivity: emis = kappa * s ([k][N], dtype of kappa)."""
+    import torch
+    if emis is None:
+        emis = torch.empty(s.shape, dtype=kappa.dtype, device=s.device)
+    prec = F64 if kappa.dtype == torch.float64 else F32
+    st = lib().porta_emissivity(int(s.shape[-1]), int(s.shape[0]), _ptr(kappa), _ptr(s),
+                                _ptr(emis), int(prec), _stream(stream))
+    _check("porta_emissivity", st)
+    return emis
 
 
 def rel_change(s_new, s_old, rc=None, workspace=None, stream=None):

@@ -157,3 +157,42 @@ def test_vcycle_fp32_sweep_close_to_oracle(mgo):
     assert rel00 < 2e-5 / atm.eps_c
     assert k2 < 2e-5 / atm.eps_c
     torch.cuda.synchronize()
+
+
+def test_emissivity_call():
+    import torch
+    rng = np.random.default_rng(9)
+    n = 1000
+    s = rng.standard_normal((6, n))
+    kap = rng.uniform(0.1, 3.0, n)
+    for dt in (torch.float64, torch.float32):
+        got = porta.emissivity(_dev(kap, dt), _dev(s)).cpu().numpy().astype(np.float64)
+        k = kap.astype(np.float32).astype(np.float64) if dt == torch.float32 else kap
+        np.testing.assert_allclose(got, k * s, rtol=1e-15 if dt == torch.float64 else 1e-7,
+                                   atol=0)
+    torch.cuda.synchronize()
+
+
+def test_mixed_precision_cycles_reach_fp64_result():
+    """Three V-cycles with FP32 sweeps, then three with FP64 sweeps, end where six FP64
+    cycles end, to less than what one more cycle still changes (the FP32 cycles only
+    move the starting point of the FP64 ones)."""
+    import torch
+    from paper_1307_4217_amd.multigrid import MultigridSolver
+    atm, q = _mg_atmosphere(16, 33)
+    a = MultigridSolver(atm, q, 2, porta.F64, ncoarse=10)
+    for _ in range(6):
+        rc_a = a.vcycle().item()
+    b = MultigridSolver(atm, q, 2, porta.F32, ncoarse=10)
+    for _ in range(3):
+        b.vcycle()
+    b.set_precision(porta.F64)
+    for _ in range(3):
+        rc_b = b.vcycle().item()
+    sa, sb = a.source.cpu().numpy(), b.source.cpu().numpy()
+    err = (np.abs(sa - sb).max(axis=1) / np.abs(sa).max(axis=1)).max()
+    print(f"mixed precision: R_c {rc_b:.2e} (FP64 {rc_a:.2e}), max diff / scale {err:.2e}",
+          flush=True)
+    assert err < rc_a
+    assert rc_b < 2 * rc_a
+    torch.cuda.synchronize()
