@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--ray-batch", type=int, default=40,
                     help="rays swept together in the forward sweep and in the adjoint")
+    ap.add_argument("--adjoint-ray-batch", type=int, default=0,
+                    help="rays per batch in the adjoint (default: --ray-batch)")
     ap.add_argument("--checkpoint-stride", type=int, default=11)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block", type=int, default=0)
@@ -188,8 +190,13 @@ def main():
     opts = porta.options(ray_batch=args.ray_batch, block=args.block)
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
     nbatches = -(-(cfg.nmu * cfg.nchi) // nrb)
-    ws = torch.empty(porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts), dtype=torch.uint8,
-                     device=dev)
+    adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block)
+    ws_bytes = porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts)
+    if not args.no_adjoint:
+        # the sweep and the adjoint run one after the other and share one workspace
+        ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
+                                                      args.checkpoint_stride, adj_opts))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ws_see = torch.empty(8 * ((cfg.npoints + 255) // 256) + 256, dtype=torch.uint8, device=dev)
     jkq = torch.empty((10, cfg.npoints), dtype=torch.float64, device=dev)
     itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=tdt, device=dev)
@@ -208,12 +215,9 @@ def main():
         # adjoint, which then only recomputes the planes between checkpoints
         ckpt = torch.empty(porta.checkpoint_size(hg, prec, args.checkpoint_stride) + 256,
                            dtype=torch.uint8, device=dev)
-        ws_adj = torch.empty(porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
-                                                  args.checkpoint_stride, opts),
-                             dtype=torch.uint8, device=dev)
+        ws_adj = ws
         g_k, g_p, g_e = torch.empty_like(kappa), torch.empty_like(prop), torch.empty_like(emis)
-        seed_buf = torch.empty_like(itop)
-        log(f"adjoint workspace {ws_adj.numel() / 1e9:.2f} GB, checkpoints "
+        log(f"shared sweep/adjoint workspace {ws.numel() / 1e9:.2f} GB, checkpoints "
             f"{ckpt.numel() / 1e9:.2f} GB (stride {args.checkpoint_stride})")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -241,13 +245,14 @@ def main():
                          s_new=state["s_new"], rc=rc, workspace=ws_see)
         e[2].record()
         if adj:
-            # dL/dI_top of L = sum (I_top - target)^2, then the reverse sweep
-            torch.sub(itop, target, out=seed_buf).mul_(2.0)
+            # dL/dI_top of L = sum (I_top - target)^2, formed in place of I_top (not read
+            # again this step), then the reverse sweep
+            seed = itop.sub_(target).mul_(2.0)
             e[3].record()
             g_k.zero_(), g_p.zero_(), g_e.zero_()
-            porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, seed_buf, atm.w2, prec=prec,
+            porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, seed, atm.w2, prec=prec,
                              checkpoint_stride=args.checkpoint_stride, g_kappa=g_k,
-                             g_propmat=g_p, g_emis=g_e, opts=opts, workspace=ws_adj,
+                             g_propmat=g_p, g_emis=g_e, opts=adj_opts, workspace=ws_adj,
                              checkpoints=ckpt)
         else:
             e[3].record()
@@ -295,7 +300,8 @@ def main():
              "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4),
              "adjoint_ms": round(adj_ms, 2),
              "adjoint_updates_per_s": (adj_updates / (adj_ms * 1e-3)) if adj else None,
-             "adjoint_over_forward_time": round(adj_ms / sweep_ms, 3) if adj else None}
+             "adjoint_over_forward_time": round(adj_ms / sweep_ms, 3) if adj else None,
+             "peak_device_memory_GB": round(torch.cuda.max_memory_allocated() / 1e9, 1)}
     if not args.no_fp64_rate and prec == porta.F32:
         del ws
         if adj:
@@ -345,6 +351,7 @@ def main():
                    "updates_per_step": cfg.updates + adj_updates,
                    "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
                    "ray_batch": nrb, "checkpoint_stride": args.checkpoint_stride,
+                   "adjoint_ray_batch": adj_opts.ray_batch,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

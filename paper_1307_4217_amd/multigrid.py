@@ -194,8 +194,10 @@ def main(argv=None):
     ap.add_argument("--nfreq", type=int, default=41)
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--cycles", type=int, default=4)
+    ap.add_argument("--tol", type=float, default=0.0, help="stop once R_c falls below this")
     ap.add_argument("--jacobi", type=int, default=0, help="also run this many Jacobi iterations")
     ap.add_argument("--ncoarse", type=int, default=20)
+    ap.add_argument("--ray-batch", type=int, default=40)
     ap.add_argument("--prec", default="f64", choices=["f32", "f64"])
     ap.add_argument("--fp32-until", type=float, default=0.0,
                     help="sweep in FP32 until R_c drops below this value, then in FP64")
@@ -211,7 +213,8 @@ def main(argv=None):
     if args.fp32_until > 0:
         prec = porta.F32
     import torch
-    solver = MultigridSolver(atm, q, args.levels, prec, ncoarse=args.ncoarse)
+    solver = MultigridSolver(atm, q, args.levels, prec, ncoarse=args.ncoarse,
+                             opts=porta.options(ray_batch=args.ray_batch))
     work = solver.fine_sweeps_per_cycle()
     t0 = time.perf_counter()
     for c in range(args.cycles):
@@ -219,15 +222,17 @@ def main(argv=None):
         print(json.dumps({"cycle": c + 1, "R_c": rc, "fine_sweeps": round(work * (c + 1), 2),
                           "sweep_prec": "f32" if solver.prec == porta.F32 else "f64",
                           "elapsed_s": round(time.perf_counter() - t0, 3)}), flush=True)
+        if rc < args.tol:
+            break
         if args.fp32_until > 0 and rc < args.fp32_until:
             solver.set_precision(porta.F64)
     mg_s = time.perf_counter() - t0
-    out = {"grid": [args.nx, args.nx, args.nz], "levels": args.levels, "cycles": args.cycles,
+    out = {"grid": [args.nx, args.nx, args.nz], "levels": args.levels, "cycles": solver.cycles,
            "rays": cfg.nrays, "freqs": args.nfreq, "prec": args.prec, "mg_seconds": round(mg_s, 3),
            "final_R_c": rc, "fine_sweeps_per_cycle": round(work, 3)}
     if args.jacobi:
         from .jacobi import JacobiSolver
-        js = JacobiSolver(atm, q, prec)
+        js = JacobiSolver(atm, q, prec, opts=porta.options(ray_batch=args.ray_batch))
         t0 = time.perf_counter()
         for it in range(args.jacobi):
             rcj = float(js.step().item())
