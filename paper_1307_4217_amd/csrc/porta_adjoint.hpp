@@ -58,8 +58,11 @@ __device__ inline void kprime_outer(T psi, const T l[4], const T x[4], double g[
   g[5] -= (double)(psi * (l[1] * x[2] - l[2] * x[1]));
 }
 
+// FP32: three waves per SIMD (168 VGPRs); the few spills this costs fall in the per-node
+// set-up and epilogue, not in the frequency loop.
 template <class T>
-__global__ void __launch_bounds__(256) k_adjoint_plane(const AdjArgs<T> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+k_adjoint_plane(const AdjArgs<T> a) {
   extern __shared__ double s_tab[];
   T* s_phi = reinterpret_cast<T*>(s_tab);
   for (int t = threadIdx.x; t < a.nfreq; t += blockDim.x) s_phi[t] = a.phi[t];
