@@ -30,7 +30,8 @@ class Problem(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("z", _dp),
                 ("nmu", C.c_int), ("nchi", C.c_int), ("nfreq", C.c_int),
                 ("mu", _dp), ("wmu", _dp), ("phi", _dp), ("wfreq", _dp),
-                ("i_bottom", C.c_double), ("w2", C.c_double), ("interp", C.c_int)]
+                ("i_bottom", C.c_double), ("w2", C.c_double), ("interp", C.c_int),
+                ("control", C.c_int)]
 
 
 def build(force: bool = True) -> str:
@@ -67,6 +68,8 @@ def lib():
             L.oracle_coefficients.argtypes = [C.c_double, _dp]
             L.oracle_besser_cm.argtypes = [C.c_double] * 5
             L.oracle_besser_cm.restype = C.c_double
+            L.oracle_parabolic_cm.argtypes = [C.c_double] * 5
+            L.oracle_parabolic_cm.restype = C.c_double
             L.oracle_bezier1d.argtypes = [C.c_double] * 4
             L.oracle_bezier1d.restype = C.c_double
             L.oracle_interp_plane.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -91,7 +94,8 @@ def _f64(a):
 class OracleProblem:
     """Holds the NumPy arrays behind a Problem struct."""
 
-    def __init__(self, atm, quad, interp: int = 0, i_bottom: float | None = None):
+    def __init__(self, atm, quad, interp: int = 0, i_bottom: float | None = None,
+                 control: int = 0):
         self.nx, self.ny, self.nz = atm.nx, atm.ny, atm.nz
         self.N = atm.nx * atm.ny * atm.nz
         self.z = _f64(atm.z)
@@ -109,7 +113,7 @@ class OracleProblem:
                               _d(self.z), len(self.mu), self.nchi, self.nfreq, _d(self.mu),
                               _d(self.wmu), _d(self.phi), _d(self.wfreq),
                               float(atm.i_bottom if i_bottom is None else i_bottom),
-                              float(atm.w2), int(interp))
+                              float(atm.w2), int(interp), int(control))
 
     def with_fields(self, kappa=None, prop=None, emis=None):
         """Shallow copy with replaced material arrays."""
@@ -257,6 +261,10 @@ def coefficients(tau: float) -> np.ndarray:
 
 def besser_cm(yM, yO, yP, hM, hP) -> float:
     return lib().oracle_besser_cm(float(yM), float(yO), float(yP), float(hM), float(hP))
+
+
+def parabolic_cm(yM, yO, yP, hM, hP) -> float:
+    return lib().oracle_parabolic_cm(float(yM), float(yO), float(yP), float(hM), float(hP))
 
 
 def bezier1d(ym, y0, yp, t) -> float:

@@ -84,6 +84,8 @@ typedef struct {
   double i_bottom;      /* Stokes I entering at the bottom for upward rays */
   double w2;            /* w^(2) of the transition */
   int interp;           /* 0 bilinear, 1 9-point monotonic Bezier */
+  int control;          /* control point along the ray: 0 BESSER (Sect. 3.2, steps 1-9),
+                           1 parabolic (steps 1, 3, 4 only: the DELOPAR choice) */
 } oracle_problem;
 }
 
@@ -243,6 +245,24 @@ T besser_cm(const T& yM, const T& yO, const T& yP, const T& hM, const T& hP) {
     cM = yO - 0.5 * hM * yd;
   }
   return cM;
+}
+
+/* The control point of the parabola through M, O, P (steps 1, 3 and 4 of Sect. 3.2
+ * without the monotonicity tests): the formal solver then interpolates the source
+ * function parabolically, as DELOPAR does (Sect. 3). */
+template <class T>
+T parabolic_cm(const T& yM, const T& yO, const T& yP, const T& hM, const T& hP) {
+  if (!(rp(hM) > 0.0)) return yO;
+  if (!(rp(hP) > 0.0)) return 0.5 * (yM + yO);   // no downwind point: the chord's midpoint
+  const T dM = (yO - yM) / hM;
+  const T dP = (yP - yO) / hP;
+  const T yd = (hM * dP + hP * dM) / (hM + hP);
+  return yO - 0.5 * hM * yd;
+}
+
+template <class T>
+T control_point(int control, const T& yM, const T& yO, const T& yP, const T& hM, const T& hP) {
+  return control == 1 ? parabolic_cm(yM, yO, yP, hM, hP) : besser_cm(yM, yO, yP, hM, hP);
 }
 
 /* One-dimensional monotonic quadratic Bezier interpolation through three
@@ -427,7 +447,7 @@ void sweep_one(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray, in
           SM[st] = emission(t, st, eM, pb.w2) / etaIM;
           SO[st] = emission(t, st, eO, pb.w2) / etaIO;
           SP[st] = hasP ? emission(t, st, eP, pb.w2) / etaIP : T(0.0);
-          cM[st] = hasP ? besser_cm(SM[st], SO[st], SP[st], tauMO, tauOP)
+          cM[st] = hasP ? control_point(pb.control, SM[st], SO[st], SP[st], tauMO, tauOP)
                         : 0.5 * (SM[st] + SO[st]);   // reading A5
         }
         T KM[4][4], KO[4][4];
@@ -496,7 +516,8 @@ void accumulate_j(const Ray& ray, double Wj, const double* I,
 
 bool valid_problem(const oracle_problem* pb) {
   if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 2 || pb->nmu < 1 || pb->nchi < 1 ||
-      pb->nfreq < 1 || !pb->z || !pb->mu || !pb->wmu || !pb->phi || !pb->wfreq)
+      pb->nfreq < 1 || !pb->z || !pb->mu || !pb->wmu || !pb->phi || !pb->wfreq ||
+      (pb->interp != 0 && pb->interp != 1) || (pb->control != 0 && pb->control != 1))
     return false;
   for (int k = 1; k < pb->nz; ++k)
     if (!(pb->z[k] > pb->z[k - 1])) return false;
@@ -571,7 +592,8 @@ void lc_one(const oracle_problem& pb, const FieldsT<double>& f, const Ray& ray, 
             SM[st] = emission(t, st, eM, pb.w2) / (nM.kap * phi);
             SO[st] = emission(t, st, eO, pb.w2) / (nO.kap * phi);
             SP[st] = hp ? emission(t, st, eP, pb.w2) / (nP->kap * phi) : 0.0;
-            cM[st] = hp ? besser_cm(SM[st], SO[st], SP[st], tauMO, tauOP) : 0.5 * (SM[st] + SO[st]);
+            cM[st] = hp ? control_point(pb.control, SM[st], SO[st], SP[st], tauMO, tauOP)
+                        : 0.5 * (SM[st] + SO[st]);
           }
           double KM[4][4], KO[4][4];
           kprime(hM, nM.kap * phi, KM);
@@ -892,6 +914,10 @@ void oracle_coefficients(double tau, double* out6) {
 
 double oracle_besser_cm(double yM, double yO, double yP, double hM, double hP) {
   return besser_cm(yM, yO, yP, hM, hP);
+}
+
+double oracle_parabolic_cm(double yM, double yO, double yP, double hM, double hP) {
+  return parabolic_cm(yM, yO, yP, hM, hP);
 }
 
 double oracle_bezier1d(double ym, double y0, double yp, double t) {
