@@ -128,7 +128,13 @@ typedef struct {
   int32_t block;            /* threads per block of the sweep kernel (0: 256) */
   int32_t xcd_remap;        /* R > 0: each XCD takes R consecutive tiles per round;
                                0: hardware order; -1: default (8) */
+  int32_t control;          /* control point of the source function along a ray:
+                               PORTA_CONTROL_BESSER (Sect. 3.2, default) or
+                               PORTA_CONTROL_PARABOLIC (parabola through M, O, P: steps
+                               1, 3, 4 only, the DELOPAR choice of Sect. 3) */
 } porta_options;
+
+typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;
 
 /* Bytes of device workspace needed by one call of the given kind (0 on invalid
  * arguments).  `prec` selects the sweep precision; `checkpoint_stride` is

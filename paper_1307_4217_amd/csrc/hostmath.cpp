@@ -20,6 +20,14 @@ double hm_besser_cm(double yM, double yO, double yP, double ratio) {
   return porta::besser_cm(yM, yO, yP, ratio);
 }
 
+double hm_parabolic_cm(double yM, double yO, double yP, double ratio) {
+  return porta::parabolic_cm(yM, yO, yP, ratio);
+}
+
+double hm_parabolic_cm_grad(double yM, double yO, double yP, double ratio, double* d4) {
+  return porta::parabolic_cm_grad(yM, yO, yP, ratio, d4);
+}
+
 double hm_bezier3_f64(double ym, double y0, double yp, double t) {
   return porta::bezier3(ym, y0, yp, t);
 }

@@ -111,6 +111,16 @@ size_t elem(int prec) { return prec == PORTA_F32 ? sizeof(float) : sizeof(double
 
 // Tiles per XCD per round of the plane kernels (measured best on MI355X: 8).
 int xcd_chunk(const porta_options* o) { return (o && o->xcd_remap >= 0) ? o->xcd_remap : 8; }
+int parabolic_of(const porta_options* o) { return (o && o->control == PORTA_CONTROL_PARABOLIC) ? 1 : 0; }
+
+int validate_options(const porta_options* o) {
+  if (!o) return PORTA_OK;
+  if (o->ray_batch < 0 || o->block < 0 || o->xcd_remap < -1)
+    return fail(PORTA_EINVAL, "ray_batch and block must be >= 0, xcd_remap >= -1");
+  if (o->control != PORTA_CONTROL_BESSER && o->control != PORTA_CONTROL_PARABOLIC)
+    return fail(PORTA_EINVAL, "unknown control point rule %d", o->control);
+  return PORTA_OK;
+}
 
 int ray_batch(const porta_quad* q, const porta_options* o) {
   const int nh = q->nmu * q->nchi;
@@ -318,6 +328,8 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
         a.inv_dy = ny / g->ly;
         a.ray0 = ray0;
         a.xcd_remap = xcd_chunk(o);
+  a.parabolic = parabolic_of(o);
+        a.parabolic = parabolic_of(o);
         a.ibound = ibound;
         const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
         const dim3 grid((np + block - 1) / block, nrb);
@@ -375,6 +387,7 @@ int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* 
   a.inv_dy = ny / g->ly;
   a.ray0 = ray0;
   a.xcd_remap = xcd_chunk(o);
+  a.parabolic = parabolic_of(o);
   a.ibound = (T)f->i_bottom;
   const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
   hipLaunchKernelGGL((k_sweep_plane<T, 0>), dim3((np + block - 1) / block, nrb), dim3(block), lds,
@@ -462,6 +475,8 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.inv_dy = ny / g->ly;
         a.ray0 = r0;
         a.xcd_remap = xcd_chunk(o);
+  a.parabolic = parabolic_of(o);
+        a.parabolic = parabolic_of(o);
         a.ibound = (T)f->i_bottom;
         hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
                            lds_adj, st, a);
@@ -568,8 +583,7 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
-  if (opts && (opts->ray_batch < 0 || opts->block < 0 || opts->xcd_remap < -1))
-    return fail(PORTA_EINVAL, "options must be >= 0");
+  if ((rc = validate_options(opts))) return rc;
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
@@ -642,8 +656,7 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
     return fail(PORTA_EINVAL, "seed and gradient arrays must not be NULL");
   if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1)
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
-  if (opts && (opts->ray_batch < 0 || opts->block < 0))
-    return fail(PORTA_EINVAL, "options must be >= 0");
+  if ((rc = validate_options(opts))) return rc;
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");

@@ -44,6 +44,7 @@ struct AdjArgs {
   double inv_dx, inv_dy;
   int ray0;
   int xcd_remap;       // tiles per XCD per round, see xcd_tile
+  int parabolic;       // control point: 0 BESSER, 1 parabola through M, O, P
   T ibound;
 };
 
@@ -75,7 +76,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
   PointSetup ps;
   Stencil9 unused9;
   setup_point<0>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
-                 a.dzP, a.inv_dx, a.inv_dy, rc, p, ps, unused9);
+                 a.dzP, a.inv_dx, a.inv_dy, rc, p, a.parabolic != 0, ps, unused9);
   const int i = p % a.nx, j = p / a.nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   // nodes of the plane above whose upwind stencil contains p
@@ -183,7 +184,10 @@ k_adjoint_plane(const AdjArgs<T> a) {
   for (int s = 0; s < 4; ++s) {
     if (ps.hasP) {
       double d[4];
-      besser_cm_grad(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio, d);
+      if (a.parabolic)
+        parabolic_cm_grad(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio, d);
+      else
+        besser_cm_grad(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio, d);
       gSM[s] += gCM[s] * d[0];
       gSO[s] += gCM[s] * d[1];
       gSP[s] += gCM[s] * d[2];

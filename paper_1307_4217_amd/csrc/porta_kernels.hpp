@@ -204,8 +204,8 @@ template <int MODE, class T>
 __device__ inline void setup_point(const T* __restrict__ kappa, const T* __restrict__ prop,
                                    const T* __restrict__ emis, size_t N, int nx, int ny, int np,
                                    int kO, int kM, int kP, double dzM, double dzP, double inv_dx,
-                                   double inv_dy, const RayConsts& rc, int p, PointSetup& ps,
-                                   Stencil9& sM9) {
+                                   double inv_dy, const RayConsts& rc, int p, bool parabolic,
+                                   PointSetup& ps, Stencil9& sM9) {
   const int i = p % nx, j = p / nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   ps.dsM = dzM * inv_mu;
@@ -274,7 +274,7 @@ __device__ inline void setup_point(const T* __restrict__ kappa, const T* __restr
 #pragma unroll
       for (int c = 0; c < 6; ++c) ep += rc.emis[s][c] * ps.epsP[c];
       ps.SP[s] = ep * ps.ikP;
-      ps.cM[s] = besser_cm(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio);
+      ps.cM[s] = control_cm(ps.SM[s], ps.SO[s], ps.SP[s], ps.ratio, parabolic);
     }
   } else {
     // no downwind plane: linear control point
@@ -365,6 +365,7 @@ struct PlaneArgs {
   double inv_dx, inv_dy;
   int ray0;
   int xcd_remap;     // tiles per XCD per round (0: hardware order), see xcd_tile
+  int parabolic;     // control point: 0 BESSER, 1 parabola through M, O, P
   T ibound;          // Stokes I on the boundary plane of this hemisphere
 };
 
@@ -436,8 +437,13 @@ __device__ inline void upwind_bez9(const T* __restrict__ q, const Stencil9& s,
   }
 }
 
+// Occupancy targets: three waves per SIMD for the FP32 bilinear sweep (168 VGPRs;
+// measured 4.8% faster than leaving the allocation free), two for the others (the
+// 9-point mode would otherwise drop to one).
 template <class T, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_plane(const PlaneArgs<T> a) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MODE == 0 && sizeof(T) == 4 ? 3 : 2)))
+k_sweep_plane(const PlaneArgs<T> a) {
   // per-frequency weights and profile, read from LDS inside the frequency loop so that
   // no vector-memory wait (which on gfx9 also covers earlier stores) sits in the loop
   extern __shared__ double s_tab[];
@@ -460,7 +466,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   PointSetup ps;
   Stencil9 sM9;
   setup_point<MODE>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
-                    a.dzP, a.inv_dx, a.inv_dy, rc, pp, ps, sM9);
+                    a.dzP, a.inv_dx, a.inv_dy, rc, pp, a.parabolic != 0, ps, sM9);
   const BezW<T> bwx = bez_weights(MODE == 1 ? (T)sM9.tx : T(0));
   const BezW<T> bwy = bez_weights(MODE == 1 ? (T)sM9.ty : T(0));
   const Stencil& sM = ps.sM;

@@ -155,6 +155,29 @@ __host__ __device__ inline double besser_cm(double yM, double yO, double yP, dou
   return cM;
 }
 
+// Control point of the parabola through M, O, P: steps 1, 3 and 4 without the
+// monotonicity tests (the choice of the DELOPAR solver), in the same ratio form.
+__host__ __device__ inline double parabolic_cm(double yM, double yO, double yP, double r) {
+  const double dM = yO - yM, dP = yP - yO;
+  return yO - (r * r * dP + dM) * (0.5 / (1.0 + r));
+}
+
+// The control point of either rule from one evaluation of steps 1, 3 and 4: the
+// parabolic rule returns there, BESSER goes on with its tests (same result as
+// besser_cm).
+__host__ __device__ inline double control_cm(double yM, double yO, double yP, double r,
+                                             bool parabolic) {
+  const double dM = yO - yM, dP = yP - yO;
+  const double inv = 0.5 / (1.0 + r);
+  const double cM = yO - (r * r * dP + dM) * inv;
+  if (parabolic) return cM;
+  if (dM * dP <= 0.0) return yO;
+  if ((cM - yM) * (cM - yO) > 0.0) return yM;
+  const double cP = yO + (r * dP + dM / r) * inv;
+  if ((cP - yO) * (cP - yP) > 0.0) return yO - r * dP;
+  return cM;
+}
+
 // The same control point in the sweep precision, for interpolation on the grid.
 template <class T>
 __host__ __device__ inline T besser_cm_t(T yM, T yO, T yP, T r) {
@@ -242,6 +265,18 @@ __host__ __device__ inline double besser_cm_grad(double yM, double yO, double yP
   d[2] = -r * r * inv;
   d[3] = -2.0 * (r * r * dP + 2.0 * r * dP - dM) * inv * inv;
   return cM;
+}
+
+// The parabolic control point with d = (dc/dy_M, dc/dy_O, dc/dy_P, dc/dr).
+__host__ __device__ inline double parabolic_cm_grad(double yM, double yO, double yP, double r,
+                                                    double d[4]) {
+  const double dM = yO - yM, dP = yP - yO;
+  const double inv = 0.5 / (1.0 + r);
+  d[0] = inv;
+  d[1] = 1.0 - (1.0 - r * r) * inv;
+  d[2] = -r * r * inv;
+  d[3] = -2.0 * (r * r * dP + 2.0 * r * dP - dM) * inv * inv;
+  return yO - (r * r * dP + dM) * inv;
 }
 
 // dL/dtau from the adjoints of the six coefficients, with the derivatives

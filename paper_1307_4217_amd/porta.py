@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libporta.so")
 
 F64, F32 = 0, 1
 BILINEAR, BEZIER2D = 0, 1
+CONTROL_BESSER, CONTROL_PARABOLIC = 0, 1
 WS_SWEEP, WS_ADJOINT, WS_JKQ, WS_SEE, WS_ADJOINT_CKPT = 0, 1, 2, 3, 4
 
 _dp = C.POINTER(C.c_double)
@@ -43,7 +44,8 @@ class Atom(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32)]
+    _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32),
+                ("control", C.c_int32)]
 
 
 class PortaError(RuntimeError):
@@ -153,8 +155,9 @@ class HostGrid:
                    quad.phi, quad.wfreq)
 
 
-def options(ray_batch=0, block=0, xcd_remap=-1):
-    return Options(int(ray_batch), int(block), int(xcd_remap))
+def options(ray_batch=0, block=0, xcd_remap=-1, control=0):
+    """porta_options; control = CONTROL_BESSER or CONTROL_PARABOLIC."""
+    return Options(int(ray_batch), int(block), int(xcd_remap), int(control))
 
 
 def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:

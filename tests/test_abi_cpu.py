@@ -170,3 +170,16 @@ def test_kernel_code_digest_found_in_built_library():
         d = bench.kernel_code_sha256(k)
         assert d is not None and re.fullmatch(r"[0-9a-f]{64}", d)
     assert bench.kernel_code_sha256("no such kernel") is None
+
+
+def test_unknown_control_point_rule_rejected():
+    L = porta.lib()
+    hg = small_hg()
+    d = np.zeros(8).ctypes.data
+    f = porta.Fields(d, d, d, 1.0, 1.0)
+    bad = porta.options(control=2)
+    assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, C.byref(bad),
+                            d, 0, d, None, 0, d, 1 << 40, None) == -1
+    assert b"control" in L.porta_last_error()
+    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
+                              C.byref(bad), d, None, 2, d, d, d, d, 1 << 40, None) == -1

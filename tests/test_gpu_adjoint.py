@@ -33,9 +33,9 @@ def gpu_grad(case, w, stride=3, opts=None):
     return [x.cpu().numpy().astype(np.float64) for x in g]
 
 
-def oracle_directional(orc, atm, q, w, dk, dp, de, pairs=None):
+def oracle_directional(orc, atm, q, w, dk, dp, de, pairs=None, control=0):
     """<w, d I_top> along (dk, dp, de) by complex step on the oracle."""
-    op = orc.OracleProblem(atm, q)
+    op = orc.OracleProblem(atm, q, control=control)
     nup = len(q.mu) * q.nchi
     if pairs is None:
         rays, freqs = np.arange(nup), np.arange(len(q.phi))
@@ -279,3 +279,24 @@ def test_adjoint_with_checkpoints_from_the_sweep(prec, stride, rb_fwd, rb_adj):
     torch.cuda.synchronize()
     for a, b in zip(own, ext):
         assert torch.equal(a, b)
+
+
+def test_adjoint_with_parabolic_control_point(orc):
+    """FP64 adjoint through the parabolic control point (no clamps, so its derivative
+    is the linear formula of steps 3-4 and the ratio) against the oracle's complex step."""
+    atm, q = tiny_case(porta.F64, seed=14, nx=5, ny=4, nz=6)
+    case = Case(atm, q, porta.F64)
+    rng = np.random.default_rng(15)
+    w = seed_for(case, rng)
+    opts = porta.options(control=porta.CONTROL_PARABOLIC)
+    for stride in (1, 3):
+        g = gpu_grad(case, w, stride=stride, opts=opts)
+        v = [rng.normal(size=atm.npoints) * atm.kappa,
+             rng.normal(size=(6, atm.npoints)) * atm.kappa,
+             rng.normal(size=(6, atm.npoints)) * atm.emis.std(axis=1, keepdims=True)]
+        got = sum(np.sum(a * b) for a, b in zip(g, v))
+        ref = oracle_directional(orc, atm, q, w, *v, control=1)
+        assert got == pytest.approx(ref, rel=1e-10)
+    # and it is a different derivative from the BESSER one
+    gb = gpu_grad(case, w, stride=1)
+    assert max(np.abs(a - b).max() for a, b in zip(g, gb)) > 0

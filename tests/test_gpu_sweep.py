@@ -206,3 +206,32 @@ def test_bezier2d_mode_matches_oracle(orc, prec):
         _, it_bl = Case(atm, q, prec).sweep()
         assert np.abs(it_bl - itop).max() > 1e-6
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_parabolic_control_point_matches_oracle(orc, prec):
+    """porta_options.control = PARABOLIC (the parabola through M, O, P, as DELOPAR
+    interpolates the source function) against the oracle's control = 1, also combined
+    with the 9-point interpolation in FP64."""
+    import torch
+    tol_i, tol_p = (1e-10, 1e-12) if prec == porta.F64 else (2e-5, 1e-7)
+    opts = porta.options(control=porta.CONTROL_PARABOLIC)
+    cases = [(inputs.CONFIGS["C1"], 0, porta.BILINEAR),
+             (inputs.Config("rag", 7, 5, 9, 2, 3, 5, True), 4, porta.BILINEAR)]
+    if prec == porta.F64:
+        cases.append((inputs.Config("rag", 7, 5, 9, 2, 3, 5, True), 4, porta.BEZIER2D))
+    for cfg, seed, interp in cases:
+        atm = inputs.make_atmosphere(cfg, seed=seed)
+        if cfg.name == "rag":
+            atm = dataclasses.replace(atm, lx=530.0, ly=410.0)
+        if prec == porta.F32:
+            atm = rounded(atm, np.float32)
+        q = inputs.make_quadrature(cfg)
+        ref = orc.fs_sweep(orc.OracleProblem(atm, q, interp=interp, control=1))
+        jkq, itop = Case(atm, q, prec).sweep(interp=interp, opts=opts)
+        what = f"parabolic {cfg.name} interp {interp}"
+        compare_stokes(itop, up_rays(ref["itop"], q), tol_i, tol_p, what)
+        compare_jkq(jkq, ref["jkq"], tol_i, what)
+        _, it_b = Case(atm, q, prec).sweep(interp=interp)
+        assert np.abs(it_b - itop).max() > 1e-8       # BESSER clamps somewhere
+        torch.cuda.synchronize()

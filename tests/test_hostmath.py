@@ -22,6 +22,10 @@ def hm():
     L.hm_coefficients_f64.argtypes = [C.c_double, _dp]
     L.hm_besser_cm.argtypes = [C.c_double] * 4
     L.hm_besser_cm.restype = C.c_double
+    L.hm_parabolic_cm.argtypes = [C.c_double] * 4
+    L.hm_parabolic_cm.restype = C.c_double
+    L.hm_parabolic_cm_grad.argtypes = [C.c_double] * 4 + [_dp]
+    L.hm_parabolic_cm_grad.restype = C.c_double
     L.hm_bezier3_f64.argtypes = [C.c_double] * 4
     L.hm_bezier3_f64.restype = C.c_double
     L.hm_bezier3_f32.argtypes = [C.c_float] * 4
@@ -222,3 +226,24 @@ def test_bezier3_closed_form_equals_branchy_besser(hm, orc):
         assert hm.hm_bezier3_f64(ym, y0, yp, t) == pytest.approx(ref, abs=4e-16 * scale)
         f = hm.hm_bezier3_f32(ym, y0, yp, t)
         assert f == pytest.approx(ref, abs=3e-6 * scale)
+
+
+def test_parabolic_control_point_matches_oracle_and_its_gradient(hm, orc):
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        y = rng.normal(size=3)
+        hM, hP = rng.uniform(0.05, 3.0, 2)
+        r = hM / hP
+        assert hm.hm_parabolic_cm(*y, r) == pytest.approx(orc.parabolic_cm(*y, hM, hP),
+                                                          rel=1e-13, abs=1e-14)
+        d = np.zeros(4)
+        c = hm.hm_parabolic_cm_grad(*y, r, p(d))
+        assert c == hm.hm_parabolic_cm(*y, r)
+        args = [*y, r]
+        for k in range(4):
+            h = 1e-6 * max(1.0, abs(args[k]))
+            up, dn = list(args), list(args)
+            up[k] += h
+            dn[k] -= h
+            fd = (hm.hm_parabolic_cm(*up) - hm.hm_parabolic_cm(*dn)) / (2 * h)
+            assert d[k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
