@@ -429,9 +429,11 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
   const size_t lds_adj = (size_t)q->nfreq * sizeof(T);
   for (r0 = 0; r0 < nh; r0 += nrb_max) {
     const int nrb = std::min(nrb_max, nh - r0);
-    // forward pass keeping every C-th plane (unless the sweep already kept them)
+    // forward pass up to the last checkpoint plane, keeping every C-th plane (unless
+    // the sweep already kept them); the planes above it are recomputed with the top
+    // segment
     if (!ext_ck)
-      for (int k = 1; k < nz; ++k)
+      for (int k = 1; k <= C * checkpoint_count(nz, C); ++k)
         if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
                                    st)))
           return rc;
@@ -440,7 +442,9 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
     int cur = 0;
     for (int khi = nz - 1; khi >= 1;) {
       const int s0 = C * ((khi - 1) / C);
-      for (int k = s0 + 1; k <= khi; ++k)
+      // the adjoint of plane k reads the forward state of plane k-1 only, so the top
+      // plane of a segment needs no state
+      for (int k = s0 + 1; k < khi; ++k)
         if (!is_checkpoint(k, nz, C))
           if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
                                      st)))
@@ -453,7 +457,6 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.rays = reinterpret_cast<const RayConsts*>(ws + L.rays);
         a.phi = reinterpret_cast<const T*>(ws + L.phiT);
         a.iprev = plane(k - 1);
-        a.icur = plane(k);
         a.lam_next = lam_next;
         a.seed = seed + (size_t)r0 * q->nfreq * np * 4;
         a.lam_cur = (k - 1 >= 1) ? lam[cur] : nullptr;

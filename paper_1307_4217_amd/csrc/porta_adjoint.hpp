@@ -30,7 +30,6 @@ struct AdjArgs {
   const RayConsts* rays;
   const T* phi;
   const T* iprev;      // forward state of plane kM, or nullptr for the boundary plane
-  const T* icur;       // forward state of plane kO
   const T* lam_next;   // Lambda of plane kO + 1, or nullptr when kO is the top plane
   const T* seed;       // dL/dI on the top plane for this batch (used when lam_next is null)
   T* lam_cur;          // Lambda of plane kO, or nullptr when plane kM is the boundary
@@ -104,7 +103,6 @@ k_adjoint_plane(const AdjArgs<T> a) {
   const size_t fstride = (size_t)a.np * 4;
   const size_t rstride = (size_t)a.nfreq * fstride;
   const T* ip = a.iprev ? a.iprev + rb * rstride : nullptr;
-  const T* cp = a.icur + rb * rstride + (size_t)p * 4;
   const T* lp = a.lam_next ? a.lam_next + rb * rstride : nullptr;
   const T* sp = a.seed + rb * rstride + (size_t)p * 4;
   T* lo = a.lam_cur ? a.lam_cur + rb * rstride + (size_t)p * 4 : nullptr;
@@ -138,18 +136,23 @@ k_adjoint_plane(const AdjArgs<T> a) {
       IM[0] = a.ibound;
       IM[1] = IM[2] = IM[3] = T(0);
     }
-    T IO[4];
-    load4(cp + fo, IO);
     const T ph = s_phi[f];
     const T tau = tau0 * ph;
     const Coefs<T> cf = coefficients(tau);
-    // lambda_b = (1 + psi'_O K'_O)^-T lambda
+    // the forward update at O again (Eq. fsbez), instead of reading the stored I_O
+    T KIM[4], b[4], IO[4];
+    kprime_apply(eMv, rMv, IM, KIM);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      b[s] = cf.e * IM[s] - cf.psiM * KIM[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
     const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
-    const T ron[3] = {-cf.psiO * rOv[0], -cf.psiO * rOv[1], -cf.psiO * rOv[2]};
+    const T ro[3] = {cf.psiO * rOv[0], cf.psiO * rOv[1], cf.psiO * rOv[2]};
+    solve_stokes(eo, ro, b, IO);
+    // lambda_b = (1 + psi'_O K'_O)^-T lambda
+    const T ron[3] = {-ro[0], -ro[1], -ro[2]};
     T lb[4];
     solve_stokes(eo, ron, lam, lb);
-    T KIM[4], KIO[4];
-    kprime_apply(eMv, rMv, IM, KIM);
+    T KIO[4];
     kprime_apply(eOv, rOv, IO, KIO);
     T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;
 #pragma unroll
