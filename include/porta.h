@@ -132,6 +132,13 @@ typedef struct {
                                PORTA_CONTROL_BESSER (Sect. 3.2, default) or
                                PORTA_CONTROL_PARABOLIC (parabola through M, O, P: steps
                                1, 3, 4 only, the DELOPAR choice of Sect. 3) */
+  int32_t stokes;           /* 0 or 4: the Stokes vector (default); 1: intensity only,
+                               the unpolarized problem (K' = 0, emission eps^0_0; the
+                               propagation matrix and the K = 2 emissivities are not
+                               read).  With 1, i_top holds one value per node
+                               ([nmu*nchi][nfreq][ny][nx]), J^K_Q comes from Stokes I
+                               alone, and checkpoints, PORTA_INTERP_BEZIER2D and
+                               porta_fs_adjoint return PORTA_EUNSUPPORTED */
 } porta_options;
 
 typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;
@@ -158,6 +165,7 @@ size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int
  *                   or added to (accumulate = 1)
  *   i_top         : device [nmu*nchi][nfreq][ny][nx][4] (sweep precision),
  *                   Stokes vectors of the upward rays at z[nz-1], or NULL
+ *                   ([..][nx] without the Stokes axis when opts->stokes == 1)
  *   checkpoints   : device, porta_checkpoint_size() bytes, or NULL; filled with
  *                   the upward rays' states every checkpoint_stride planes for a
  *                   later porta_fs_adjoint of the same fields (no extra traffic:

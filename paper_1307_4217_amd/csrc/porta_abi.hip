@@ -13,6 +13,7 @@
 #include "porta_adjoint.hpp"
 #include "porta_host.hpp"
 #include "porta_kernels.hpp"
+#include "porta_unpol.hpp"
 
 namespace porta {
 namespace host {
@@ -112,6 +113,8 @@ size_t elem(int prec) { return prec == PORTA_F32 ? sizeof(float) : sizeof(double
 // Tiles per XCD per round of the plane kernels (measured best on MI355X: 8).
 int xcd_chunk(const porta_options* o) { return (o && o->xcd_remap >= 0) ? o->xcd_remap : 8; }
 int parabolic_of(const porta_options* o) { return (o && o->control == PORTA_CONTROL_PARABOLIC) ? 1 : 0; }
+// Stokes parameters carried by the sweep: 4, or 1 for the unpolarized problem.
+int nstokes(const porta_options* o) { return (o && o->stokes == 1) ? 1 : 4; }
 
 int validate_options(const porta_options* o) {
   if (!o) return PORTA_OK;
@@ -119,6 +122,8 @@ int validate_options(const porta_options* o) {
     return fail(PORTA_EINVAL, "ray_batch and block must be >= 0, xcd_remap >= -1");
   if (o->control != PORTA_CONTROL_BESSER && o->control != PORTA_CONTROL_PARABOLIC)
     return fail(PORTA_EINVAL, "unknown control point rule %d", o->control);
+  if (o->stokes != 0 && o->stokes != 1 && o->stokes != 4)
+    return fail(PORTA_EINVAL, "stokes must be 0 or 4 (Stokes vector) or 1 (intensity only)");
   return PORTA_OK;
 }
 
@@ -166,7 +171,7 @@ Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const po
   Layout L = tables_layout(q, prec);
   const size_t np = (size_t)g->nx * g->ny;
   const size_t nrb = (size_t)ray_batch(q, o);
-  const size_t state = nrb * q->nfreq * np * 4 * elem(prec);
+  const size_t state = nrb * q->nfreq * np * nstokes(o) * elem(prec);
   size_t off = L.end_tables;
   L.stateA = off;
   off = align_up(off + state);
@@ -269,6 +274,7 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
     if ((rc = fill(jkq, 10 * N, 0.0, st))) return rc;
   const int nh = q->nmu * q->nchi;
   const int nrb_max = ray_batch(q, o);
+  const int ns = nstokes(o);
   const int block = (o && o->block > 0) ? o->block : 256;
   if (block % 64 != 0 || block > 256) return fail(PORTA_EINVAL, "block must be 64, 128, 192 or 256");
   const RayConsts* rays = reinterpret_cast<const RayConsts*>(ws + L.rays);
@@ -301,7 +307,7 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
         a.wn = wn;
         a.iprev = prev;
         const bool last = (step == nz - 1);
-        const size_t batch_off = (size_t)r0 * q->nfreq * np * 4;
+        const size_t batch_off = (size_t)r0 * q->nfreq * np * ns;
         if (last && up && itop)
           a.inext = itop + batch_off;
         else if (up && ckpt && is_checkpoint(k, nz, C))   // kept for the adjoint
@@ -328,12 +334,13 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
         a.inv_dy = ny / g->ly;
         a.ray0 = ray0;
         a.xcd_remap = xcd_chunk(o);
-  a.parabolic = parabolic_of(o);
         a.parabolic = parabolic_of(o);
         a.ibound = ibound;
         const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
         const dim3 grid((np + block - 1) / block, nrb);
-        if (interp == PORTA_INTERP_BEZIER2D)
+        if (ns == 1)
+          hipLaunchKernelGGL(k_sweep_plane_i<T>, grid, dim3(block), lds, st, a);
+        else if (interp == PORTA_INTERP_BEZIER2D)
           hipLaunchKernelGGL((k_sweep_plane<T, 1>), grid, dim3(block), lds, st, a);
         else
           hipLaunchKernelGGL((k_sweep_plane<T, 0>), grid, dim3(block), lds, st, a);
@@ -478,7 +485,6 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.inv_dy = ny / g->ly;
         a.ray0 = r0;
         a.xcd_remap = xcd_chunk(o);
-  a.parabolic = parabolic_of(o);
         a.parabolic = parabolic_of(o);
         a.ibound = (T)f->i_bottom;
         hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
@@ -587,6 +593,10 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
   if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
   if ((rc = validate_options(opts))) return rc;
+  if (nstokes(opts) == 1 && interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
+  if (nstokes(opts) == 1 && checkpoints)
+    return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
@@ -660,6 +670,8 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1)
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if ((rc = validate_options(opts))) return rc;
+  if (nstokes(opts) == 1)
+    return fail(PORTA_EUNSUPPORTED, "the adjoint is for the Stokes-vector sweep");
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");

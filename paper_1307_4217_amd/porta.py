@@ -45,7 +45,7 @@ class Atom(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32),
-                ("control", C.c_int32)]
+                ("control", C.c_int32), ("stokes", C.c_int32)]
 
 
 class PortaError(RuntimeError):
@@ -155,9 +155,10 @@ class HostGrid:
                    quad.phi, quad.wfreq)
 
 
-def options(ray_batch=0, block=0, xcd_remap=-1, control=0):
-    """porta_options; control = CONTROL_BESSER or CONTROL_PARABOLIC."""
-    return Options(int(ray_batch), int(block), int(xcd_remap), int(control))
+def options(ray_batch=0, block=0, xcd_remap=-1, control=0, stokes=4):
+    """porta_options; control = CONTROL_BESSER or CONTROL_PARABOLIC; stokes = 4 (Stokes
+    vector) or 1 (intensity only, the unpolarized problem)."""
+    return Options(int(ray_batch), int(block), int(xcd_remap), int(control), int(stokes))
 
 
 def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:
@@ -196,8 +197,10 @@ def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, int
     if want_jkq and jkq is None:
         jkq = torch.empty((10, hg.N), dtype=torch.float64, device=dev)
     if want_itop and i_top is None:
-        i_top = torch.empty((hg.nray_up, hg.nfreq, hg.ny, hg.nx, 4), dtype=dtype_of(prec),
-                            device=dev)
+        shape = (hg.nray_up, hg.nfreq, hg.ny, hg.nx)
+        if not (opts is not None and opts.stokes == 1):
+            shape += (4,)
+        i_top = torch.empty(shape, dtype=dtype_of(prec), device=dev)
     if workspace is None:
         workspace = _workspace(workspace_size(hg, prec, WS_SWEEP, 1, opts), dev)
     f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))

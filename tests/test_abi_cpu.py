@@ -183,3 +183,24 @@ def test_unknown_control_point_rule_rejected():
     assert b"control" in L.porta_last_error()
     assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
                               C.byref(bad), d, None, 2, d, d, d, d, 1 << 40, None) == -1
+
+
+def test_intensity_only_option_checks():
+    L = porta.lib()
+    hg = small_hg()
+    d = np.zeros(8).ctypes.data
+    f = porta.Fields(d, d, d, 1.0, 1.0)
+    args = lambda o, interp=0, ck=None, stride=0: (C.byref(hg.grid), C.byref(hg.quad), C.byref(f),
+                                                   0, interp, C.byref(o), d, 0, d, ck, stride, d,
+                                                   1 << 40, None)
+    assert L.porta_fs_sweep(*args(porta.options(stokes=2))) == -1
+    assert L.porta_fs_sweep(*args(porta.options(stokes=1), interp=1)) == -2
+    assert L.porta_fs_sweep(*args(porta.options(stokes=1), ck=d, stride=2)) == -2
+    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
+                              C.byref(porta.options(stokes=1)), d, None, 2, d, d, d, d, 1 << 40,
+                              None) == -2
+    # the workspace of the intensity-only sweep holds a quarter of the plane states
+    w4 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1, porta.options(ray_batch=4))
+    w1 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1,
+                              porta.options(ray_batch=4, stokes=1))
+    assert w1 < w4

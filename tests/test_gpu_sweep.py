@@ -235,3 +235,35 @@ def test_parabolic_control_point_matches_oracle(orc, prec):
         _, it_b = Case(atm, q, prec).sweep(interp=interp)
         assert np.abs(it_b - itop).max() > 1e-8       # BESSER clamps somewhere
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_intensity_only_sweep_matches_oracle(orc, prec):
+    """opts.stokes = 1 (the unpolarized problem: K' = 0, emission eps^0_0) on the full
+    synthetic model, whose propagation matrix and K = 2 emissivities it must ignore,
+    against the oracle on the same model with those set to zero (where Q = U = V = 0):
+    Stokes I at the top, every J^K_Q (from I alone) and Lambda-bar."""
+    import torch
+    tol = 1e-10 if prec == porta.F64 else 2e-5
+    cases = [(inputs.CONFIGS["C1"], 0, porta.options(stokes=1)),
+             (inputs.Config("rag", 7, 5, 9, 2, 3, 5, True), 4,
+              porta.options(ray_batch=3, block=64, stokes=1, control=porta.CONTROL_PARABOLIC))]
+    for cfg, seed, opts in cases:
+        atm = inputs.make_atmosphere(cfg, seed=seed)
+        if cfg.name == "rag":
+            atm = dataclasses.replace(atm, lx=530.0, ly=410.0)
+        if prec == porta.F32:
+            atm = rounded(atm, np.float32)
+        q = inputs.make_quadrature(cfg)
+        emis0 = atm.emis.copy()
+        emis0[1:] = 0.0
+        ref_atm = dataclasses.replace(atm, propmat=0 * atm.propmat, emis=emis0)
+        ref = orc.fs_sweep(orc.OracleProblem(ref_atm, q, control=opts.control))
+        want = up_rays(ref["itop"], q)
+        assert np.abs(want[..., 1:]).max() == 0.0
+        jkq, itop = Case(atm, q, prec).sweep(opts=opts)
+        assert itop.shape == want.shape[:-1]
+        rel = np.abs(itop - want[..., 0]) / np.abs(want[..., 0])
+        assert rel.max() <= tol, f"{cfg.name}: I max rel err {rel.max():.3e}"
+        compare_jkq(jkq, ref["jkq"], tol, f"intensity-only {cfg.name}")
+        torch.cuda.synchronize()
