@@ -51,17 +51,59 @@ def _linear_1d(c, axis, periodic):
     return np.moveaxis(out, 0, axis)
 
 
-def prolong(c, nxc, nyc, nzc):
-    """Tri-linear prolongation (Sect. 6.2): coarse [k][nzc*nyc*nxc] -> fine [k][N_f].
-    Nodes on coarse nodes take the coarse value, nodes on coarse lines and planes are
-    interpolated linearly and bilinearly, the rest tri-linearly: the tensor product of
-    one-dimensional linear interpolation along z, y and x."""
+def _lagrange_weights(nodes, x):
+    """Weights of the Lagrange polynomial through `nodes` evaluated at x."""
+    w = []
+    for a in nodes:
+        v = 1.0
+        for b in nodes:
+            if b != a:
+                v *= (x - b) / (a - b)
+        w.append(v)
+    return w
+
+
+def _cubic_1d(c, axis, periodic):
+    """Cubic interpolation along one axis to twice the resolution: node 2i takes c[i];
+    node 2i+1 takes the cubic through the four coarse nodes around it, i-1 .. i+2
+    (periodic axis), or, next to the ends of a non-periodic axis, through the four
+    nodes nearest to it inside the axis (Sect. 6.2)."""
+    c = np.moveaxis(c, axis, 0)
+    n = c.shape[0]
+    nf = 2 * n if periodic else 2 * n - 1
+    out = np.empty((nf,) + c.shape[1:])
+    for i in range(nf):
+        if i % 2 == 0:
+            out[i] = c[i // 2]
+            continue
+        x = i / 2.0                                  # position in coarse units
+        if periodic:
+            base = i // 2 - 1
+            nodes = [base, base + 1, base + 2, base + 3]
+            idx = [m % n for m in nodes]
+        else:
+            base = min(max(i // 2 - 1, 0), n - 4)
+            nodes = [base, base + 1, base + 2, base + 3]
+            idx = nodes
+        w = _lagrange_weights(nodes, x)
+        out[i] = sum(wk * c[m] for wk, m in zip(w, idx))
+    return np.moveaxis(out, 0, axis)
+
+
+def prolong(c, nxc, nyc, nzc, order=1):
+    """Prolongation (Sect. 6.2): coarse [k][nzc*nyc*nxc] -> fine [k][N_f].
+    order 1, tri-linear: nodes on coarse nodes take the coarse value, nodes on coarse
+    lines and planes are interpolated linearly and bilinearly, the rest tri-linearly.
+    order 3, tri-cubic-centred: the same with cubic interpolation through four coarse
+    nodes per axis (4^3 nodes for the tri-cubic case); needs n_z of the coarse grid
+    >= 4.  Both are tensor products of one-dimensional interpolations along z, y, x."""
     c = np.asarray(c, dtype=np.float64)
     k = c.shape[0]
     g = c.reshape(k, nzc, nyc, nxc)
-    g = _linear_1d(g, 1, periodic=False)
-    g = _linear_1d(g, 2, periodic=True)
-    g = _linear_1d(g, 3, periodic=True)
+    one_d = _linear_1d if order == 1 else _cubic_1d
+    g = one_d(g, 1, periodic=False)
+    g = one_d(g, 2, periodic=True)
+    g = one_d(g, 3, periodic=True)
     return g.reshape(k, -1)
 
 
@@ -152,7 +194,7 @@ def make_levels(atm, quad, nlevels, interp=0):
     return levels
 
 
-def vcycle(levels, S, f, l=0, nu1=2, nu2=4, ncoarse=20):
+def vcycle(levels, S, f, l=0, nu1=2, nu2=4, ncoarse=20, order=1):
     """One V-cycle of the FAS scheme of Sect. 6.1 on levels[l:] (levels[0] finest):
     nu1 Jacobi smoothing iterations, the residual, restriction of rho and of the
     residual, the coarse-grid equation L_c(rho_c) rho_c = L_c(R rho) R rho + R r
@@ -170,10 +212,32 @@ def vcycle(levels, S, f, l=0, nu1=2, nu2=4, ncoarse=20):
     coarse = levels[l + 1]
     Sc = restrict(S, nx, ny, nz)
     fc = orc.see_operator(coarse.radiation(Sc), Sc, coarse.atm) + restrict(r, nx, ny, nz)
-    Sc_new = vcycle(levels, Sc.copy(), fc, l + 1, nu1, nu2, ncoarse)
-    S = S + prolong(Sc_new - Sc, *coarse.shape)
+    Sc_new = vcycle(levels, Sc.copy(), fc, l + 1, nu1, nu2, ncoarse, order)
+    S = S + prolong(Sc_new - Sc, *coarse.shape, order=order)
     for _ in range(nu2):
         S, _ = lev.jacobi(S, f)
+    return S
+
+
+def nested(levels, S0, cycles=1, nu1=2, nu2=4, ncoarse=20, order=1):
+    """Nested multigrid: solve on the coarsest grid (ncoarse Jacobi iterations from S0
+    injected there), then on each finer grid start from the prolonged solution of the
+    grid below and apply `cycles` V-cycles on it and the grids below it.  Returns the
+    finest-grid S."""
+    # the initial guess on every level: S0 sampled at its nodes
+    guesses = [np.asarray(S0, dtype=np.float64)]
+    for lev in levels[:-1]:
+        guesses.append(inject(guesses[-1], *lev.shape))
+    top = len(levels) - 1
+    S = guesses[top]
+    f = levels[top].planck_rhs()
+    for _ in range(ncoarse):
+        S, _ = levels[top].jacobi(S, f)
+    for l in range(top - 1, -1, -1):
+        S = prolong(S, *levels[l + 1].shape, order=order)
+        f = levels[l].planck_rhs()
+        for _ in range(cycles):
+            S = vcycle(levels, S, f, l, nu1, nu2, ncoarse, order)
     return S
 
 

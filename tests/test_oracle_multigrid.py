@@ -181,3 +181,55 @@ def test_coarse_grid_correction_accelerates_smoothing(mg):
         S2 = cycle(S1)
         ratios.append(mg.relative_change(S2, S1) / mg.relative_change(S1, S))
     assert ratios[0] < 0.3 * ratios[1]
+
+
+def test_tricubic_prolongation_reproduces_cubics(mg):
+    """The tri-cubic-centred prolongation is exact for cubic polynomials along z (also
+    next to the boundaries, where the interpolant shifts inward) and along x away from
+    the periodic seam, and takes the coarse values on coarse nodes."""
+    nxc, nyc, nzc = 8, 3, 6
+    nx, ny, nz = 2 * nxc, 2 * nyc, 2 * nzc - 1
+    p3 = lambda t: 0.3 * t ** 3 - 1.1 * t * t + 0.7 * t - 2.0
+    kc = np.arange(nzc, dtype=float)
+    cz = np.repeat(p3(kc), nyc * nxc)[None, :]
+    fz = mg.prolong(cz, nxc, nyc, nzc, order=3).reshape(nz, ny, nx)
+    np.testing.assert_allclose(fz[:, 0, 0], p3(np.arange(nz) / 2.0), rtol=1e-13, atol=1e-13)
+    ic = np.arange(nxc, dtype=float)
+    cx = np.tile(p3(ic), nzc * nyc)[None, :]
+    fx = mg.prolong(cx, nxc, nyc, nzc, order=3).reshape(nz, ny, nx)
+    inner = np.arange(2, 2 * nxc - 4)          # stencils that do not cross the seam
+    np.testing.assert_allclose(fx[0, 0, inner], p3(inner / 2.0), rtol=1e-13, atol=1e-13)
+    rng = np.random.default_rng(6)
+    c = rng.normal(size=(2, nzc * nyc * nxc))
+    f = mg.prolong(c, nxc, nyc, nzc, order=3)
+    np.testing.assert_array_equal(mg.inject(f, nx, ny, nz), c)
+    # the centred weights (-1, 9, 9, -1)/16 and the boundary ones (5, 15, -5, 1)/16
+    e = np.zeros((1, nzc * nyc * nxc))
+    e[0, 0] = 1.0                               # coarse node (0, 0, 0)
+    g = mg.prolong(e, nxc, nyc, nzc, order=3).reshape(nz, ny, nx)
+    assert g[1, 0, 0] == pytest.approx(5 / 16)              # z: first interval
+    assert g[0, 0, 1] == pytest.approx(9 / 16)              # x: centred, right of node 0
+    assert g[0, 0, 2 * nxc - 1] == pytest.approx(9 / 16)    # x: across the periodic seam
+    assert g[0, 0, 3] == pytest.approx(-1 / 16)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_fas_fixed_point_with_either_prolongation(mg, tiny_problem, order):
+    atm, q, f, s_star = tiny_problem
+    levels = mg.make_levels(atm, q, 2)
+    S = mg.vcycle(levels, s_star.copy(), f, ncoarse=10, order=order)
+    np.testing.assert_allclose(S, s_star, rtol=0, atol=1e-12 * np.abs(s_star).max())
+
+
+def test_nested_multigrid_starts_closer_than_a_vcycle(mg):
+    """Nested multigrid (coarsest-grid solution prolonged upwards, one V-cycle per grid)
+    leaves a smaller residual than one V-cycle from the flat initial guess, for a few
+    coarse-grid sweeps more."""
+    atm, q = _atmosphere(16, 16, 33, nfreq=3)
+    levels = mg.make_levels(atm, q, 3)
+    f = levels[0].planck_rhs()
+    r_v = np.abs(levels[0].residual(mg.vcycle(levels, atm.source.copy(), f, ncoarse=20), f))
+    S = mg.nested(levels, atm.source, cycles=1, ncoarse=20)
+    r_n = np.abs(levels[0].residual(S, f))
+    assert r_n.max() < 0.5 * r_v.max()
+    assert r_n[0].max() < 0.1 * r_v[0].max()
