@@ -243,12 +243,15 @@ int porta_mg_restrict(int nx, int ny, int nz, int ncomp, const double* fine, dou
 
 /*
  * porta_mg_prolong: fine += P(coarse_a - coarse_b) (coarse_b may be NULL), P the
- *   tri-linear prolongation of Sect. 6.2: a fine node on a coarse node takes its value,
- *   one on a coarse line or plane the linear or bilinear mean, the others the
- *   tri-linear mean of 8 coarse nodes.  FP64.  With kappa (device [Nf], precision
+ *   prolongation of Sect. 6.2 of the given order.  order 1, tri-linear: a fine node on
+ *   a coarse node takes its value, one on a coarse line or plane the linear or
+ *   bilinear mean, the others the tri-linear mean of 8 coarse nodes.  order 3,
+ *   tri-cubic-centred: the same with cubics through 4 coarse nodes per axis (centred,
+ *   periodic in x and y; next to the ends of z the four nearest nodes inside), up to
+ *   4^3 nodes; needs (nz + 1)/2 >= 4.  FP64.  With kappa (device [Nf], precision
  *   prec), emis = kappa * fine is written too ([ncomp][Nf]); both or neither.
  */
-int porta_mg_prolong(int nx, int ny, int nz, int ncomp, const double* coarse_a,
+int porta_mg_prolong(int nx, int ny, int nz, int ncomp, int order, const double* coarse_a,
                      const double* coarse_b, double* fine, const void* kappa, void* emis,
                      int prec, void* stream);
 

@@ -129,10 +129,13 @@ __global__ void __launch_bounds__(256) k_restrict(const RestrictArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Tri-linear prolongation of a coarse difference (Sect. 6.2): thread = fine node;
-// fine += P(a - b) (b may be absent), where a fine node on a coarse node takes its
-// value, one on a coarse line or plane the linear or bilinear mean, the rest the
-// tri-linear mean of 8 coarse nodes.  Optionally emis = kappa * fine.
+// Prolongation of a coarse difference (Sect. 6.2): thread = fine node; fine += P(a - b)
+// (b may be absent).  Along each axis a fine node on a coarse node takes its value;
+// one between coarse nodes takes the linear mean of the two (order 1) or the cubic
+// through four coarse nodes (order 3: centred, periodic in x and y; shifted inward next
+// to the ends of z).  The tensor product gives tri-linear or tri-cubic-centred
+// interpolation, bilinear / bicubic on coarse planes and linear / cubic on coarse
+// lines.  Optionally emis = kappa * fine.
 // ---------------------------------------------------------------------------
 template <class T>
 struct ProlongArgs {
@@ -141,8 +144,38 @@ struct ProlongArgs {
   double* fine;
   const T* kappa;     // or nullptr
   T* emis;            // or nullptr
-  int nx, ny, nz, ncomp;
+  int nx, ny, nz, ncomp, order;
 };
+
+// Coarse indices and weights along one axis for fine index f (n coarse nodes).
+__device__ inline int prolong_axis(int f, int n, bool periodic, int order, int idx[4],
+                                   double w[4]) {
+  const int c = f >> 1;
+  if ((f & 1) == 0) {
+    idx[0] = c;
+    w[0] = 1.0;
+    return 1;
+  }
+  if (order == 1) {
+    idx[0] = c;
+    idx[1] = (c + 1 == n) ? 0 : c + 1;   // only reached on a periodic axis at the seam
+    w[0] = w[1] = 0.5;
+    return 2;
+  }
+  int base = c - 1;
+  if (!periodic) base = base < 0 ? 0 : (base > n - 4 ? n - 4 : base);
+  const double x = c + 0.5;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double v = 1.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b != a) v *= (x - (base + b)) / (double)(a - b);
+    w[a] = v;
+    idx[a] = periodic ? wrap_index(base + a, n) : base + a;
+  }
+  return 4;
+}
 
 template <class T>
 __global__ void __launch_bounds__(256) k_prolong(const ProlongArgs<T> a) {
@@ -151,26 +184,22 @@ __global__ void __launch_bounds__(256) k_prolong(const ProlongArgs<T> a) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= Nf) return;
   const int i = (int)(p % a.nx), j = (int)((p / a.nx) % a.ny), k = (int)(p / ((size_t)a.nx * a.ny));
-  // two coarse indices and weights per axis (the second weight 0 on coarse nodes)
-  const int x0 = i >> 1, x1 = (x0 + 1 == nxc) ? 0 : x0 + 1;
-  const int y0 = j >> 1, y1 = (y0 + 1 == nyc) ? 0 : y0 + 1;
-  const int z0 = k >> 1, z1 = (k & 1) ? z0 + 1 : z0;
-  const double wx1 = (i & 1) ? 0.5 : 0.0, wy1 = (j & 1) ? 0.5 : 0.0, wz1 = (k & 1) ? 0.5 : 0.0;
-  const double wx[2] = {1.0 - wx1, wx1}, wy[2] = {1.0 - wy1, wy1}, wz[2] = {1.0 - wz1, wz1};
-  const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+  int xi[4], yi[4], zi[4];
+  double xw[4], yw[4], zw[4];
+  const int nxs = prolong_axis(i, nxc, true, a.order, xi, xw);
+  const int nys = prolong_axis(j, nyc, true, a.order, yi, yw);
+  const int nzs = prolong_axis(k, nzc, false, a.order, zi, zw);
   for (int c = 0; c < a.ncomp; ++c) {
     double acc = 0.0;
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const double w = wz[dz] * wy[dy] * wx[dx];
-          if (w == 0.0) continue;
-          const size_t q = (size_t)c * Nc + ((size_t)zs[dz] * nyc + ys[dy]) * nxc + xs[dx];
-          acc += w * (a.cb ? a.ca[q] - a.cb[q] : a.ca[q]);
+    for (int dz = 0; dz < nzs; ++dz)
+      for (int dy = 0; dy < nys; ++dy) {
+        const size_t row = (size_t)c * Nc + ((size_t)zi[dz] * nyc + yi[dy]) * nxc;
+        const double wzy = zw[dz] * yw[dy];
+        for (int dx = 0; dx < nxs; ++dx) {
+          const size_t q = row + xi[dx];
+          acc += wzy * xw[dx] * (a.cb ? a.ca[q] - a.cb[q] : a.ca[q]);
         }
+      }
     const size_t o = (size_t)c * Nf + p;
     const double v = a.fine[o] + acc;
     a.fine[o] = v;

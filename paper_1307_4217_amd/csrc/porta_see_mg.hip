@@ -117,11 +117,14 @@ int porta_mg_restrict(int nx, int ny, int nz, int ncomp, const double* fine, dou
   return check_launch("mg_restrict");
 }
 
-int porta_mg_prolong(int nx, int ny, int nz, int ncomp, const double* coarse_a,
+int porta_mg_prolong(int nx, int ny, int nz, int ncomp, int order, const double* coarse_a,
                      const double* coarse_b, double* fine, const void* kappa, void* emis,
                      int prec, void* stream) {
   int rc;
   if ((rc = validate_coarsening(nx, ny, nz, ncomp)) || (rc = validate_prec(prec))) return rc;
+  if (order != 1 && order != 3) return fail(PORTA_EINVAL, "order must be 1 or 3");
+  if (order == 3 && (nz + 1) / 2 < 4)
+    return fail(PORTA_EINVAL, "cubic prolongation needs at least 4 coarse planes (nz >= 7)");
   if (!coarse_a || !fine) return fail(PORTA_EINVAL, "NULL argument");
   if ((emis == nullptr) != (kappa == nullptr))
     return fail(PORTA_EINVAL, "kappa and emis go together");
@@ -129,11 +132,11 @@ int porta_mg_prolong(int nx, int ny, int nz, int ncomp, const double* coarse_a,
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (prec == PORTA_F64) {
     ProlongArgs<double> a{coarse_a, coarse_b, fine, static_cast<const double*>(kappa),
-                          static_cast<double*>(emis), nx, ny, nz, ncomp};
+                          static_cast<double*>(emis), nx, ny, nz, ncomp, order};
     hipLaunchKernelGGL(k_prolong<double>, dim3(blocks_for(Nf)), dim3(256), 0, st, a);
   } else {
     ProlongArgs<float> a{coarse_a, coarse_b, fine, static_cast<const float*>(kappa),
-                         static_cast<float*>(emis), nx, ny, nz, ncomp};
+                         static_cast<float*>(emis), nx, ny, nz, ncomp, order};
     hipLaunchKernelGGL(k_prolong<float>, dim3(blocks_for(Nf)), dim3(256), 0, st, a);
   }
   return check_launch("mg_prolong");

@@ -88,11 +88,12 @@ class MultigridSolver:
     keeping the current iterate (J, the SEE and the transfers are FP64 either way)."""
 
     def __init__(self, atm, quad, nlevels=2, prec=porta.F64, device="cuda:0", opts=None,
-                 nu1=2, nu2=4, ncoarse=20):
+                 nu1=2, nu2=4, ncoarse=20, order=1):
         import torch
         self.torch = torch
         self.atm, self.quad, self.nlevels, self.opts = atm, quad, nlevels, opts
         self.nu1, self.nu2, self.ncoarse = nu1, nu2, ncoarse
+        self.order = order          # prolongation: 1 tri-linear, 3 tri-cubic-centred
         self.dev = torch.device(device)
         self.levels = []
         self._build_levels(prec)
@@ -160,7 +161,7 @@ class MultigridSolver:
         co.operator(co.r, 1.0, co.f)                        # f_c = L_c(R rho) R rho + R r
         self._vcycle(l + 1, co.f)
         porta.mg_prolong(lev.S, nx, ny, nz, co.S, co.S0, kappa=lev.kappa, emis=lev.emis,
-                         prec=lev.prec)
+                         prec=lev.prec, order=self.order)
         for _ in range(self.nu2):
             lev.jacobi(rhs)
 
@@ -169,6 +170,32 @@ class MultigridSolver:
         fine = self.levels[0]
         self.S_prev.copy_(fine.S)
         self._vcycle(0, None)
+        self.cycles += 1
+        return porta.rel_change(fine.S, self.S_prev, rc=self.rc, workspace=fine.ws_see)
+
+    def nested(self, cycles=1):
+        """Nested multigrid from the current finest-grid S: that S sampled on the
+        coarsest grid is relaxed by ncoarse Jacobi iterations, and each finer grid
+        starts from the prolonged solution of the grid below and takes `cycles`
+        V-cycles (Sect. 6; the nested scheme of Fabiani Bendicho et al.).  Returns the
+        device scalar R_c of the last finest-grid cycle."""
+        fine = self.levels[0]
+        self.S_prev.copy_(fine.S)
+        top = len(self.levels) - 1
+        for l in range(top):                      # initial guess on every grid
+            up, lo = self.levels[l], self.levels[l + 1]
+            lo.S.copy_(porta.mg_inject(up.S, *up.dims))
+        co = self.levels[top]
+        porta.emissivity(co.kappa, co.S, emis=co.emis)
+        for _ in range(self.ncoarse):
+            co.jacobi(None)
+        for l in range(top - 1, -1, -1):
+            lev, lo = self.levels[l], self.levels[l + 1]
+            lev.S.zero_()
+            porta.mg_prolong(lev.S, *lev.dims, lo.S, kappa=lev.kappa, emis=lev.emis,
+                             prec=lev.prec, order=self.order)
+            for _ in range(cycles):
+                self._vcycle(l, None)
         self.cycles += 1
         return porta.rel_change(fine.S, self.S_prev, rc=self.rc, workspace=fine.ws_see)
 
@@ -198,6 +225,9 @@ def main(argv=None):
     ap.add_argument("--jacobi", type=int, default=0, help="also run this many Jacobi iterations")
     ap.add_argument("--ncoarse", type=int, default=20)
     ap.add_argument("--ray-batch", type=int, default=40)
+    ap.add_argument("--cubic", action="store_true", help="tri-cubic-centred prolongation")
+    ap.add_argument("--nested", action="store_true",
+                    help="start with one nested-multigrid pass instead of a V-cycle")
     ap.add_argument("--prec", default="f64", choices=["f32", "f64"])
     ap.add_argument("--fp32-until", type=float, default=0.0,
                     help="sweep in FP32 until R_c drops below this value, then in FP64")
@@ -214,11 +244,12 @@ def main(argv=None):
         prec = porta.F32
     import torch
     solver = MultigridSolver(atm, q, args.levels, prec, ncoarse=args.ncoarse,
-                             opts=porta.options(ray_batch=args.ray_batch))
+                             opts=porta.options(ray_batch=args.ray_batch),
+                             order=3 if args.cubic else 1)
     work = solver.fine_sweeps_per_cycle()
     t0 = time.perf_counter()
     for c in range(args.cycles):
-        rc = float(solver.vcycle().item())
+        rc = float((solver.nested() if (args.nested and c == 0) else solver.vcycle()).item())
         print(json.dumps({"cycle": c + 1, "R_c": rc, "fine_sweeps": round(work * (c + 1), 2),
                           "sweep_prec": "f32" if solver.prec == porta.F32 else "f64",
                           "elapsed_s": round(time.perf_counter() - t0, 3)}), flush=True)

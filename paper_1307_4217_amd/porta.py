@@ -85,7 +85,7 @@ def lib():
                                              vp, vp]
             ci = C.c_int
             L.porta_mg_restrict.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, vp]
-            L.porta_mg_prolong.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, vp]
+            L.porta_mg_prolong.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, vp]
             L.porta_mg_inject.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp]
             L.porta_rel_change.argtypes = [C.c_int64, vp, vp, vp, vp, sz, vp]
             L.porta_emissivity.argtypes = [C.c_int64, ci, vp, vp, vp, ci, vp]
@@ -286,9 +286,11 @@ def mg_restrict(fine, nx, ny, nz, out=None, kappa_c=None, emis_c=None, prec=F64,
 
 
 def mg_prolong(fine, nx, ny, nz, coarse_a, coarse_b=None, kappa=None, emis=None, prec=F64,
-               stream=None):
-    """porta_mg_prolong: fine += P(coarse_a - coarse_b), in place; returns fine."""
-    st = lib().porta_mg_prolong(int(nx), int(ny), int(nz), int(fine.shape[0]), _ptr(coarse_a),
+               stream=None, order=1):
+    """porta_mg_prolong: fine += P(coarse_a - coarse_b), in place (order 1 tri-linear,
+    3 tri-cubic-centred); returns fine."""
+    st = lib().porta_mg_prolong(int(nx), int(ny), int(nz), int(fine.shape[0]), int(order),
+                                _ptr(coarse_a),
                                 _ptr(coarse_b), _ptr(fine), _ptr(kappa), _ptr(emis), int(prec),
                                 _stream(stream))
     _check("porta_mg_prolong", st)

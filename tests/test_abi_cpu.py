@@ -151,11 +151,13 @@ def test_multigrid_entry_points_validate():
     for nx, ny, nz, k, prec in ((5, 4, 5, 1, 0), (4, 4, 6, 1, 0), (4, 4, 1, 1, 0), (0, 4, 5, 1, 0),
                                 (4, 4, 5, 0, 0), (4, 4, 5, 65, 0), (4, 4, 5, 1, 7)):
         assert L.porta_mg_restrict(nx, ny, nz, k, d, d, None, None, prec, None) == -1
-        assert L.porta_mg_prolong(nx, ny, nz, k, d, None, d, None, None, prec, None) == -1
+        assert L.porta_mg_prolong(nx, ny, nz, k, 1, d, None, d, None, None, prec, None) == -1
     assert L.porta_mg_restrict(4, 4, 5, 1, d, d, d, None, 0, None) == -1
-    assert L.porta_mg_prolong(4, 4, 5, 1, d, None, d, None, d, 0, None) == -1
+    assert L.porta_mg_prolong(4, 4, 5, 1, 1, d, None, d, None, d, 0, None) == -1
+    assert L.porta_mg_prolong(4, 4, 9, 1, 2, d, None, d, None, None, 0, None) == -1   # order
+    assert L.porta_mg_prolong(4, 4, 5, 1, 3, d, None, d, None, None, 0, None) == -1   # nzc < 4
     assert L.porta_mg_restrict(4, 4, 5, 1, None, d, None, None, 0, None) == -1
-    assert L.porta_mg_prolong(4, 4, 5, 1, None, None, d, None, None, 0, None) == -1
+    assert L.porta_mg_prolong(4, 4, 5, 1, 1, None, None, d, None, None, 0, None) == -1
     assert L.porta_mg_inject(4, 4, 5, 1, 2, d, d, None) == -1
     assert L.porta_mg_inject(4, 4, 4, 1, 8, d, d, None) == -1
     assert L.porta_rel_change(10, d, d, d, d, 4, None) == -3
