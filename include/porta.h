@@ -24,7 +24,7 @@
  *    of all rays sum to one.
  *  - Frequencies: every absorption and emission coefficient is its
  *    line-centre value times phi[j] (complete redistribution, one line
- *    profile).  The frequency weights of Eq. 1 are renormalized on the
+ *    profile).  The frequency weights of Eq. 1 are renormalized (Sect. 4.2) on the
  *    discrete grid: W_j = wfreq[j] phi[j] / sum_j' wfreq[j'] phi[j'].
  *  - Multipole components are stored in the order
  *    (X00, X20, Re X21, Im X21, Re X22, Im X22); the Q < 0 components follow
@@ -215,7 +215,7 @@ int porta_see_update(int64_t npoints, const double* jkq, const porta_atom* atom,
  * unknowns, L(rho) rho of Sect. 2 Eq. nonlte (left-hand sides above, with J from
  * the formal solution of these s), combined as
  *   out = base + sign * L(rho) rho,   base = [6][N] FP64 or, if NULL, (eps_c B, 0, ...).
- * sign = -1 gives the residual r = f - L(rho) rho of Sect. 6.1 Eq. resid; sign = +1
+ * sign = -1 gives the residual r = f - L(rho) rho of Sect. 5.1 Eq. resid; sign = +1
  * with base = R(r) gives the coarse-grid right-hand side of Eq. mgcsfy.
  *   jkq : device [10][N] FP64 (Lbar unused); s, out : device [6][N] FP64.
  * out may not alias s or jkq; it may alias base.
@@ -225,7 +225,7 @@ int porta_see_operator(int64_t npoints, const double* jkq, const porta_atom* ato
                        void* stream);
 
 /*
- * Grid transfer of the multigrid iteration (Sect. 6.1-6.2).  The coarser grid keeps
+ * Grid transfer of the multigrid iteration (Sect. 5.1-5.2).  The coarser grid keeps
  * every second node along each axis: coarse node (i, j, k) is fine node (2i, 2j, 2k).
  * The fine grid (nx, ny, nz) needs even nx, ny >= 2 (periodic; coarse nx/2, ny/2)
  * and odd nz >= 3 (coarse (nz+1)/2); otherwise PORTA_EINVAL.  Fields are
@@ -243,7 +243,7 @@ int porta_mg_restrict(int nx, int ny, int nz, int ncomp, const double* fine, dou
 
 /*
  * porta_mg_prolong: fine += P(coarse_a - coarse_b) (coarse_b may be NULL), P the
- *   prolongation of Sect. 6.2 of the given order.  order 1, tri-linear: a fine node on
+ *   prolongation of Sect. 5.2 of the given order.  order 1, tri-linear: a fine node on
  *   a coarse node takes its value, one on a coarse line or plane the linear or
  *   bilinear mean, the others the tri-linear mean of 8 coarse nodes.  order 3,
  *   tri-cubic-centred: the same with cubics through 4 coarse nodes per axis (centred,

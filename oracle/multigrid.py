@@ -1,11 +1,11 @@
-"""Non-linear multigrid (FAS) iteration of the two-level problem (Sect. 6 of the paper),
+"""Non-linear multigrid (FAS) iteration of the two-level problem (Sect. 5 of the paper),
 written plainly on top of the oracle's formal solver and statistical equilibrium.
 
 TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg of the
 benchmark may import this module.  The GPU library never calls it.
 
 Grids: the grid of level l-1 keeps every second node of level l along each axis, so
-coarse node (i, j, k) is fine node (2i, 2j, 2k) (Sect. 6.1).  x and y are periodic
+coarse node (i, j, k) is fine node (2i, 2j, 2k) (Sect. 5.1).  x and y are periodic
 (n_x, n_y even); z is not (n_z odd, both boundary planes kept).  Fields are [c][N]
 arrays with x fastest, N = n_z n_y n_x.
 
@@ -16,7 +16,7 @@ Readings where the paper is silent:
   fine one sampled at the coarse nodes (injection); the quadrature is the same;
 * the restriction is the adjoint of tri-linear prolongation divided by the sum of its
   weights, so that it maps a constant to itself; at a z boundary this leaves the
-  2 x 3^2 nodes of Sect. 6.2 with z weights (2/3, 1/3);
+  2 x 3^2 nodes of Sect. 5.2 with z weights (2/3, 1/3);
 * the coarsest grid is "solved" by a fixed number of Jacobi iterations.
 """
 from __future__ import annotations
@@ -67,7 +67,7 @@ def _cubic_1d(c, axis, periodic):
     """Cubic interpolation along one axis to twice the resolution: node 2i takes c[i];
     node 2i+1 takes the cubic through the four coarse nodes around it, i-1 .. i+2
     (periodic axis), or, next to the ends of a non-periodic axis, through the four
-    nodes nearest to it inside the axis (Sect. 6.2)."""
+    nodes nearest to it inside the axis (Sect. 5.2)."""
     c = np.moveaxis(c, axis, 0)
     n = c.shape[0]
     nf = 2 * n if periodic else 2 * n - 1
@@ -91,7 +91,7 @@ def _cubic_1d(c, axis, periodic):
 
 
 def prolong(c, nxc, nyc, nzc, order=1):
-    """Prolongation (Sect. 6.2): coarse [k][nzc*nyc*nxc] -> fine [k][N_f].
+    """Prolongation (Sect. 5.2): coarse [k][nzc*nyc*nxc] -> fine [k][N_f].
     order 1, tri-linear: nodes on coarse nodes take the coarse value, nodes on coarse
     lines and planes are interpolated linearly and bilinearly, the rest tri-linearly.
     order 3, tri-cubic-centred: the same with cubic interpolation through four coarse
@@ -108,7 +108,7 @@ def prolong(c, nxc, nyc, nzc, order=1):
 
 
 def restrict(f, nx, ny, nz):
-    """Restriction (Sect. 6.2): at each coarse node, the weighted mean of the 3^3 fine
+    """Restriction (Sect. 5.2): at each coarse node, the weighted mean of the 3^3 fine
     nodes around it with weights w(dx) w(dy) w(dz), w(0) = 1, w(+-1) = 1/2 (the
     adjoint of tri-linear prolongation), over the nodes that exist."""
     f = np.asarray(f, dtype=np.float64)
@@ -195,7 +195,7 @@ def make_levels(atm, quad, nlevels, interp=0):
 
 
 def vcycle(levels, S, f, l=0, nu1=2, nu2=4, ncoarse=20, order=1):
-    """One V-cycle of the FAS scheme of Sect. 6.1 on levels[l:] (levels[0] finest):
+    """One V-cycle of the FAS scheme of Sect. 5.1 on levels[l:] (levels[0] finest):
     nu1 Jacobi smoothing iterations, the residual, restriction of rho and of the
     residual, the coarse-grid equation L_c(rho_c) rho_c = L_c(R rho) R rho + R r
     (Eq. mgcsfy) solved by the next V-cycle (Jacobi iterations on the coarsest grid),

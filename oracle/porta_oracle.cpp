@@ -758,7 +758,7 @@ int oracle_jkq_accumulate(const oracle_problem* pb, int ray0, int nray, int f0, 
  *              - (1-eps) w2 conj(J2_Q)                             = f2_Q   (Q = -2..2)
  * with Kmat the matrix of b.J in the rank-2 representation; f = (eps B, 0, ...)
  * for the problem itself, another right-hand side on the coarse grids of the
- * multigrid iteration (Sect. 6, Eq. mgcsfy).  Components with Q < 0 follow from
+ * multigrid iteration (Sect. 5, Eq. mgcsfy).  Components with Q < 0 follow from
  * X_{-Q} = (-1)^Q conj(X_Q) for S, J and f alike. */
 namespace {
 

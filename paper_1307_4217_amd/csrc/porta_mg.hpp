@@ -1,4 +1,4 @@
-// Kernels of the non-linear multigrid iteration (Sect. 6): the statistical-equilibrium
+// Kernels of the non-linear multigrid iteration (Sect. 5): the statistical-equilibrium
 // operator L(rho) rho, restriction, prolongation and injection between a grid and the
 // next coarser one, and the maximum relative change between two iterates.
 //
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_see_operator(const SeeOpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Restriction (Sect. 6.2): thread = coarse node; the weighted mean of the 3^3 fine
+// Restriction (Sect. 5.2): thread = coarse node; the weighted mean of the 3^3 fine
 // nodes around it with weights w(dx) w(dy) w(dz), w(0) = 1, w(+-1) = 1/2 (the adjoint
 // of tri-linear prolongation), over the nodes that exist (2 x 3^2 at a z boundary),
 // for ncomp components.  Optionally also emis = kappa_c * out in the sweep precision.
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_restrict(const RestrictArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Prolongation of a coarse difference (Sect. 6.2): thread = fine node; fine += P(a - b)
+// Prolongation of a coarse difference (Sect. 5.2): thread = fine node; fine += P(a - b)
 // (b may be absent).  Along each axis a fine node on a coarse node takes its value;
 // one between coarse nodes takes the linear mean of the two (order 1) or the cubic
 // through four coarse nodes (order 3: centred, periodic in x and y; shifted inward next

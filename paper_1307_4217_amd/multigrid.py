@@ -1,8 +1,8 @@
-"""Non-linear multigrid (FAS) iteration of the two-level problem on the GPU (Sect. 6).
+"""Non-linear multigrid (FAS) iteration of the two-level problem on the GPU (Sect. 5).
 
 Each level is a grid with every second node of the finer one (x, y periodic with even
 n_x, n_y; z with odd n_z), its model sampled at those nodes (porta_mg_inject), and the
-same quadrature.  A V-cycle on level l (Sect. 6.1):
+same quadrature.  A V-cycle on level l (Sect. 5.1):
 
   nu1 Jacobi iterations           porta_fs_sweep + porta_see_update (rhs f_l)
   residual r = f - L(rho) rho     porta_fs_sweep + porta_see_operator (sign -1)
@@ -177,7 +177,7 @@ class MultigridSolver:
         """Nested multigrid from the current finest-grid S: that S sampled on the
         coarsest grid is relaxed by ncoarse Jacobi iterations, and each finer grid
         starts from the prolonged solution of the grid below and takes `cycles`
-        V-cycles (Sect. 6; the nested scheme of Fabiani Bendicho et al.).  Returns the
+        V-cycles (Sect. 5; the nested scheme of Fabiani Bendicho et al.).  Returns the
         device scalar R_c of the last finest-grid cycle."""
         fine = self.levels[0]
         self.S_prev.copy_(fine.S)

@@ -1,4 +1,4 @@
-"""GPU multigrid calls (Sect. 6) against the oracle: grid transfer, the statistical-
+"""GPU multigrid calls (Sect. 5) against the oracle: grid transfer, the statistical-
 equilibrium operator and right-hand side, and whole V-cycles."""
 import dataclasses
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's multigrid iteration (Sect. 6): the transfer operators against
+"""Pins of the oracle's multigrid iteration (Sect. 5): the transfer operators against
 library interpolation and their defining identities, the statistical-equilibrium
 operator against the Jacobi update, and the FAS cycle against a direct solution of
 the (linear, two-level) discrete problem on a tiny grid."""
@@ -164,7 +164,7 @@ def test_vcycles_converge_to_the_discrete_solution(mg):
 
 
 def test_coarse_grid_correction_accelerates_smoothing(mg):
-    """Sect. 6.1: the same cycle (2 + 4 Jacobi iterations around a residual) reduces
+    """Sect. 5.1: the same cycle (2 + 4 Jacobi iterations around a residual) reduces
     R_c several times more with the coarse-grid correction than without it."""
     atm, q = _atmosphere(16, 16, 33, nfreq=5)
     levels = mg.make_levels(atm, q, 2)
