@@ -392,25 +392,6 @@ __device__ inline void xcd_tile(int chunk, int& bx, int& by) {
 
 constexpr int kMaxFreq = 4096;   // frequencies held in LDS by the sweep kernels
 
-#ifndef PORTA_PREFETCH_F32
-#define PORTA_PREFETCH_F32 0
-#endif
-#ifndef PORTA_PREFETCH_F64
-#define PORTA_PREFETCH_F64 0
-#endif
-// Whether the frequency loop fetches the upwind values one frequency ahead
-// (costs 16 registers of the sweep precision).
-template <class T>
-struct SweepTraits;
-template <>
-struct SweepTraits<float> {
-  static constexpr bool kPrefetch = PORTA_PREFETCH_F32;
-};
-template <>
-struct SweepTraits<double> {
-  static constexpr bool kPrefetch = PORTA_PREFETCH_F64;
-};
-
 template <class T>
 __device__ inline void load_upwind(const T* __restrict__ q, const Stencil& s, T v[4][4]) {
   load4(q + 4 * (size_t)s.i00, v[0]);
@@ -537,20 +518,6 @@ k_sweep_plane(const PlaneArgs<T> a) {
       T IM[4];
       upwind_bez9(ip + (size_t)f * fstride, sM9, bwx, bwy, IM);
       update(f, IM[0], IM[1], IM[2], IM[3]);
-    }
-  } else if (SweepTraits<T>::kPrefetch) {
-    // two register sets for the upwind values: the loads of frequency f + 1 are in
-    // flight while frequency f is computed
-    T va[4][4], vb[4][4];
-    load_upwind(ip, sM, va);
-    for (int f = 0; f < a.nfreq; f += 2) {
-      const bool has1 = f + 1 < a.nfreq;
-      if (has1) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vb);
-      update(f, PORTA_BILIN(va, 0), PORTA_BILIN(va, 1), PORTA_BILIN(va, 2), PORTA_BILIN(va, 3));
-      if (!has1) break;
-      if (f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, va);
-      update(f + 1, PORTA_BILIN(vb, 0), PORTA_BILIN(vb, 1), PORTA_BILIN(vb, 2),
-             PORTA_BILIN(vb, 3));
     }
   } else {
     T v[4][4];
