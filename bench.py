@@ -124,17 +124,22 @@ def kernel_code_sha256(kernel, lib_path=None):
     return None
 
 
-def measured_traffic(kernel, workload_matches):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None if
-    the kernel's machine code differs from the one the counters were taken on (or the
-    workload differs)."""
+def measured_counters(kernel, workload_matches):
+    """The committed counter record of a kernel (HBM bytes per launch from FETCH_SIZE /
+    WRITE_SIZE, VALU busy), or None if the kernel's machine code differs from the one the
+    counters were taken on (or the workload differs)."""
     if not workload_matches or not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
     k = rec["kernels"].get(kernel)
     if k is None or k.get("code_sha256") != kernel_code_sha256(kernel):
         return None
-    return k["traffic_bytes_per_launch"]
+    return k
+
+
+def measured_traffic(kernel, workload_matches):
+    k = measured_counters(kernel, workload_matches)
+    return None if k is None else k["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, atm, q, pairs):
@@ -289,10 +294,12 @@ def main():
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
     kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
-    traffic = measured_traffic(kname, cfg.name == "C3" and nrb == 40 and args.block in (0, 256))
+    counters = measured_counters(kname, cfg.name == "C3" and nrb == 40 and args.block in (0, 256))
+    traffic = None if counters is None else counters["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname,
+                "valu_busy_pct": None if counters is None else counters.get("valu_busy_pct"),
                 "launch_ms": round(launch_ms, 4), "bytes_per_launch": lbytes,
                 "updates_per_launch": lupd}
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
