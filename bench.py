@@ -7,8 +7,11 @@ the fused FP64 J^K_Q / Lambda* integration, the FP64 statistical-equilibrium
 update that rewrites the emissivities for the next iteration, and the FP32
 reverse-sweep adjoint of an emergent-Stokes loss sum (I_top - target)^2
 (gradients with respect to eta_I, the propagation matrix and the
-emissivities; planes recomputed from checkpoints).  Inputs are seeded
-synthetic fields already resident in HBM.  Prints one JSON line on stdout.
+emissivities).  The upward rays go range by range: a range is swept keeping
+every plane and reversed at once, and the downward rays are swept after them;
+where those planes do not fit in device memory, one forward sweep keeps every
+C-th plane and the adjoint recomputes the rest.  Inputs are seeded synthetic
+fields already resident in HBM.  Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -23,7 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_c3_fp32.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -41,7 +44,16 @@ def parse():
                     help="rays swept together in the forward sweep and in the adjoint")
     ap.add_argument("--adjoint-ray-batch", type=int, default=0,
                     help="rays per batch in the adjoint (default: --ray-batch)")
-    ap.add_argument("--checkpoint-stride", type=int, default=11)
+    ap.add_argument("--checkpoint-stride", type=int, default=11,
+                    help="checkpoint stride of the shared schedule")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "interleaved", "shared"],
+                    help="interleaved: each range of upward rays is swept keeping every plane, "
+                         "then reversed at once (no recompute); shared: one forward sweep keeps "
+                         "every C-th plane and the adjoint recomputes the others; auto: "
+                         "interleaved when its checkpoints fit in device memory")
+    ap.add_argument("--range-rays", type=int, default=0,
+                    help="upward rays per range of the interleaved schedule (0: the most, up "
+                         "to 16, whose checkpoints fit)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-fp64-rate", action="store_true",
@@ -124,22 +136,28 @@ def kernel_code_sha256(kernel, lib_path=None):
     return None
 
 
-def measured_counters(kernel, workload_matches):
-    """The committed counter record of a kernel (HBM bytes per launch from FETCH_SIZE /
-    WRITE_SIZE, VALU busy), or None if the kernel's machine code differs from the one the
-    counters were taken on (or the workload differs)."""
-    if not workload_matches or not os.path.exists(COUNTERS):
-        return None
-    rec = json.load(open(COUNTERS))
-    k = rec["kernels"].get(kernel)
-    if k is None or k.get("code_sha256") != kernel_code_sha256(kernel):
-        return None
-    return k
+def counter_workload(cfg, prec_name, schedule, nrb, range_rays):
+    """The workload string under which the counters of a run are committed."""
+    w = f"{cfg.nx}x{cfg.ny}x{cfg.nz} grid, {cfg.nrays} rays, {cfg.nfreq} frequencies, " \
+        f"{'FP32' if prec_name == 'f32' else 'FP64'}"
+    if schedule == "interleaved":
+        return w + f", interleaved ranges of {range_rays} upward rays, downward ray batch {nrb}"
+    return w + f", ray batch {nrb}"
 
 
-def measured_traffic(kernel, workload_matches):
-    k = measured_counters(kernel, workload_matches)
-    return None if k is None else k["traffic_bytes_per_launch"]
+def measured_counters(kernel, workload):
+    """The committed counter record of a kernel for a workload (HBM bytes per launch from
+    FETCH_SIZE / WRITE_SIZE, VALU busy), or None if there is none or the kernel's machine
+    code differs from the one the counters were taken on."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "hbm_counters_*.json"))):
+        rec = json.load(open(path))
+        if rec.get("workload") != workload:
+            continue
+        k = rec["kernels"].get(kernel)
+        if k is not None and k.get("code_sha256") == kernel_code_sha256(kernel):
+            return k
+    return None
 
 
 def cpu_baseline(cfg, atm, q, pairs):
@@ -194,10 +212,44 @@ def main():
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
     opts = porta.options(ray_batch=args.ray_batch, block=args.block)
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
-    nbatches = -(-(cfg.nmu * cfg.nchi) // nrb)
     adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block)
     ws_bytes = porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts)
-    if not args.no_adjoint:
+    nh = hg.nray_up
+    schedule = "shared" if args.no_adjoint else args.schedule
+    if schedule in ("auto", "interleaved"):
+        # rays per range: checkpoints of every plane for them, plus the adjoint's
+        # workspace beyond the sweep's, must fit beside what is already resident
+        fixed = (2 * hg.nray_up * cfg.nfreq * cfg.npoints // cfg.nz * 4 * elem   # I_top, target
+                 + 26 * cfg.npoints * (elem + 8) + ws_bytes)
+        free = torch.cuda.mem_get_info()[0] - fixed - (8 << 30)
+        want = [args.range_rays] if args.range_rays > 0 else range(min(16, nh), 0, -1)
+        range_rays = 0
+        for n in want:
+            o = porta.options(ray_batch=n, block=args.block, ray_count=n)
+            need = (porta.checkpoint_size(hg, prec, 1, o)
+                    + max(0, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1, o)
+                          - ws_bytes))
+            if need <= free:
+                range_rays = n
+                break
+        if range_rays:
+            schedule = "interleaved"
+        elif schedule == "interleaved":
+            sys.exit(f"the interleaved schedule needs more device memory than is free")
+        else:
+            schedule = "shared"
+    if schedule == "interleaved":
+        ranges = [(r, min(range_rays, nh - r)) for r in range(0, nh, range_rays)]
+        range_opts = [porta.options(ray_batch=range_rays, block=args.block, ray_first=r,
+                                    ray_count=n) for r, n in ranges]
+        down_opts = porta.options(ray_batch=args.ray_batch, block=args.block, ray_first=nh,
+                                  ray_count=nh)
+        # the sweep of a range and its adjoint run one after the other and share one
+        # workspace with the sweep of the downward rays
+        ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1,
+                                                      range_opts[0]),
+                       porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, range_opts[0]))
+    elif not args.no_adjoint:
         # the sweep and the adjoint run one after the other and share one workspace
         ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
                                                       args.checkpoint_stride, adj_opts))
@@ -212,18 +264,28 @@ def main():
         # loss target: emergent Stokes vectors of a seeded perturbed atmosphere
         tatm = inputs.perturbed_target_atmosphere(atm, seed=5)
         target = torch.empty_like(itop)
-        porta.fs_sweep(hg, t(tatm.kappa, tdt), t(tatm.propmat, tdt), t(tatm.emis, tdt),
-                       atm.i_bottom, atm.w2, prec=prec, want_jkq=False, i_top=target, opts=opts,
-                       workspace=ws)
-        del tatm
-        # the forward sweep of each step keeps the upward rays' checkpoint planes for the
-        # adjoint, which then only recomputes the planes between checkpoints
-        ckpt = torch.empty(porta.checkpoint_size(hg, prec, args.checkpoint_stride) + 256,
-                           dtype=torch.uint8, device=dev)
+        tk, tp, te = t(tatm.kappa, tdt), t(tatm.propmat, tdt), t(tatm.emis, tdt)
+        # swept with the launches of one step, so that a profile of the whole run holds
+        # the step's mix of launch shapes
+        for o in (range_opts + [down_opts] if schedule == "interleaved" else [opts]):
+            porta.fs_sweep(hg, tk, tp, te, atm.i_bottom, atm.w2, prec=prec, want_jkq=False,
+                           i_top=target, opts=o, workspace=ws)
+        del tatm, tk, tp, te
+        if schedule == "interleaved":
+            # every plane of one range of upward rays, reused range after range
+            ckpt = torch.empty(porta.checkpoint_size(hg, prec, 1, range_opts[0]) + 256,
+                               dtype=torch.uint8, device=dev)
+        else:
+            # the forward sweep of each step keeps the upward rays' checkpoint planes for
+            # the adjoint, which then only recomputes the planes between checkpoints
+            ckpt = torch.empty(porta.checkpoint_size(hg, prec, args.checkpoint_stride) + 256,
+                               dtype=torch.uint8, device=dev)
         ws_adj = ws
         g_k, g_p, g_e = torch.empty_like(kappa), torch.empty_like(prop), torch.empty_like(emis)
-        log(f"shared sweep/adjoint workspace {ws.numel() / 1e9:.2f} GB, checkpoints "
-            f"{ckpt.numel() / 1e9:.2f} GB (stride {args.checkpoint_stride})")
+        log(f"{schedule} schedule: sweep/adjoint workspace {ws.numel() / 1e9:.2f} GB, "
+            f"checkpoints {ckpt.numel() / 1e9:.2f} GB "
+            + (f"(every plane of {range_rays} rays at a time)" if schedule == "interleaved"
+               else f"(stride {args.checkpoint_stride})"))
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     # the SEE writes the next emissivities into a second buffer, swapped in after the
@@ -236,7 +298,45 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    def step_interleaved(times):
+        # per step: [sweep ms, SEE ms, adjoint ms] from events around every call
+        emis_cur = state["emis"]
+        marks = []
+        g_k.zero_(), g_p.zero_(), g_e.zero_()
+        for i, (r, n) in enumerate(ranges):
+            e = [ev() for _ in range(3)]
+            e[0].record()
+            porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
+                           accumulate=i > 0, i_top=itop, opts=range_opts[i], workspace=ws,
+                           checkpoints=ckpt, checkpoint_stride=1)
+            e[1].record()
+            # dL/dI_top of L = sum (I_top - target)^2 for this range's rows, in place
+            seed = itop[r:r + n].sub_(target[r:r + n]).mul_(2.0)
+            porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, itop, atm.w2, prec=prec,
+                             checkpoint_stride=1, g_kappa=g_k, g_propmat=g_p, g_emis=g_e,
+                             opts=range_opts[i], workspace=ws_adj, checkpoints=ckpt)
+            e[2].record()
+            marks.append(("sweep", e[0], e[1]))
+            marks.append(("adjoint", e[1], e[2]))
+            del seed
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
+                       accumulate=True, want_itop=False, opts=down_opts, workspace=ws)
+        e[1].record()
+        porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
+                         bhat, kappa=kappa, emis_out=state["emis_next"], prec=prec,
+                         s_new=state["s_new"], rc=rc, workspace=ws_see)
+        e[2].record()
+        marks.append(("sweep", e[0], e[1]))
+        marks.append(("see", e[1], e[2]))
+        state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
+        state["emis"], state["emis_next"] = state["emis_next"], state["emis"]
+        times.append(marks)
+
     def step(times):
+        if schedule == "interleaved":
+            return step_interleaved(times)
         e = [ev() for _ in range(5)]
         emis_cur = state["emis"]
         e[0].record()
@@ -264,7 +364,13 @@ def main():
         e[4].record()
         state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
         state["emis"], state["emis_next"] = state["emis_next"], state["emis"]
-        times.append(e)
+        times.append([("sweep", e[0], e[1]), ("see", e[1], e[2]), ("adjoint", e[3], e[4])])
+
+    def split(marks):
+        out = {"sweep": 0.0, "see": 0.0, "adjoint": 0.0}
+        for kind, a, b in marks:
+            out[kind] += a.elapsed_time(b)
+        return out
 
     for w in range(args.warmup):
         step([])
@@ -276,25 +382,33 @@ def main():
     for k in range(args.steps):
         step(times)
         torch.cuda.synchronize()
-        e = times[-1]
-        log(f"step {k + 1}/{args.steps}: sweep {e[0].elapsed_time(e[1]):.1f} ms, "
-            f"SEE {e[1].elapsed_time(e[2]):.2f} ms, adjoint {e[3].elapsed_time(e[4]):.1f} ms, "
-            f"R_c {rc.item():.3e}")
+        m = split(times[-1])
+        log(f"step {k + 1}/{args.steps}: sweep {m['sweep']:.1f} ms, SEE {m['see']:.2f} ms, "
+            f"adjoint {m['adjoint']:.1f} ms, R_c {rc.item():.3e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sweep_ms = sum(e[0].elapsed_time(e[1]) for e in times) / args.steps
-    see_ms = sum(e[1].elapsed_time(e[2]) for e in times) / args.steps
-    adj_ms = sum(e[3].elapsed_time(e[4]) for e in times) / args.steps
+    per = [split(e) for e in times]
+    sweep_ms = sum(m["sweep"] for m in per) / args.steps
+    see_ms = sum(m["see"] for m in per) / args.steps
+    adj_ms = sum(m["adjoint"] for m in per) / args.steps
     step_ms = wall * 1e3 / args.steps
     adj_updates = cfg.npoints * (cfg.nrays // 2) * cfg.nfreq if adj else 0
     value = (cfg.updates + adj_updates) * args.steps / wall
 
-    launches = 2 * (cfg.nz - 1) * nbatches
-    lbytes, lupd = sweep_launch_bytes(cfg, nrb, elem)
+    # every plane launch of the sweep kernel in one step: its rays and algorithmic bytes
+    if schedule == "interleaved":
+        shapes = [n for _, n in ranges] + [min(nrb, nh - r) for r in range(0, nh, nrb)]
+    else:
+        shapes = [min(nrb, nh - r) for r in range(0, nh, nrb)] * 2
+    launches = (cfg.nz - 1) * len(shapes)
+    lbytes = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, elem)[0] for n in shapes) / launches
+    lupd = cfg.updates / launches
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
     kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
-    counters = measured_counters(kname, cfg.name == "C3" and nrb == 40 and args.block in (0, 256))
+    workload = counter_workload(cfg, args.prec, schedule, nrb,
+                                range_rays if schedule == "interleaved" else 0)
+    counters = measured_counters(kname, workload) if args.block in (0, 256) else None
     traffic = None if counters is None else counters["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -357,8 +471,10 @@ def main():
                                + (" + adjoint of the emergent-Stokes loss" if adj else ""),
                    "updates_per_step": cfg.updates + adj_updates,
                    "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
-                   "ray_batch": nrb, "checkpoint_stride": args.checkpoint_stride,
-                   "adjoint_ray_batch": adj_opts.ray_batch,
+                   "ray_batch": nrb, "schedule": schedule,
+                   "checkpoint_stride": 1 if schedule == "interleaved" else args.checkpoint_stride,
+                   "adjoint_ray_batch": (range_rays if schedule == "interleaved"
+                                         else adj_opts.ray_batch),
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -124,7 +124,7 @@ typedef struct {
 
 /* Optional tuning; pass NULL for defaults. */
 typedef struct {
-  int32_t ray_batch;        /* rays swept together (0: a whole hemisphere) */
+  int32_t ray_batch;        /* rays swept together (0: all of the call's rays in a hemisphere) */
   int32_t block;            /* threads per block of the sweep kernel (0: 256) */
   int32_t xcd_remap;        /* R > 0: each XCD takes R consecutive tiles per round;
                                0: hardware order; -1: default (8) */
@@ -139,6 +139,12 @@ typedef struct {
                                ([nmu*nchi][nfreq][ny][nx]), J^K_Q comes from Stokes I
                                alone, and checkpoints, PORTA_INTERP_BEZIER2D and
                                porta_fs_adjoint return PORTA_EUNSUPPORTED */
+  int32_t ray_first;        /* rays of the call: [ray_first, ray_first + ray_count) of the */
+  int32_t ray_count;        /* ray enumeration (0 = every ray).  porta_fs_sweep sweeps only
+                               them (J with accumulate = 1 then sums the calls),
+                               porta_fs_adjoint takes only their upward part; i_top and
+                               dl_ditop keep the layout of all upward rays; checkpoints
+                               hold only the upward rays of the range */
 } porta_options;
 
 typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;
@@ -150,10 +156,11 @@ size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int 
                             int kind, int checkpoint_stride, const porta_options* opts);
 
 /* Bytes of the checkpoint buffer that porta_fs_sweep fills for porta_fs_adjoint:
- * the states of the upward rays on planes C, 2C, ... below the top plane,
- * layout [(nz-2)/C][nmu*nchi][nfreq][ny][nx][4] in the sweep precision. */
+ * the states of the upward rays of the options' ray range (all by default) on planes
+ * C, 2C, ... below the top plane, layout [(nz-2)/C][those rays][nfreq][ny][nx][4] in
+ * the sweep precision.  opts may be NULL. */
 size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int prec,
-                             int checkpoint_stride);
+                             int checkpoint_stride, const porta_options* opts);
 
 /*
  * Formal solution for every ray and frequency (Sect. 3; Eqs. fsint, fsbez,

@@ -124,13 +124,39 @@ int validate_options(const porta_options* o) {
     return fail(PORTA_EINVAL, "unknown control point rule %d", o->control);
   if (o->stokes != 0 && o->stokes != 1 && o->stokes != 4)
     return fail(PORTA_EINVAL, "stokes must be 0 or 4 (Stokes vector) or 1 (intensity only)");
+  if (o->ray_count < 0 || o->ray_first < 0)
+    return fail(PORTA_EINVAL, "ray_first and ray_count must be >= 0");
   return PORTA_OK;
 }
 
+int validate_rays(const porta_quad* q, const porta_options* o) {
+  if (o && o->ray_count > 0 && (int64_t)o->ray_first + o->ray_count > 2LL * q->nmu * q->nchi)
+    return fail(PORTA_EINVAL, "ray range %d + %d beyond the %d rays", o->ray_first, o->ray_count,
+                2 * q->nmu * q->nchi);
+  return PORTA_OK;
+}
+
+// Rays of the call: [first, first + count) of the enumeration (upward rays first), all
+// rays when count is 0; the part of it in one hemisphere as [lo, hi) of 0..nh-1.
+void hemi_range(const porta_quad* q, const porta_options* o, int hemi, int& lo, int& hi) {
+  const int nh = q->nmu * q->nchi;
+  const int first = (o && o->ray_count > 0) ? o->ray_first : 0;
+  const int last = (o && o->ray_count > 0) ? o->ray_first + o->ray_count : 2 * nh;
+  lo = std::max(first, hemi * nh) - hemi * nh;
+  hi = std::min(last, (hemi + 1) * nh) - hemi * nh;
+  if (hi < lo) hi = lo;
+}
+
+// Rays swept together: the options' batch, at most the call's rays in one hemisphere.
 int ray_batch(const porta_quad* q, const porta_options* o) {
   const int nh = q->nmu * q->nchi;
-  int rb = (o && o->ray_batch > 0) ? o->ray_batch : nh;
-  return std::min(rb, nh);
+  int rb = (o && o->ray_batch > 0) ? o->ray_batch : nh, cap = 1;
+  for (int hemi = 0; hemi < 2; ++hemi) {
+    int lo, hi;
+    hemi_range(q, o, hemi, lo, hi);
+    cap = std::max(cap, hi - lo);
+  }
+  return std::min(rb, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,8 +245,13 @@ Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int st
   return L;
 }
 
-size_t checkpoint_bytes(const porta_grid* g, const porta_quad* q, int prec, int stride) {
-  return (size_t)checkpoint_count(g->nz, stride) * q->nmu * q->nchi * q->nfreq *
+// Checkpoints hold the upward rays of the call's ray range:
+// [(nz-2)/C][upward rays of the range][nfreq][ny][nx][4].
+size_t checkpoint_bytes(const porta_grid* g, const porta_quad* q, int prec, int stride,
+                        const porta_options* o) {
+  int lo, hi;
+  hemi_range(q, o, 0, lo, hi);
+  return (size_t)checkpoint_count(g->nz, stride) * (hi - lo) * q->nfreq *
          ((size_t)g->nx * g->ny) * 4 * elem(prec);
 }
 
@@ -292,8 +323,11 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
     const bool up = (hemi == 0);
     const int kb = up ? 0 : nz - 1, s = up ? 1 : -1;
     const T ibound = up ? (T)f->i_bottom : T(0);
-    for (int r0 = 0; r0 < nh; r0 += nrb_max) {
-      const int nrb = std::min(nrb_max, nh - r0);
+    int lo, hi, up_lo, up_hi;
+    hemi_range(q, o, hemi, lo, hi);
+    hemi_range(q, o, 0, up_lo, up_hi);
+    for (int r0 = lo; r0 < hi; r0 += nrb_max) {
+      const int nrb = std::min(nrb_max, hi - r0);
       const int ray0 = hemi * nh + r0;
       const T* prev = nullptr;
       for (int step = 1; step < nz; ++step) {
@@ -311,7 +345,8 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
         if (last && up && itop)
           a.inext = itop + batch_off;
         else if (up && ckpt && is_checkpoint(k, nz, C))   // kept for the adjoint
-          a.inext = ckpt + (size_t)(k / C - 1) * nh * q->nfreq * np * 4 + batch_off;
+          a.inext = ckpt + ((size_t)(k / C - 1) * (up_hi - up_lo) + (r0 - up_lo)) *
+                               q->nfreq * np * 4;
         else
           a.inext = state[step & 1];
         // plane k writes partial sums into jpart[step & 1] while the first ray row of
@@ -422,20 +457,21 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
   T* lam[2] = {reinterpret_cast<T*>(ws + L.lamA), reinterpret_cast<T*>(ws + L.lamB)};
   // forward state of plane k of the current batch: the boundary (nullptr), a
   // checkpoint (own or the caller's, rays contiguous in both), or a recompute slot
-  int r0 = 0;
+  int r0 = 0, up_lo, up_hi;
+  hemi_range(q, o, 0, up_lo, up_hi);
   auto plane = [&](int k) -> T* {
     if (k == 0) return nullptr;
     if (is_checkpoint(k, nz, C)) {
       if (ext_ck)
-        return const_cast<T*>(ext_ck) + (size_t)(k / C - 1) * nh * q->nfreq * np * 4 +
-               (size_t)r0 * q->nfreq * np * 4;
+        return const_cast<T*>(ext_ck) +
+               ((size_t)(k / C - 1) * (up_hi - up_lo) + (r0 - up_lo)) * q->nfreq * np * 4;
       return ck + (size_t)(k / C - 1) * pe;
     }
     return slots + (size_t)((k - 1) % C) * pe;
   };
   const size_t lds_adj = (size_t)q->nfreq * sizeof(T);
-  for (r0 = 0; r0 < nh; r0 += nrb_max) {
-    const int nrb = std::min(nrb_max, nh - r0);
+  for (r0 = up_lo; r0 < up_hi; r0 += nrb_max) {
+    const int nrb = std::min(nrb_max, up_hi - r0);
     // forward pass up to the last checkpoint plane, keeping every C-th plane (unless
     // the sweep already kept them); the planes above it are recomputed with the top
     // segment
@@ -571,13 +607,15 @@ size_t porta_workspace_size(const porta_grid* grid, const porta_quad* quad, int 
 }
 
 size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int prec,
-                             int checkpoint_stride) {
-  if (validate_prec(prec) || validate_grid(grid) || validate_quad(quad)) return 0;
+                             int checkpoint_stride, const porta_options* opts) {
+  if (validate_prec(prec) || validate_grid(grid) || validate_quad(quad) ||
+      validate_options(opts) || validate_rays(quad, opts))
+    return 0;
   if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1) {
     fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
     return 0;
   }
-  return checkpoint_bytes(grid, quad, prec, checkpoint_stride);
+  return checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
 }
 
 int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
@@ -592,7 +630,7 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
   if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
     return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
-  if ((rc = validate_options(opts))) return rc;
+  if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
   if (nstokes(opts) == 1 && interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
   if (nstokes(opts) == 1 && checkpoints)
@@ -669,7 +707,7 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
     return fail(PORTA_EINVAL, "seed and gradient arrays must not be NULL");
   if (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1)
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
-  if ((rc = validate_options(opts))) return rc;
+  if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
   if (nstokes(opts) == 1)
     return fail(PORTA_EUNSUPPORTED, "the adjoint is for the Stokes-vector sweep");
   if (interp != PORTA_INTERP_BILINEAR)

@@ -45,7 +45,8 @@ class Atom(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32),
-                ("control", C.c_int32), ("stokes", C.c_int32)]
+                ("control", C.c_int32), ("stokes", C.c_int32), ("ray_first", C.c_int32),
+                ("ray_count", C.c_int32)]
 
 
 class PortaError(RuntimeError):
@@ -75,7 +76,7 @@ def lib():
                                          C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
                                          vp, C.c_int, vp, sz, vp]
             L.porta_checkpoint_size.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int,
-                                                C.c_int]
+                                                C.c_int, C.POINTER(Options)]
             L.porta_checkpoint_size.restype = sz
             L.porta_jkq_accumulate.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int, C.c_int,
                                                C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, sz, vp]
@@ -155,10 +156,13 @@ class HostGrid:
                    quad.phi, quad.wfreq)
 
 
-def options(ray_batch=0, block=0, xcd_remap=-1, control=0, stokes=4):
+def options(ray_batch=0, block=0, xcd_remap=-1, control=0, stokes=4, ray_first=0,
+            ray_count=0):
     """porta_options; control = CONTROL_BESSER or CONTROL_PARABOLIC; stokes = 4 (Stokes
-    vector) or 1 (intensity only, the unpolarized problem)."""
-    return Options(int(ray_batch), int(block), int(xcd_remap), int(control), int(stokes))
+    vector) or 1 (intensity only, the unpolarized problem); rays [ray_first,
+    ray_first + ray_count) of the enumeration (ray_count 0: every ray)."""
+    return Options(int(ray_batch), int(block), int(xcd_remap), int(control), int(stokes),
+                   int(ray_first), int(ray_count))
 
 
 def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:
@@ -169,11 +173,13 @@ def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> 
     return int(n)
 
 
-def checkpoint_size(hg: HostGrid, prec, checkpoint_stride) -> int:
-    """Bytes of the checkpoint buffer (0 also when no plane is a checkpoint; an invalid
-    stride is reported by fs_sweep / fs_adjoint)."""
+def checkpoint_size(hg: HostGrid, prec, checkpoint_stride, opts=None) -> int:
+    """Bytes of the checkpoint buffer for the upward rays of the options' ray range (0 also
+    when no plane is a checkpoint; an invalid stride is reported by fs_sweep /
+    fs_adjoint)."""
     return int(lib().porta_checkpoint_size(C.byref(hg.grid), C.byref(hg.quad), int(prec),
-                                           int(checkpoint_stride)))
+                                           int(checkpoint_stride),
+                                           C.byref(opts) if opts else None))
 
 
 def _workspace(nbytes, device):

@@ -206,3 +206,35 @@ def test_intensity_only_option_checks():
     w1 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1,
                               porta.options(ray_batch=4, stokes=1))
     assert w1 < w4
+
+
+def test_ray_range_checks_and_sizes():
+    """A ray range [ray_first, ray_first + ray_count) beyond the 2 nmu nchi rays is
+    rejected before any launch; checkpoints and workspaces are sized for the range."""
+    L = porta.lib()
+    hg = small_hg()
+    nh = hg.nray_up
+    d = np.zeros(8).ctypes.data
+    f = porta.Fields(d, d, d, 1.0, 1.0)
+    for first, count in ((0, 2 * nh + 1), (2 * nh - 5, 6), (-1, 2), (0, -1)):
+        o = porta.options(ray_first=first, ray_count=count)
+        assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
+                                C.byref(o), d, 0, d, None, 0, d, 1 << 40, None) == -1
+        assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
+                                  C.byref(o), d, None, 2, d, d, d, d, 1 << 40, None) == -1
+        assert porta.checkpoint_size(hg, porta.F32, 4, o) == 0
+    full = porta.checkpoint_size(hg, porta.F32, 4)
+    # only the upward rays of the range are kept: 10 of [30, 50), none of the downward
+    assert porta.checkpoint_size(hg, porta.F32, 4,
+                                 porta.options(ray_first=nh - 10, ray_count=20)) == full // 4
+    assert porta.checkpoint_size(hg, porta.F32, 4,
+                                 porta.options(ray_first=nh, ray_count=nh)) == 0
+    assert porta.checkpoint_size(hg, porta.F32, 1, porta.options(ray_count=8)) == \
+        (32 - 2) * 8 * 21 * 256 * 16
+    # the batch of a call is at most its rays in one hemisphere
+    for kind, stride in ((porta.WS_SWEEP, 1), (porta.WS_ADJOINT_CKPT, 1), (porta.WS_ADJOINT, 3)):
+        sub = porta.workspace_size(hg, porta.F32, kind, stride,
+                                   porta.options(ray_first=8, ray_count=8))
+        assert sub == porta.workspace_size(hg, porta.F32, kind, stride,
+                                           porta.options(ray_batch=8))
+        assert sub < porta.workspace_size(hg, porta.F32, kind, stride)

@@ -300,3 +300,45 @@ def test_adjoint_with_parabolic_control_point(orc):
     # and it is a different derivative from the BESSER one
     gb = gpu_grad(case, w, stride=1)
     assert max(np.abs(a - b).max() for a, b in zip(g, gb)) > 0
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_adjoint_over_ray_ranges(prec):
+    """Adjoint calls over ray ranges (gradients added into the same arrays) give the
+    one-call gradient, with their own checkpoints and with stride-1 checkpoints kept by a
+    sweep of the same range just before: the schedule that interleaves forward and reverse
+    sweeps range by range without recomputing a plane."""
+    torch = require_gpu()
+    atm, q = tiny_case(prec, seed=32, nx=5, ny=4, nz=7)
+    case = Case(atm, q, prec)
+    nh = case.hg.nray_up
+    w = to_dev(seed_for(case, np.random.default_rng(9)), case.dt)
+    ref = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
+                           prec=prec, checkpoint_stride=2)
+    _, ref_t = case.sweep()
+    torch.cuda.synchronize()
+    scale = max(float(x.abs().max()) for x in ref)
+    # FP32: each call rounds its share of the gradient to the sweep precision
+    tol = 1e-13 if prec == porta.F64 else 2e-6
+    ranges = ((0, 3), (3, 2), (5, nh - 5 + 4), (nh + 4, nh - 4))
+    g_own = [torch.zeros_like(x) for x in ref]
+    g_fused = [torch.zeros_like(x) for x in ref]
+    itop = torch.full(ref_t.shape, float("nan"), dtype=case.dt, device="cuda")
+    for first, count in ranges:
+        o = porta.options(ray_batch=2, ray_first=first, ray_count=count)
+        porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
+                         prec=prec, checkpoint_stride=3, g_kappa=g_own[0], g_propmat=g_own[1],
+                         g_emis=g_own[2], opts=o)
+        ck = torch.empty(max(porta.checkpoint_size(case.hg, prec, 1, o), 256), dtype=torch.uint8,
+                         device="cuda")
+        porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2, prec=prec,
+                       want_jkq=False, i_top=itop, opts=o, checkpoints=ck, checkpoint_stride=1)
+        porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
+                         prec=prec, checkpoint_stride=1, g_kappa=g_fused[0],
+                         g_propmat=g_fused[1], g_emis=g_fused[2], opts=o, checkpoints=ck)
+        torch.cuda.synchronize()
+    assert np.array_equal(itop.cpu().numpy(), ref_t)
+    for g in (g_own, g_fused):
+        for a, b in zip(g, ref):
+            err = float((a.double() - b.double()).abs().max()) / scale
+            assert err <= tol, err

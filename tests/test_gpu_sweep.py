@@ -267,3 +267,35 @@ def test_intensity_only_sweep_matches_oracle(orc, prec):
         assert rel.max() <= tol, f"{cfg.name}: I max rel err {rel.max():.3e}"
         compare_jkq(jkq, ref["jkq"], tol, f"intensity-only {cfg.name}")
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_ray_ranges_sum_to_the_full_sweep(prec):
+    """Calls over ray ranges that split the enumeration (one straddles the hemispheres,
+    none aligned with the ray batches) give the one-call sweep: each writes its own rows
+    of I_top, bitwise, and J summed with accumulate = 1 matches up to summation order."""
+    torch = require_gpu()
+    cfg = inputs.Config("sub", 7, 5, 9, 2, 3, 5, True)
+    atm = dataclasses.replace(inputs.make_atmosphere(cfg, seed=6), lx=530.0, ly=410.0)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, prec)
+    ref_j, ref_t = case.sweep(opts=porta.options(ray_batch=2))
+    nh = case.hg.nray_up
+    jkq = torch.full((10, case.hg.N), float("nan"), dtype=torch.float64, device="cuda")
+    itop = torch.full(ref_t.shape, float("nan"), dtype=case.dt, device="cuda")
+    for i, (first, count) in enumerate(((nh + 3, nh - 3), (0, 3), (3, nh))):
+        porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                       prec=prec, jkq=jkq, accumulate=i > 0, i_top=itop,
+                       opts=porta.options(ray_batch=2, ray_first=first, ray_count=count))
+    torch.cuda.synchronize()
+    assert np.array_equal(itop.cpu().numpy(), ref_t)
+    np.testing.assert_allclose(jkq.cpu().numpy(), ref_j, rtol=1e-13,
+                               atol=1e-15 * np.abs(ref_j).max())
+    # a downward-only range leaves I_top alone
+    itop2 = itop.clone()
+    porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2, prec=prec,
+                   i_top=itop2, want_jkq=False, opts=porta.options(ray_first=nh, ray_count=nh))
+    torch.cuda.synchronize()
+    assert torch.equal(itop, itop2)
