@@ -49,13 +49,13 @@ struct AdjArgs {
 
 // Partials of b's K' I term: dL/d(e_Q, e_U, e_V, r_Q, r_U, r_V) of -psi lambda^T K' x.
 template <class T>
-__device__ inline void kprime_outer(T psi, const T l[4], const T x[4], double g[6]) {
-  g[0] -= (double)(psi * (l[0] * x[1] + l[1] * x[0]));
-  g[1] -= (double)(psi * (l[0] * x[2] + l[2] * x[0]));
-  g[2] -= (double)(psi * (l[0] * x[3] + l[3] * x[0]));
-  g[3] -= (double)(psi * (l[2] * x[3] - l[3] * x[2]));
-  g[4] -= (double)(psi * (l[3] * x[1] - l[1] * x[3]));
-  g[5] -= (double)(psi * (l[1] * x[2] - l[2] * x[1]));
+__device__ inline void kprime_outer(T psi, const T l[4], const T x[4], T g[6]) {
+  g[0] -= psi * (l[0] * x[1] + l[1] * x[0]);
+  g[1] -= psi * (l[0] * x[2] + l[2] * x[0]);
+  g[2] -= psi * (l[0] * x[3] + l[3] * x[0]);
+  g[3] -= psi * (l[2] * x[3] - l[3] * x[2]);
+  g[4] -= psi * (l[3] * x[1] - l[1] * x[3]);
+  g[5] -= psi * (l[1] * x[2] - l[2] * x[1]);
 }
 
 // FP32: three waves per SIMD (168 VGPRs); the few spills this costs fall in the per-node
@@ -107,8 +107,10 @@ k_adjoint_plane(const AdjArgs<T> a) {
   const T* sp = a.seed + rb * rstride + (size_t)p * 4;
   T* lo = a.lam_cur ? a.lam_cur + rb * rstride + (size_t)p * 4 : nullptr;
 
-  double gT = 0.0, gSM[4] = {0, 0, 0, 0}, gSO[4] = {0, 0, 0, 0}, gCM[4] = {0, 0, 0, 0};
-  double gKM[6] = {0, 0, 0, 0, 0, 0}, gKO[6] = {0, 0, 0, 0, 0, 0};
+  // sums over frequency of the partials, in the sweep precision (FP32: each is a sum
+  // of nfreq terms whose rounding stays at the level of the FP32 terms themselves)
+  T aT = 0, aSM[4] = {0, 0, 0, 0}, aSO[4] = {0, 0, 0, 0}, aCM[4] = {0, 0, 0, 0};
+  T aKM[6] = {0, 0, 0, 0, 0, 0}, aKO[6] = {0, 0, 0, 0, 0, 0};
   for (int f = 0; f < a.nfreq; ++f) {
     const size_t fo = (size_t)f * fstride;
     T lam[4];
@@ -163,13 +165,13 @@ k_adjoint_plane(const AdjArgs<T> a) {
       gOM += lb[s] * SMt[s];
       gOO += lb[s] * SOt[s];
       gOC += lb[s] * cMt[s];
-      gSM[s] += (double)(cf.omM * lb[s]);
-      gSO[s] += (double)(cf.omO * lb[s]);
-      gCM[s] += (double)(cf.omC * lb[s]);
+      aSM[s] += cf.omM * lb[s];
+      aSO[s] += cf.omO * lb[s];
+      aCM[s] += cf.omC * lb[s];
     }
-    gT += (double)(ph * coef_tau_grad(cf, tau, gE, gPM, gPO, gOM, gOO, gOC));
-    kprime_outer(cf.psiM, lb, IM, gKM);
-    kprime_outer(cf.psiO, lb, IO, gKO);
+    aT += ph * coef_tau_grad(cf, tau, gE, gPM, gPO, gOM, gOO, gOC);
+    kprime_outer(cf.psiM, lb, IM, aKM);
+    kprime_outer(cf.psiO, lb, IO, aKO);
     if (lo) {
       // Lambda = (e - psi'_M K'_M)^T lambda_b
       T KT[4];
@@ -181,6 +183,18 @@ k_adjoint_plane(const AdjArgs<T> a) {
     }
   }
 
+  double gT = aT, gSM[4], gSO[4], gCM[4], gKM[6], gKO[6];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    gSM[s] = aSM[s];
+    gSO[s] = aSO[s];
+    gCM[s] = aCM[s];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    gKM[c] = aKM[c];
+    gKO[c] = aKO[c];
+  }
   // control points (branch of the forward evaluation)
   double gSP[4] = {0, 0, 0, 0}, gR = 0.0;
 #pragma unroll
