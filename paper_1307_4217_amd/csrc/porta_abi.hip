@@ -545,7 +545,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         b.inv_dy = a.inv_dy;
         b.ray0 = r0;
         b.nrb = nrb;
-        hipLaunchKernelGGL(k_adjoint_gather, dim3((np + 255) / 256), dim3(256), 0, st, b);
+        hipLaunchKernelGGL(k_adjoint_gather, dim3((np + 255) / 256, 4), dim3(256), 0, st, b);
         if ((rc = check_launch("adjoint_gather"))) return rc;
         lam_next = a.lam_cur;
         cur ^= 1;

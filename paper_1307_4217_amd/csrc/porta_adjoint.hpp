@@ -274,7 +274,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
 }
 
 // Gather the per-(node, ray) partials of one plane onto the coefficient
-// gradients of planes kM, kO and kP (fixed ray order, one thread per node).
+// gradients of planes kM, kO and kP (fixed ray order per component, no atomics).
 struct GatherArgs {
   const double* g_o;
   const double* g_m;
@@ -288,51 +288,55 @@ struct GatherArgs {
   int ray0, nrb;
 };
 
+// blockIdx.y: component group (0: the 13 at O; 1, 2: the 13 at M in two halves; 3: the
+// 7 at P), so that four threads share a node and each stencil is built once per group.
 __global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs a) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.np) return;
+  const int grp = blockIdx.y;
+  if (q >= a.np || (grp == 3 && a.kP < 0)) return;
   const int i = q % a.nx, j = q / a.nx;
   const size_t np = (size_t)a.np;
-  double accO[13], accM[13], accP[7];
+  const int c0 = (grp == 2) ? 7 : 0;
+  const int nc = (grp == 0) ? 13 : (grp == 1 ? 7 : (grp == 2 ? 6 : 7));
+  double acc[13];
 #pragma unroll
-  for (int c = 0; c < 13; ++c) accO[c] = accM[c] = 0.0;
+  for (int c = 0; c < 13; ++c) acc[c] = 0.0;
+  if (grp == 0) {
+    for (int rb = 0; rb < a.nrb; ++rb) {
+      const double* go = a.g_o + (size_t)rb * 13 * np + q;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) accP[c] = 0.0;
+      for (int c = 0; c < 13; ++c) acc[c] += go[c * np];
+    }
+#pragma unroll
+    for (int c = 0; c < 13; ++c) a.grad[c * a.N + (size_t)a.kO * np + q] += acc[c];
+    return;
+  }
+  const bool atM = (grp < 3);
   for (int rb = 0; rb < a.nrb; ++rb) {
     const RayConsts& rc = a.rays[a.ray0 + rb];
     const double inv_mu = 1.0 / fabs(rc.mu);
-    const double dsM = a.dzM * inv_mu;
-    const Stencil tM = make_tstencil(i, j, a.nx, a.ny, -dsM * rc.sx * a.inv_dx,
-                                     -dsM * rc.sy * a.inv_dy);
-    const double* go = a.g_o + (size_t)rb * 13 * np;
-    const double* gm = a.g_m + (size_t)rb * 13 * np;
+    const double ds = (atM ? a.dzM : a.dzP) * inv_mu;
+    const double sds = atM ? -ds : ds;   // M upwind, P downwind, as in the sweep
+    const Stencil t = make_tstencil(i, j, a.nx, a.ny, sds * rc.sx * a.inv_dx,
+                                    sds * rc.sy * a.inv_dy);
+    const double* gb = atM ? a.g_m + ((size_t)rb * 13 + c0) * np : a.g_p + (size_t)rb * 7 * np;
 #pragma unroll
-    for (int c = 0; c < 13; ++c) {
-      const double* g = gm + c * np;
-      accO[c] += go[c * np + q];
-      accM[c] += tM.w00 * g[tM.i00] + tM.w10 * g[tM.i10] + tM.w01 * g[tM.i01] + tM.w11 * g[tM.i11];
-    }
-    if (a.kP >= 0) {
-      const double dsP = a.dzP * inv_mu;
-      const Stencil tP = make_tstencil(i, j, a.nx, a.ny, dsP * rc.sx * a.inv_dx,
-                                       dsP * rc.sy * a.inv_dy);
-      const double* gp = a.g_p + (size_t)rb * 7 * np;
-#pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        const double* g = gp + c * np;
-        accP[c] += tP.w00 * g[tP.i00] + tP.w10 * g[tP.i10] + tP.w01 * g[tP.i01] + tP.w11 * g[tP.i11];
+    for (int c = 0; c < 7; ++c) {
+      if (c < nc) {
+        const double* g = gb + c * np;
+        acc[c] += t.w00 * g[t.i00] + t.w10 * g[t.i10] + t.w01 * g[t.i01] + t.w11 * g[t.i11];
       }
     }
   }
+  if (atM) {
 #pragma unroll
-  for (int c = 0; c < 13; ++c) {
-    a.grad[c * a.N + (size_t)a.kO * np + q] += accO[c];
-    a.grad[c * a.N + (size_t)a.kM * np + q] += accM[c];
-  }
-  if (a.kP >= 0) {
-    a.grad[(size_t)a.kP * np + q] += accP[0];
+    for (int c = 0; c < 7; ++c)
+      if (c < nc) a.grad[(c0 + c) * a.N + (size_t)a.kM * np + q] += acc[c];
+  } else {
+    // eta_I and the six emissivities at P (gradient rows 0 and 7..12)
+    a.grad[(size_t)a.kP * np + q] += acc[0];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a.grad[(7 + c) * a.N + (size_t)a.kP * np + q] += accP[1 + c];
+    for (int c = 1; c < 7; ++c) a.grad[(6 + c) * a.N + (size_t)a.kP * np + q] += acc[c];
   }
 }
 
