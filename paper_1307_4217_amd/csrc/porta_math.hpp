@@ -39,9 +39,9 @@ __host__ __device__ inline double recip(double x) { return 1.0 / x; }
 //   (quadratic Bezier source function with control point c_M).
 // Below a threshold the closed forms cancel; a Taylor series about tau = 0 is
 // used instead (Table 1 gives the FP64 thresholds 0.14 / 0.18 for the omegas).
-// FP32 uses ten terms below tau = 1.2, which keeps every coefficient within
-// 1e-6 relative of its exact value; FP64 uses eight terms below the paper's
-// thresholds (0.1 for the psi').
+// FP32 switches at tau = 1.2 (one series for all six, below); FP64 uses eight
+// terms of each coefficient's own series below the paper's thresholds (0.1 for
+// the psi').
 // ---------------------------------------------------------------------------
 template <class T>
 struct Coefs {
@@ -57,37 +57,33 @@ __host__ __device__ inline T series(T tau, const T (&c)[NT]) {
   return acc * tau;
 }
 
-// Series coefficients (-1)^n a_n for n = 0..9 of
-//   psi'_M: 1/(n! (n+2))      psi'_O: 1/(n+2)!
-//   omega_M: 1/(n! (n+3))     omega_O: 2/(n+3)!     omega_C: 2/(n! (n+2)(n+3))
-#define PORTA_SERIES_TABLES(T)                                                        \
-  const T kPM[10] = {T(1.0 / 2), T(-1.0 / 3), T(1.0 / 8), T(-1.0 / 30), T(1.0 / 144),  \
-                     T(-1.0 / 840), T(1.0 / 5760), T(-1.0 / 45360), T(1.0 / 403200),  \
-                     T(-1.0 / 3991680)};                                               \
-  const T kPO[10] = {T(1.0 / 2), T(-1.0 / 6), T(1.0 / 24), T(-1.0 / 120), T(1.0 / 720), \
-                     T(-1.0 / 5040), T(1.0 / 40320), T(-1.0 / 362880),                  \
-                     T(1.0 / 3628800), T(-1.0 / 39916800)};                            \
-  const T kOM[10] = {T(1.0 / 3), T(-1.0 / 4), T(1.0 / 10), T(-1.0 / 36), T(1.0 / 168),  \
-                     T(-1.0 / 960), T(1.0 / 6480), T(-1.0 / 50400), T(1.0 / 443520),  \
-                     T(-1.0 / 4354560)};                                               \
-  const T kOO[10] = {T(1.0 / 3), T(-1.0 / 12), T(1.0 / 60), T(-1.0 / 360),             \
-                     T(1.0 / 2520), T(-1.0 / 20160), T(1.0 / 181440),                  \
-                     T(-1.0 / 1814400), T(1.0 / 19958400), T(-1.0 / 239500800)};       \
-  const T kOC[10] = {T(1.0 / 3), T(-1.0 / 6), T(1.0 / 20), T(-1.0 / 90), T(1.0 / 504),  \
-                     T(-1.0 / 3360), T(1.0 / 25920), T(-1.0 / 226800),                 \
-                     T(1.0 / 2217600), T(-1.0 / 23950080)};
-
+// FP32 below tau = 1.2: all six from one series.  With the exponential remainders
+//   E_n(t) = sum_k (-t)^k / (k + n)!,   E_n = 1/n! - t E_{n+1},   e = 1 - t E_1,
+// the series of the coefficients regroup as
+//   psi'_O = t E_2,   psi'_M = t (E_1 - E_2),   omega_O = 2 t E_3,
+//   omega_M = t (E_1 - 2 E_2 + 2 E_3),   omega_C = t (2 E_2 - 4 E_3),
+// (from 1/(n!(n+2)) = 1/(n+1)! - 1/(n+2)!, 1/(n!(n+3)) = 1/(n+1)! - 2/(n+2)! + 2/(n+3)!
+// and 2/(n!(n+2)(n+3)) = 2/(n+2)! - 4/(n+3)!), so ten terms of E_3 and the downward
+// recurrence (stable for t < 1.2) give every coefficient within 1e-6 relative.
 __host__ __device__ inline Coefs<float> coefficients(float tau) {
-  PORTA_SERIES_TABLES(float)
   Coefs<float> c;
-  c.e = exp_neg(tau);
   if (tau < 1.2f) {
-    c.psiM = series(tau, kPM);
-    c.psiO = series(tau, kPO);
-    c.omM = series(tau, kOM);
-    c.omO = series(tau, kOO);
-    c.omC = series(tau, kOC);
+    const float kE3[10] = {1.0f / 6, -1.0f / 24, 1.0f / 120, -1.0f / 720, 1.0f / 5040,
+                           -1.0f / 40320, 1.0f / 362880, -1.0f / 3628800, 1.0f / 39916800,
+                           -1.0f / 479001600};
+    float E3 = kE3[9];
+#pragma unroll
+    for (int n = 8; n >= 0; --n) E3 = E3 * tau + kE3[n];
+    const float E2 = 0.5f - tau * E3;
+    const float E1 = 1.0f - tau * E2;
+    c.e = 1.0f - tau * E1;
+    c.psiO = tau * E2;
+    c.psiM = tau * (E1 - E2);
+    c.omO = (2.0f * tau) * E3;
+    c.omM = tau * (E1 + 2.0f * (E3 - E2));
+    c.omC = tau * (2.0f * E2 - 4.0f * E3);
   } else {
+    c.e = exp_neg(tau);
     const float it = recip(tau), it2 = it * it;
     const float g = c.e + tau - 1.0f;               // e + tau - 1
     c.psiO = g * it;
