@@ -44,6 +44,28 @@ void hm_solve_stokes_f32(const float* e3, const float* r3, const float* b4, floa
   porta::solve_stokes(e3, r3, b4, x4);
 }
 
+// (1 + p K')^-1 b (sgn = 1) or its transpose (sgn = -1), through the per-node
+// operator and per-frequency scalars the kernels use.
+void hm_stokes_solve_scaled_f64(const double* e3, const double* r3, double p, const double* b4,
+                                int sgn, double* x4) {
+  const porta::StokesOp<double> k = porta::stokes_op(e3, r3);
+  const porta::StokesFreq<double> F = porta::stokes_freq(k, p);
+  if (sgn > 0)
+    porta::stokes_solve<1>(k, F, b4, x4);
+  else
+    porta::stokes_solve<-1>(k, F, b4, x4);
+}
+
+void hm_stokes_solve_scaled_f32(const float* e3, const float* r3, float p, const float* b4,
+                                int sgn, float* x4) {
+  const porta::StokesOp<float> k = porta::stokes_op(e3, r3);
+  const porta::StokesFreq<float> F = porta::stokes_freq(k, p);
+  if (sgn > 0)
+    porta::stokes_solve<1>(k, F, b4, x4);
+  else
+    porta::stokes_solve<-1>(k, F, b4, x4);
+}
+
 void hm_kprime_apply(const double* e3, const double* r3, const double* x4, double* y4) {
   porta::kprime_apply(e3, r3, x4, y4);
 }

@@ -88,6 +88,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
   const T rMv[3] = {(T)(ps.etaM[3] * ps.ikM), (T)(ps.etaM[4] * ps.ikM), (T)(ps.etaM[5] * ps.ikM)};
   const T eOv[3] = {(T)(ps.etaO[0] * ps.ikO), (T)(ps.etaO[1] * ps.ikO), (T)(ps.etaO[2] * ps.ikO)};
   const T rOv[3] = {(T)(ps.etaO[3] * ps.ikO), (T)(ps.etaO[4] * ps.ikO), (T)(ps.etaO[5] * ps.ikO)};
+  const StokesOp<T> KO = stokes_op(eOv, rOv);
   const T rMn[3] = {-rMv[0], -rMv[1], -rMv[2]};
   T SMt[4], SOt[4], cMt[4];
 #pragma unroll
@@ -147,13 +148,11 @@ k_adjoint_plane(const AdjArgs<T> a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
       b[s] = cf.e * IM[s] - cf.psiM * KIM[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
-    const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
-    const T ro[3] = {cf.psiO * rOv[0], cf.psiO * rOv[1], cf.psiO * rOv[2]};
-    solve_stokes(eo, ro, b, IO);
+    const StokesFreq<T> F = stokes_freq(KO, cf.psiO);
+    stokes_solve<1>(KO, F, b, IO);
     // lambda_b = (1 + psi'_O K'_O)^-T lambda
-    const T ron[3] = {-ro[0], -ro[1], -ro[2]};
     T lb[4];
-    solve_stokes(eo, ron, lam, lb);
+    stokes_solve<-1>(KO, F, lam, lb);
     T KIO[4];
     kprime_apply(eOv, rOv, IO, KIO);
     T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;

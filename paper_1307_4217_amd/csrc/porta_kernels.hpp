@@ -465,6 +465,7 @@ k_sweep_plane(const PlaneArgs<T> a) {
   const T rMv[3] = {(T)(etaM[3] * ikM), (T)(etaM[4] * ikM), (T)(etaM[5] * ikM)};
   const T eOv[3] = {(T)(etaO[0] * ikO), (T)(etaO[1] * ikO), (T)(etaO[2] * ikO)};
   const T rOv[3] = {(T)(etaO[3] * ikO), (T)(etaO[4] * ikO), (T)(etaO[5] * ikO)};
+  const StokesOp<T> KO = stokes_op(eOv, rOv);
   T SMt[4], SOt[4], cMt[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -495,10 +496,8 @@ k_sweep_plane(const PlaneArgs<T> a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
       b[s] = cf.e * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
-    const T eo[3] = {cf.psiO * eOv[0], cf.psiO * eOv[1], cf.psiO * eOv[2]};
-    const T ro[3] = {cf.psiO * rOv[0], cf.psiO * rOv[1], cf.psiO * rOv[2]};
     T x[4];
-    solve_stokes(eo, ro, b, x);
+    stokes_solve<1>(KO, stokes_freq(KO, cf.psiO), b, x);
     store4(op + (size_t)f * fstride, x);
     const double W = s_wn[f];
     jacc0 += W * (double)x[0];

@@ -322,6 +322,79 @@ __host__ __device__ inline void solve_stokes(const T e[3], const T r[3], const T
   x[0] = b[0] - (e[0] * x[1] + e[1] * x[2] + e[2] * x[3]);
 }
 
+// The same solve for the family 1 + p K' with K' fixed per node and ray and the
+// scalar p = psi'_O varying with frequency.  With X = e x r,
+//   B^-1 c = (c - p c x r + p^2 (c.r) r) / (1 + p^2 r.r),
+//   v = B^-1 (p e) = p (e - p X + p^2 (e.r) r) / (1 + p^2 r.r),
+//   (p e).v = p^2 (e.e + p^2 (e.r)^2) / (1 + p^2 r.r)      (since e.X = 0),
+// so the products of e and r are formed once (StokesOp) and each frequency needs
+// two reciprocals (StokesFreq) shared by the system and its transpose, which is the
+// same with r -> -r (SGN = -1).
+template <class T>
+struct StokesOp {
+  T e[3], r[3], X[3], C[3];   // e, r, e x r, (e.r) r
+  T rr, ee, er2;              // r.r, e.e, (e.r)^2
+};
+
+template <class T>
+__host__ __device__ inline StokesOp<T> stokes_op(const T e[3], const T r[3]) {
+  StokesOp<T> k;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    k.e[i] = e[i];
+    k.r[i] = r[i];
+  }
+  k.X[0] = e[1] * r[2] - e[2] * r[1];
+  k.X[1] = e[2] * r[0] - e[0] * r[2];
+  k.X[2] = e[0] * r[1] - e[1] * r[0];
+  const T er = e[0] * r[0] + e[1] * r[1] + e[2] * r[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k.C[i] = er * r[i];
+  k.rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  k.ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  k.er2 = er * er;
+  return k;
+}
+
+template <class T>
+struct StokesFreq {
+  T p, p2, inv_den, fden;     // p, p^2, 1/(1 + p^2 r.r), 1/(1 - (p e).v)
+};
+
+template <class T>
+__host__ __device__ inline StokesFreq<T> stokes_freq(const StokesOp<T>& k, T p) {
+  StokesFreq<T> F;
+  F.p = p;
+  F.p2 = p * p;
+  F.inv_den = recip(T(1) + F.p2 * k.rr);
+  F.fden = recip(T(1) - F.p2 * F.inv_den * (k.ee + F.p2 * k.er2));
+  return F;
+}
+
+// x = (1 + p K')^-1 b (SGN = 1) or (1 + p K')^-T b (SGN = -1).
+template <int SGN, class T>
+__host__ __device__ inline void stokes_solve(const StokesOp<T>& k, const StokesFreq<T>& F,
+                                             const T b[4], T x[4]) {
+  const T q = SGN > 0 ? F.p : -F.p;
+  const T pb0 = F.p * b[0];
+  const T c[3] = {b[1] - pb0 * k.e[0], b[2] - pb0 * k.e[1], b[3] - pb0 * k.e[2]};
+  const T cx[3] = {c[1] * k.r[2] - c[2] * k.r[1], c[2] * k.r[0] - c[0] * k.r[2],
+                   c[0] * k.r[1] - c[1] * k.r[0]};
+  const T p2cr = F.p2 * (c[0] * k.r[0] + c[1] * k.r[1] + c[2] * k.r[2]);
+  const T s = F.p * F.inv_den;
+  T u[3], v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = (c[i] - q * cx[i] + p2cr * k.r[i]) * F.inv_den;
+    v[i] = s * (k.e[i] - q * k.X[i] + F.p2 * k.C[i]);
+  }
+  const T f = F.p * (k.e[0] * u[0] + k.e[1] * u[1] + k.e[2] * u[2]) * F.fden;
+  x[1] = u[0] + f * v[0];
+  x[2] = u[1] + f * v[1];
+  x[3] = u[2] + f * v[2];
+  x[0] = b[0] - F.p * (k.e[0] * x[1] + k.e[1] * x[2] + k.e[2] * x[3]);
+}
+
 // K' x for the same layout (eta = e, rho = r).
 template <class T>
 __host__ __device__ inline void kprime_apply(const T e[3], const T r[3], const T x[4], T y[4]) {
