@@ -56,6 +56,8 @@ def parse():
                          "to 16, whose checkpoints fit)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=-1,
+                    help="row tiles per XCD per round (-1: the library default)")
     ap.add_argument("--no-fp64-rate", action="store_true",
                     help="skip the extra FP64 sweep used for the FP32-vs-FP64 rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -76,10 +78,21 @@ def sweep_launch_bytes(cfg, nrb, elem):
     return updates * 8 * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
 
 
+def adjoint_launch_bytes(cfg, nrb, elem):
+    """Algorithmic HBM bytes of one plane launch of the adjoint kernel: per update the
+    adjoint of the plane above (or the seed) and the forward state of the plane below
+    read and the new adjoint written; per node and ray the 33 FP64 partials written;
+    three planes of the 13 transfer coefficients."""
+    np_ = cfg.nx * cfg.ny
+    updates = nrb * cfg.nfreq * np_
+    return updates * 12 * elem + nrb * np_ * 33 * 8 + 3 * np_ * 13 * elem, updates
+
+
 KERNEL_SYMBOLS = {
     "k_sweep_plane<float, 0>": "_ZN5porta13k_sweep_planeIfLi0EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane<double, 0>": "_ZN5porta13k_sweep_planeIdLi0EEEvNS_9PlaneArgsIT_EE",
     "k_adjoint_plane<float>": "_ZN5porta15k_adjoint_planeIfEEvNS_7AdjArgsIT_EE",
+    "k_adjoint_gather": "_ZN5porta16k_adjoint_gatherENS_10GatherArgsE",
 }
 
 
@@ -210,9 +223,10 @@ def main():
                                                           device=dev)
     hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
-    opts = porta.options(ray_batch=args.ray_batch, block=args.block)
+    opts = porta.options(ray_batch=args.ray_batch, block=args.block, xcd_remap=args.xcd_remap)
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
-    adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block)
+    adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block,
+                             xcd_remap=args.xcd_remap)
     ws_bytes = porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts)
     nh = hg.nray_up
     schedule = "shared" if args.no_adjoint else args.schedule
@@ -225,7 +239,7 @@ def main():
         want = [args.range_rays] if args.range_rays > 0 else range(min(16, nh), 0, -1)
         range_rays = 0
         for n in want:
-            o = porta.options(ray_batch=n, block=args.block, ray_count=n)
+            o = porta.options(ray_batch=n, block=args.block, xcd_remap=args.xcd_remap, ray_count=n)
             need = (porta.checkpoint_size(hg, prec, 1, o)
                     + max(0, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1, o)
                           - ws_bytes))
@@ -240,10 +254,11 @@ def main():
             schedule = "shared"
     if schedule == "interleaved":
         ranges = [(r, min(range_rays, nh - r)) for r in range(0, nh, range_rays)]
-        range_opts = [porta.options(ray_batch=range_rays, block=args.block, ray_first=r,
-                                    ray_count=n) for r, n in ranges]
-        down_opts = porta.options(ray_batch=args.ray_batch, block=args.block, ray_first=nh,
-                                  ray_count=nh)
+        range_opts = [porta.options(ray_batch=range_rays, block=args.block,
+                                    xcd_remap=args.xcd_remap, ray_first=r, ray_count=n)
+                      for r, n in ranges]
+        down_opts = porta.options(ray_batch=args.ray_batch, block=args.block,
+                                  xcd_remap=args.xcd_remap, ray_first=nh, ray_count=nh)
         # the sweep of a range and its adjoint run one after the other and share one
         # workspace with the sweep of the downward rays
         ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1,
@@ -271,6 +286,9 @@ def main():
             porta.fs_sweep(hg, tk, tp, te, atm.i_bottom, atm.w2, prec=prec, want_jkq=False,
                            i_top=target, opts=o, workspace=ws)
         del tatm, tk, tp, te
+        # 2 x target, so that the seed 2 (I_top - target) = lerp(I_top, 2 target, -1) is
+        # one pass over I_top
+        target2 = target.mul_(2.0)
         if schedule == "interleaved":
             # every plane of one range of upward rays, reused range after range
             ckpt = torch.empty(porta.checkpoint_size(hg, prec, 1, range_opts[0]) + 256,
@@ -304,20 +322,22 @@ def main():
         marks = []
         g_k.zero_(), g_p.zero_(), g_e.zero_()
         for i, (r, n) in enumerate(ranges):
-            e = [ev() for _ in range(3)]
+            e = [ev() for _ in range(4)]
             e[0].record()
             porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
                            accumulate=i > 0, i_top=itop, opts=range_opts[i], workspace=ws,
                            checkpoints=ckpt, checkpoint_stride=1)
             e[1].record()
             # dL/dI_top of L = sum (I_top - target)^2 for this range's rows, in place
-            seed = itop[r:r + n].sub_(target[r:r + n]).mul_(2.0)
+            seed = itop[r:r + n].lerp_(target2[r:r + n], -1.0)
+            e[2].record()
             porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, itop, atm.w2, prec=prec,
                              checkpoint_stride=1, g_kappa=g_k, g_propmat=g_p, g_emis=g_e,
                              opts=range_opts[i], workspace=ws_adj, checkpoints=ckpt)
-            e[2].record()
+            e[3].record()
             marks.append(("sweep", e[0], e[1]))
-            marks.append(("adjoint", e[1], e[2]))
+            marks.append(("seed", e[1], e[2]))
+            marks.append(("adjoint", e[2], e[3]))
             del seed
         e = [ev() for _ in range(3)]
         e[0].record()
@@ -352,7 +372,7 @@ def main():
         if adj:
             # dL/dI_top of L = sum (I_top - target)^2, formed in place of I_top (not read
             # again this step), then the reverse sweep
-            seed = itop.sub_(target).mul_(2.0)
+            seed = itop.lerp_(target2, -1.0)
             e[3].record()
             g_k.zero_(), g_p.zero_(), g_e.zero_()
             porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, seed, atm.w2, prec=prec,
@@ -364,10 +384,11 @@ def main():
         e[4].record()
         state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
         state["emis"], state["emis_next"] = state["emis_next"], state["emis"]
-        times.append([("sweep", e[0], e[1]), ("see", e[1], e[2]), ("adjoint", e[3], e[4])])
+        times.append([("sweep", e[0], e[1]), ("see", e[1], e[2]), ("seed", e[2], e[3]),
+                      ("adjoint", e[3], e[4])])
 
     def split(marks):
-        out = {"sweep": 0.0, "see": 0.0, "adjoint": 0.0}
+        out = {"sweep": 0.0, "see": 0.0, "seed": 0.0, "adjoint": 0.0}
         for kind, a, b in marks:
             out[kind] += a.elapsed_time(b)
         return out
@@ -408,7 +429,8 @@ def main():
     kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
     workload = counter_workload(cfg, args.prec, schedule, nrb,
                                 range_rays if schedule == "interleaved" else 0)
-    counters = measured_counters(kname, workload) if args.block in (0, 256) else None
+    counters = (measured_counters(kname, workload) if args.block in (0, 256)
+                and args.xcd_remap == -1 else None)
     traffic = None if counters is None else counters["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -416,7 +438,29 @@ def main():
                 "valu_busy_pct": None if counters is None else counters.get("valu_busy_pct"),
                 "launch_ms": round(launch_ms, 4), "bytes_per_launch": lbytes,
                 "updates_per_launch": lupd}
+    if adj:
+        # the adjoint kernel beside it: its launches carry the ray ranges (or adjoint
+        # batches); the calls also hold the gathers of the partials, so this is a floor
+        ashapes = ([n for _, n in ranges] if schedule == "interleaved" else
+                   [min(adj_opts.ray_batch or nh, nh - r)
+                    for r in range(0, nh, adj_opts.ray_batch or nh)])
+        alaunches = (cfg.nz - 1) * len(ashapes)
+        abytes = (cfg.nz - 1) * sum(adjoint_launch_bytes(cfg, n, elem)[0]
+                                    for n in ashapes) / alaunches
+        alaunch_ms = adj_ms / alaunches
+        aname = f"k_adjoint_plane<{'float' if elem == 4 else 'double'}>"
+        acounters = (measured_counters(aname, workload) if args.block in (0, 256)
+                     and args.xcd_remap == -1 else None)
+        roofline_adjoint = {
+            "bound": "hbm", "kernel": aname,
+            "achieved": round(abytes / (alaunch_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(abytes / (alaunch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": None if acounters is None else acounters["traffic_bytes_per_launch"],
+            "valu_busy_pct": None if acounters is None else acounters.get("valu_busy_pct"),
+            "call_ms_per_launch": round(alaunch_ms, 4), "bytes_per_launch": abytes}
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
+             "seed_ms": round(sum(m["seed"] for m in per) / args.steps, 2),
+             "roofline_adjoint": roofline_adjoint if adj else None,
              "sweep_updates_per_s": cfg.updates / (sweep_ms * 1e-3),
              "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4),
              "adjoint_ms": round(adj_ms, 2),
