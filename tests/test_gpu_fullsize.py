@@ -104,3 +104,62 @@ def test_fifty_jacobi_iterations_c1(orc):
         assert err < 1e-10, (it, err)
         assert rc == pytest.approx(rc_ref, rel=1e-8, abs=1e-15)
     print(f"50 Jacobi iterations at C1: final R_c {rc:.3e}, worst rel diff of S {worst:.2e}")
+
+
+def test_c3_interleaved_schedule_sampled(orc):
+    """The benchmark's launch configuration at 256x256x128 in FP32: a range of 16 upward
+    rays swept keeping the state of every plane (checkpoint stride 1), then reversed
+    from those planes.  I_top on sampled (ray, frequency) pairs against the oracle; the
+    adjoint for a seed on two (ray, frequency) pairs of the range, along a random
+    direction of all 13 coefficient fields, against the oracle's complex-step
+    derivative."""
+    torch = require_gpu()
+    torch.cuda.empty_cache()
+    cfg = inputs.CONFIGS["C3"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, porta.F32)
+    hg = case.hg
+    o = porta.options(ray_batch=16, ray_first=0, ray_count=16)
+    ck = torch.empty(porta.checkpoint_size(hg, porta.F32, 1, o), dtype=torch.uint8,
+                     device="cuda")
+    itop = torch.zeros((hg.nray_up, hg.nfreq, hg.ny, hg.nx, 4), dtype=torch.float32,
+                       device="cuda")
+    porta.fs_sweep(hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                   prec=porta.F32, want_jkq=False, i_top=itop, opts=o, checkpoints=ck,
+                   checkpoint_stride=1)
+    rays, freqs = [0, 9], [50, 38]
+    ref = _sampled_oracle(orc, atm, q, rays, freqs)
+    got = itop[rays][:, freqs].cpu().numpy()
+    ei, ep = compare_stokes(got, ref, 2e-5, 1e-7, "C3 interleaved")
+    print(f"C3 FP32 range of 16 rays, stride-1 checkpoints: I_top max rel err I {ei:.3e}, "
+          f"Q/I.. {ep:.3e}")
+    # adjoint with a seed on (ray 0, freq 50) and (ray 9, freq 38)
+    rng = np.random.default_rng(21)
+    pairs = [(0, 50), (9, 38)]
+    w = {p: rng.normal(size=(hg.ny, hg.nx, 4)).astype(np.float32).astype(np.float64)
+         for p in pairs}
+    seed = torch.zeros_like(itop)
+    for (r, f), wv in w.items():
+        seed[r, f] = to_dev(wv, torch.float32)
+    gk, gp, ge = porta.fs_adjoint(hg, case.kappa, case.prop, case.emis, atm.i_bottom, seed,
+                                  atm.w2, prec=porta.F32, checkpoint_stride=1, checkpoints=ck,
+                                  opts=o)
+    torch.cuda.synchronize()
+    del ck, seed
+    torch.cuda.empty_cache()
+    n = atm.npoints
+    v = [rng.normal(size=n) * atm.kappa, rng.normal(size=(6, n)) * atm.kappa,
+         rng.normal(size=(6, n)) * atm.emis.std(axis=1, keepdims=True)]
+    got = sum(float(np.sum(g.cpu().numpy().astype(np.float64) * vv))
+              for g, vv in zip((gk, gp, ge), v))
+    h = 1e-30
+    _, im = orc.fs_sweep_cs(orc.OracleProblem(atm, q), v[0], v[1], v[2], h=h, rays=rays,
+                            freqs=freqs)
+    want = sum(float(np.sum(w[(r, f)] * im[rays.index(r), freqs.index(f)])) / h
+               for r, f in pairs)
+    print(f"C3 FP32 adjoint from stride-1 checkpoints vs oracle complex step: "
+          f"{got:.9e} vs {want:.9e}")
+    assert got == pytest.approx(want, rel=1e-4)
+    del case
+    torch.cuda.empty_cache()
