@@ -418,9 +418,10 @@ __device__ inline void upwind_bez9(const T* __restrict__ q, const Stencil9& s,
   }
 }
 
-// Occupancy targets: three waves per SIMD for the FP32 bilinear sweep (168 VGPRs;
-// measured 4.8% faster than leaving the allocation free), two for the others (the
-// 9-point mode would otherwise drop to one).
+// Occupancy targets: three waves per SIMD for the FP32 bilinear sweep (168 VGPRs,
+// with the next frequency's corners in flight and no spill in the loop; four or five
+// waves were slower), two for the others (the 9-point mode would otherwise drop to
+// one).
 template <class T, int MODE>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MODE == 0 && sizeof(T) == 4 ? 3 : 2)))
@@ -486,7 +487,7 @@ k_sweep_plane(const PlaneArgs<T> a) {
 
   // one update (Eq. fsbez solved with Eq. kappa) at frequency f from the upwind
   // Stokes vector IM
-  auto update = [&](int f, T i0, T i1, T i2, T i3) {
+  auto update = [&](int f, T i0, T i1, T i2, T i3) __attribute__((always_inline)) {
     const T IM[4] = {i0, i1, i2, i3};
     const T tau = tau0 * s_phi[f];
     const Coefs<T> cf = coefficients(tau);
@@ -519,10 +520,16 @@ k_sweep_plane(const PlaneArgs<T> a) {
       update(f, IM[0], IM[1], IM[2], IM[3]);
     }
   } else {
-    T v[4][4];
-    for (int f = 0; f < a.nfreq; ++f) {
-      load_upwind(ip + (size_t)f * fstride, sM, v);
-      update(f, PORTA_BILIN(v, 0), PORTA_BILIN(v, 1), PORTA_BILIN(v, 2), PORTA_BILIN(v, 3));
+    // the corners of frequency f + 1 are loaded during the arithmetic of frequency f
+    T vA[4][4], vB[4][4];
+    load_upwind(ip, sM, vA);
+    for (int f = 0; f < a.nfreq; f += 2) {
+      if (f + 1 < a.nfreq) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vB);
+      update(f, PORTA_BILIN(vA, 0), PORTA_BILIN(vA, 1), PORTA_BILIN(vA, 2), PORTA_BILIN(vA, 3));
+      if (f + 1 >= a.nfreq) break;
+      if (f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, vA);
+      update(f + 1, PORTA_BILIN(vB, 0), PORTA_BILIN(vB, 1), PORTA_BILIN(vB, 2),
+             PORTA_BILIN(vB, 3));
     }
   }
 #undef PORTA_BILIN
