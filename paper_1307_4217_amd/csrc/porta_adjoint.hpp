@@ -117,8 +117,8 @@ k_adjoint_plane(const AdjArgs<T> a) {
   T aT = 0, aSM[4] = {0, 0, 0, 0}, aSO[4] = {0, 0, 0, 0}, aCM[4] = {0, 0, 0, 0};
   T aKM[6] = {0, 0, 0, 0, 0, 0}, aKO[6] = {0, 0, 0, 0, 0, 0};
   // The corner values of one frequency: the adjoint of the plane above (or the seed)
-  // and the forward state of the plane below.  They are loaded one frequency ahead,
-  // so that a frequency's arithmetic covers the latency of the next one's loads.  The
+  // and the forward state of the plane below.  In FP32 they are loaded one frequency
+  // ahead, so that a frequency's arithmetic covers the latency of the next one's loads.  The
   // loop is instantiated for the presence of the plane above (HL) and below (HI),
   // which is the same for every thread of a launch.
   struct Corners {
@@ -205,14 +205,23 @@ k_adjoint_plane(const AdjArgs<T> a) {
       store4(lo + fo, out);
     }
     };
-    Corners cA, cB;
-    issue(0, cA);
-    for (int f = 0; f < a.nfreq; f += 2) {
-      if (f + 1 < a.nfreq) issue(f + 1, cB);
-      body(f, cA);
-      if (f + 1 >= a.nfreq) break;
-      if (f + 2 < a.nfreq) issue(f + 2, cA);
-      body(f + 1, cB);
+    if constexpr (sizeof(T) == 4) {
+      Corners cA, cB;
+      issue(0, cA);
+      for (int f = 0; f < a.nfreq; f += 2) {
+        if (f + 1 < a.nfreq) issue(f + 1, cB);
+        body(f, cA);
+        if (f + 1 >= a.nfreq) break;
+        if (f + 2 < a.nfreq) issue(f + 2, cA);
+        body(f + 1, cB);
+      }
+    } else {
+      // FP64: one buffer (a second one does not fit in the registers of one wave)
+      for (int f = 0; f < a.nfreq; ++f) {
+        Corners c;
+        issue(f, c);
+        body(f, c);
+      }
     }
   };
   using yes = std::true_type;

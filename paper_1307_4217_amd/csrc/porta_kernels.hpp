@@ -520,16 +520,26 @@ k_sweep_plane(const PlaneArgs<T> a) {
       update(f, IM[0], IM[1], IM[2], IM[3]);
     }
   } else {
-    // the corners of frequency f + 1 are loaded during the arithmetic of frequency f
-    T vA[4][4], vB[4][4];
-    load_upwind(ip, sM, vA);
-    for (int f = 0; f < a.nfreq; f += 2) {
-      if (f + 1 < a.nfreq) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vB);
-      update(f, PORTA_BILIN(vA, 0), PORTA_BILIN(vA, 1), PORTA_BILIN(vA, 2), PORTA_BILIN(vA, 3));
-      if (f + 1 >= a.nfreq) break;
-      if (f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, vA);
-      update(f + 1, PORTA_BILIN(vB, 0), PORTA_BILIN(vB, 1), PORTA_BILIN(vB, 2),
-             PORTA_BILIN(vB, 3));
+    if constexpr (sizeof(T) == 4) {
+      // the corners of frequency f + 1 are loaded during the arithmetic of frequency f
+      // (in FP64 the second buffer does not fit without spilling)
+      T vA[4][4], vB[4][4];
+      load_upwind(ip, sM, vA);
+      for (int f = 0; f < a.nfreq; f += 2) {
+        if (f + 1 < a.nfreq) load_upwind(ip + (size_t)(f + 1) * fstride, sM, vB);
+        update(f, PORTA_BILIN(vA, 0), PORTA_BILIN(vA, 1), PORTA_BILIN(vA, 2),
+               PORTA_BILIN(vA, 3));
+        if (f + 1 >= a.nfreq) break;
+        if (f + 2 < a.nfreq) load_upwind(ip + (size_t)(f + 2) * fstride, sM, vA);
+        update(f + 1, PORTA_BILIN(vB, 0), PORTA_BILIN(vB, 1), PORTA_BILIN(vB, 2),
+               PORTA_BILIN(vB, 3));
+      }
+    } else {
+      T v[4][4];
+      for (int f = 0; f < a.nfreq; ++f) {
+        load_upwind(ip + (size_t)f * fstride, sM, v);
+        update(f, PORTA_BILIN(v, 0), PORTA_BILIN(v, 1), PORTA_BILIN(v, 2), PORTA_BILIN(v, 3));
+      }
     }
   }
 #undef PORTA_BILIN
