@@ -163,3 +163,52 @@ def test_c3_interleaved_schedule_sampled(orc):
     assert got == pytest.approx(want, rel=1e-4)
     del case
     torch.cuda.empty_cache()
+
+
+def test_c3_j_and_see_in_the_benchmark_configuration(orc):
+    """The forward half of the benchmark step at 256x256x128 in FP32: J summed over the
+    calls of the interleaved schedule (5 ranges of 16 upward rays, then the downward rays
+    in batches of 40) against the one-call sweep, and the FP64 statistical-equilibrium
+    update with Hanle rotation that follows, at every point, against the oracle's update
+    from the same J (S^K_Q, the FP32 emissivities it writes, and R_c)."""
+    torch = require_gpu()
+    torch.cuda.empty_cache()
+    cfg = inputs.CONFIGS["C3"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, porta.F32)
+    hg = case.hg
+    nh = hg.nray_up
+    ref_j, _ = porta.fs_sweep(hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                              prec=porta.F32, want_itop=False)
+    jkq = torch.empty_like(ref_j)
+    itop = torch.empty((nh, hg.nfreq, hg.ny, hg.nx, 4), dtype=torch.float32, device="cuda")
+    for i, r in enumerate(range(0, nh, 16)):
+        porta.fs_sweep(hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                       prec=porta.F32, jkq=jkq, accumulate=i > 0, i_top=itop,
+                       opts=porta.options(ray_batch=16, ray_first=r, ray_count=16))
+    porta.fs_sweep(hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2, prec=porta.F32,
+                   jkq=jkq, accumulate=True, want_itop=False,
+                   opts=porta.options(ray_batch=40, ray_first=nh, ray_count=nh))
+    torch.cuda.synchronize()
+    jh, rj = jkq.cpu().numpy(), ref_j.cpu().numpy()
+    scale = np.abs(rj[0]).max()
+    assert np.abs(jh - rj).max() / scale < 1e-13
+    _j_invariants(jh)
+    del itop, ref_j
+    S = to_dev(atm.source, torch.float64)
+    hanle, bhat = to_dev(atm.hanle, torch.float64), to_dev(atm.bhat, torch.float64)
+    emis_out = torch.empty_like(case.emis)
+    s_new, _, rc = porta.see_update(jkq, S, atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
+                                    bhat, kappa=case.kappa, emis_out=emis_out, prec=porta.F32)
+    torch.cuda.synchronize()
+    s_ref, e_ref, rc_ref = orc.see_update(jh, atm.source, atm, kappa=atm.kappa)
+    np.testing.assert_allclose(s_new.cpu().numpy(), s_ref, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(emis_out.cpu().numpy(), e_ref.astype(np.float32), rtol=2e-7,
+                               atol=1e-30)
+    assert rc.item() == pytest.approx(rc_ref, rel=1e-12)
+    print(f"C3 J over the benchmark's 7 sweep calls vs one call: "
+          f"{np.abs(jh - rj).max() / scale:.2e}; SEE at {atm.npoints} points matches, "
+          f"R_c {rc.item():.6e}")
+    del case
+    torch.cuda.empty_cache()
