@@ -101,12 +101,12 @@ double hm_besser_cm_grad(double yM, double yO, double yP, double ratio, double* 
 
 double hm_coef_tau_grad_f64(double tau, const double* g6) {
   const porta::Coefs<double> c = porta::coefficients(tau);
-  return porta::coef_tau_grad(c, tau, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
+  return porta::coef_tau_grad(c, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
 }
 
 float hm_coef_tau_grad_f32(float tau, const float* g6) {
   const porta::Coefs<float> c = porta::coefficients(tau);
-  return porta::coef_tau_grad(c, tau, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
+  return porta::coef_tau_grad(c, g6[0], g6[1], g6[2], g6[3], g6[4], g6[5]);
 }
 
 }  // extern "C"

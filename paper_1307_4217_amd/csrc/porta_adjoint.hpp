@@ -192,7 +192,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
       aSO[s] += cf.omO * lb[s];
       aCM[s] += cf.omC * lb[s];
     }
-    aT += ph * coef_tau_grad(cf, tau, gE, gPM, gPO, gOM, gOO, gOC);
+    aT += ph * coef_tau_grad(cf, gE, gPM, gPO, gOM, gOO, gOC);
     kprime_outer(cf.psiM, lb, IM, aKM);
     kprime_outer(cf.psiO, lb, IO, aKO);
     if (lo) {

@@ -46,6 +46,7 @@ __host__ __device__ inline double recip(double x) { return 1.0 / x; }
 template <class T>
 struct Coefs {
   T e, psiM, psiO, omM, omO, omC;
+  T pmt, omt, oct;   // psi'_M / tau, omega_M / tau, omega_C / tau (for the tau-derivatives)
 };
 
 // Horner evaluation of tau * sum_{n<NT} c_n tau^n.
@@ -77,11 +78,14 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
     const float E2 = 0.5f - tau * E3;
     const float E1 = 1.0f - tau * E2;
     c.e = 1.0f - tau * E1;
+    c.pmt = E1 - E2;
+    c.omt = E1 + 2.0f * (E3 - E2);
+    c.oct = 2.0f * E2 - 4.0f * E3;
     c.psiO = tau * E2;
-    c.psiM = tau * (E1 - E2);
+    c.psiM = tau * c.pmt;
     c.omO = (2.0f * tau) * E3;
-    c.omM = tau * (E1 + 2.0f * (E3 - E2));
-    c.omC = tau * (2.0f * E2 - 4.0f * E3);
+    c.omM = tau * c.omt;
+    c.omC = tau * c.oct;
   } else {
     c.e = exp_neg(tau);
     const float it = recip(tau), it2 = it * it;
@@ -91,6 +95,9 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
     c.omM = (2.0f - c.e * (tau * tau + 2.0f * tau + 2.0f)) * it2;
     c.omO = 1.0f - 2.0f * g * it2;
     c.omC = 2.0f * (tau - 2.0f + c.e * (tau + 2.0f)) * it2;
+    c.pmt = c.psiM * it;
+    c.omt = c.omM * it;
+    c.oct = c.omC * it;
   }
   return c;
 }
@@ -128,6 +135,9 @@ __host__ __device__ inline Coefs<double> coefficients(double tau) {
     c.omO = 1.0 - 2.0 * (c.e + tau - 1.0) * it2;
     c.omC = 2.0 * (tau - 2.0 + c.e * (tau + 2.0)) * it2;
   }
+  c.pmt = c.psiM * it;
+  c.omt = c.omM * it;
+  c.oct = c.omC * it;
   return c;
 }
 
@@ -276,17 +286,16 @@ __host__ __device__ inline double parabolic_cm_grad(double yM, double yO, double
 }
 
 // dL/dtau from the adjoints of the six coefficients, with the derivatives
-// written through the coefficients themselves:
-//   de/dt = -e,                 dpsi'_M/dt = e - psi'_M/t,   dpsi'_O/dt = psi'_M/t,
-//   domega_M/dt = e - 2 omega_M/t,   domega_C/dt = 2 (psi'_M - omega_C)/t,
-//   domega_O/dt = 2 (omega_M + omega_C - psi'_M)/t   (from omega_M+omega_O+omega_C = 1-e).
+// written through the coefficients themselves (pmt = psi'_M/t, omt = omega_M/t,
+// oct = omega_C/t, formed with the coefficients):
+//   de/dt = -e,                 dpsi'_M/dt = e - pmt,   dpsi'_O/dt = pmt,
+//   domega_M/dt = e - 2 omt,    domega_C/dt = 2 (pmt - oct),
+//   domega_O/dt = 2 (omt + oct - pmt)   (from omega_M+omega_O+omega_C = 1-e).
 template <class T>
-__host__ __device__ inline T coef_tau_grad(const Coefs<T>& c, T tau, T gE, T gPM, T gPO, T gOM,
-                                           T gOO, T gOC) {
-  const T it = recip(tau);
-  const T pmt = c.psiM * it;
-  return -c.e * gE + (c.e - pmt) * gPM + pmt * gPO + (c.e - T(2) * c.omM * it) * gOM +
-         T(2) * (c.omM + c.omC - c.psiM) * it * gOO + T(2) * (c.psiM - c.omC) * it * gOC;
+__host__ __device__ inline T coef_tau_grad(const Coefs<T>& c, T gE, T gPM, T gPO, T gOM, T gOO,
+                                           T gOC) {
+  return -c.e * gE + (c.e - c.pmt) * gPM + c.pmt * gPO + (c.e - T(2) * c.omt) * gOM +
+         T(2) * (c.omt + c.oct - c.pmt) * gOO + T(2) * (c.pmt - c.oct) * gOC;
 }
 
 // ---------------------------------------------------------------------------
