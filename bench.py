@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (counter calibration for profiles)")
-    ap.add_argument("--cpu-pairs", type=int, default=16,
+    ap.add_argument("--cpu-pairs", type=int, default=48,
                     help="(ray, frequency) pairs of the workload swept by the CPU oracle")
     return ap.parse_args()
 
