@@ -92,7 +92,7 @@ KERNEL_SYMBOLS = {
     "k_sweep_plane<float, 0>": "_ZN5porta13k_sweep_planeIfLi0EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane<double, 0>": "_ZN5porta13k_sweep_planeIdLi0EEEvNS_9PlaneArgsIT_EE",
     "k_adjoint_plane<float>": "_ZN5porta15k_adjoint_planeIfEEvNS_7AdjArgsIT_EE",
-    "k_adjoint_gather": "_ZN5porta16k_adjoint_gatherENS_10GatherArgsE",
+    "k_adjoint_gather<float>": "_ZN5porta16k_adjoint_gatherIfEEvNS_10GatherArgsIT_EE",
 }
 
 

@@ -233,12 +233,13 @@ Layout adjoint_layout(const porta_grid* g, const porta_quad* q, int prec, int st
   off = align_up(off + L.plane);
   L.lamB = off;
   off = align_up(off + L.plane);
+  // per-(node, ray) partials in the sweep precision
   L.go = off;
-  off = align_up(off + nrb * 13 * np * sizeof(double));
+  off = align_up(off + nrb * 13 * np * elem(prec));
   L.gm = off;
-  off = align_up(off + nrb * 13 * np * sizeof(double));
+  off = align_up(off + nrb * 13 * np * elem(prec));
   L.gp = off;
-  off = align_up(off + nrb * 7 * np * sizeof(double));
+  off = align_up(off + nrb * 7 * np * elem(prec));
   L.grad = off;
   off = align_up(off + 13 * N * sizeof(double));
   L.total = off;
@@ -447,7 +448,6 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
   const size_t N = (size_t)np * nz;
   double* grad = reinterpret_cast<double*>(ws + L.grad);
   if ((rc = fill(grad, 13 * N, 0.0, st))) return rc;
-  const int nh = q->nmu * q->nchi;
   const int nrb_max = ray_batch(q, o);
   const int block = (o && o->block > 0) ? o->block : 256;
   if (block % 64 != 0 || block > 256) return fail(PORTA_EINVAL, "block must be 64, 128, 192 or 256");
@@ -503,9 +503,9 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.lam_next = lam_next;
         a.seed = seed + (size_t)r0 * q->nfreq * np * 4;
         a.lam_cur = (k - 1 >= 1) ? lam[cur] : nullptr;
-        a.g_o = reinterpret_cast<double*>(ws + L.go);
-        a.g_m = reinterpret_cast<double*>(ws + L.gm);
-        a.g_p = reinterpret_cast<double*>(ws + L.gp);
+        a.g_o = reinterpret_cast<T*>(ws + L.go);
+        a.g_m = reinterpret_cast<T*>(ws + L.gm);
+        a.g_p = reinterpret_cast<T*>(ws + L.gp);
         a.N = N;
         a.nx = nx;
         a.ny = ny;
@@ -526,7 +526,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
                            lds_adj, st, a);
         if ((rc = check_launch("adjoint_plane"))) return rc;
-        GatherArgs b;
+        GatherArgs<T> b;
         b.g_o = a.g_o;
         b.g_m = a.g_m;
         b.g_p = a.g_p;
@@ -545,7 +545,7 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         b.inv_dy = a.inv_dy;
         b.ray0 = r0;
         b.nrb = nrb;
-        hipLaunchKernelGGL(k_adjoint_gather, dim3((np + 255) / 256, 4), dim3(256), 0, st, b);
+        hipLaunchKernelGGL(k_adjoint_gather<T>, dim3((np + 255) / 256, 4), dim3(256), 0, st, b);
         if ((rc = check_launch("adjoint_gather"))) return rc;
         lam_next = a.lam_cur;
         cur ^= 1;

@@ -35,9 +35,11 @@ struct AdjArgs {
   const T* lam_next;   // Lambda of plane kO + 1, or nullptr when kO is the top plane
   const T* seed;       // dL/dI on the top plane for this batch (used when lam_next is null)
   T* lam_cur;          // Lambda of plane kO, or nullptr when plane kM is the boundary
-  double* g_o;         // [ray in batch][13][node]: coefficients at O
-  double* g_m;         // [ray in batch][13][node]: coefficients interpolated at M
-  double* g_p;         // [ray in batch][7][node]:  eta_I and eps interpolated at P
+  T* g_o;              // [ray in batch][13][node]: coefficients at O
+  T* g_m;              // [ray in batch][13][node]: coefficients interpolated at M
+  T* g_p;              // [ray in batch][7][node]:  eta_I and eps interpolated at P
+                       // (partials of one node and ray, formed in FP64, stored in the
+                       // sweep precision; the gather sums them in FP64)
   size_t N;
   int nx, ny, np, nfreq;
   int kO, kM, kP;
@@ -304,32 +306,33 @@ k_adjoint_plane(const AdjArgs<T> a) {
     gkM -= gKM[c] * ps.etaM[c] * ps.ikM * ps.ikM;
     gkO -= gKO[c] * ps.etaO[c] * ps.ikO * ps.ikO;
   }
-  double* go = a.g_o + (size_t)rb * 13 * a.np + p;
-  double* gm = a.g_m + (size_t)rb * 13 * a.np + p;
+  T* go = a.g_o + (size_t)rb * 13 * a.np + p;
+  T* gm = a.g_m + (size_t)rb * 13 * a.np + p;
   const size_t np = (size_t)a.np;
-  go[0] = gkO;
-  gm[0] = gkM;
+  go[0] = (T)gkO;
+  gm[0] = (T)gkM;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    go[(1 + c) * np] = ghO[c];
-    gm[(1 + c) * np] = ghM[c];
-    go[(7 + c) * np] = geO[c];
-    gm[(7 + c) * np] = geM[c];
+    go[(1 + c) * np] = (T)ghO[c];
+    gm[(1 + c) * np] = (T)ghM[c];
+    go[(7 + c) * np] = (T)geO[c];
+    gm[(7 + c) * np] = (T)geM[c];
   }
   if (ps.hasP) {
-    double* gp = a.g_p + (size_t)rb * 7 * a.np + p;
-    gp[0] = gkP;
+    T* gp = a.g_p + (size_t)rb * 7 * a.np + p;
+    gp[0] = (T)gkP;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) gp[(1 + c) * np] = geP[c];
+    for (int c = 0; c < 6; ++c) gp[(1 + c) * np] = (T)geP[c];
   }
 }
 
 // Gather the per-(node, ray) partials of one plane onto the coefficient
 // gradients of planes kM, kO and kP (fixed ray order per component, no atomics).
+template <class T>
 struct GatherArgs {
-  const double* g_o;
-  const double* g_m;
-  const double* g_p;
+  const T* g_o;
+  const T* g_m;
+  const T* g_p;
   const RayConsts* rays;
   double* grad;       // [13][N]: kappa, propmat[6], emis[6]
   size_t N;
@@ -341,7 +344,8 @@ struct GatherArgs {
 
 // blockIdx.y: component group (0: the 13 at O; 1, 2: the 13 at M in two halves; 3: the
 // 7 at P), so that four threads share a node and each stencil is built once per group.
-__global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs a) {
+template <class T>
+__global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs<T> a) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
   if (q >= a.np || (grp == 3 && a.kP < 0)) return;
@@ -354,7 +358,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs a) {
   for (int c = 0; c < 13; ++c) acc[c] = 0.0;
   if (grp == 0) {
     for (int rb = 0; rb < a.nrb; ++rb) {
-      const double* go = a.g_o + (size_t)rb * 13 * np + q;
+      const T* go = a.g_o + (size_t)rb * 13 * np + q;
 #pragma unroll
       for (int c = 0; c < 13; ++c) acc[c] += go[c * np];
     }
@@ -370,11 +374,11 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs a) {
     const double sds = atM ? -ds : ds;   // M upwind, P downwind, as in the sweep
     const Stencil t = make_tstencil(i, j, a.nx, a.ny, sds * rc.sx * a.inv_dx,
                                     sds * rc.sy * a.inv_dy);
-    const double* gb = atM ? a.g_m + ((size_t)rb * 13 + c0) * np : a.g_p + (size_t)rb * 7 * np;
+    const T* gb = atM ? a.g_m + ((size_t)rb * 13 + c0) * np : a.g_p + (size_t)rb * 7 * np;
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       if (c < nc) {
-        const double* g = gb + c * np;
+        const T* g = gb + c * np;
         acc[c] += t.w00 * g[t.i00] + t.w10 * g[t.i10] + t.w01 * g[t.i01] + t.w11 * g[t.i11];
       }
     }
