@@ -212,3 +212,40 @@ def test_c3_j_and_see_in_the_benchmark_configuration(orc):
           f"R_c {rc.item():.6e}")
     del case
     torch.cuda.empty_cache()
+
+
+def test_c5_fp32_against_fp64_first_iteration():
+    """504x504x160 (40.6 M points, 160 rays, 101 frequencies, magnetic): too large for
+    the oracle, so the FP32 sweep is checked against the FP64 one on the first
+    iteration: J^K_Q and Lambda-bar to the FP32 bar relative to the scale of J^0_0,
+    and S^K_Q after the FP64 statistical-equilibrium update from each, to that bar
+    times the Jacobi denominator's bound 1/eps_c."""
+    torch = require_gpu()
+    torch.cuda.empty_cache()
+    cfg = inputs.CONFIGS["C5"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    hg = porta.HostGrid.from_inputs(atm, q)
+    S0 = to_dev(atm.source, torch.float64)
+    hanle, bhat = to_dev(atm.hanle, torch.float64), to_dev(atm.bhat, torch.float64)
+    out = {}
+    for prec, dt in ((porta.F32, torch.float32), (porta.F64, torch.float64)):
+        k, p, e = to_dev(atm.kappa, dt), to_dev(atm.propmat, dt), to_dev(atm.emis, dt)
+        jkq, _ = porta.fs_sweep(hg, k, p, e, atm.i_bottom, atm.w2, prec=prec, want_itop=False,
+                                opts=porta.options(ray_batch=40))
+        s_new, _, rc = porta.see_update(jkq, S0, atm.eps_c, atm.delta2, atm.w2, atm.planck,
+                                        hanle, bhat)
+        torch.cuda.synchronize()
+        out[prec] = (jkq, s_new, rc.item())
+        del k, p, e
+        torch.cuda.empty_cache()
+    j32, s32, rc32 = out[porta.F32]
+    j64, s64, rc64 = out[porta.F64]
+    scale = float(j64[0].abs().max())
+    ej = float((j32 - j64).abs().max()) / scale
+    es = float(((s32 - s64).abs() / s64[0].abs()).max())
+    print(f"C5 FP32 vs FP64, first iteration: J max err / scale {ej:.2e}, "
+          f"S max err / S00 {es:.2e}, R_c {rc32:.6e} vs {rc64:.6e}")
+    assert ej < 2e-5
+    assert es < 2e-5 / atm.eps_c
+    assert rc32 == pytest.approx(rc64, rel=2e-5 / atm.eps_c)
