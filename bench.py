@@ -190,10 +190,16 @@ def cpu_baseline(cfg, atm, q, pairs):
         done += len(rs) * len(fs)
     dt = time.perf_counter() - t0
     upd = done * cfg.npoints
+    # and one thread on two of the pairs
+    t1 = time.perf_counter()
+    orc.fs_sweep(op, rays=rays[:2], freqs=freqs[:1], want_j=True, want_itop=True, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": upd / dt, "unit": "point*ray*freq updates/s", "cores": nthreads,
             "kind": "oracle",
             "sample": f"{done} (ray, freq) pairs of the {cfg.nx}x{cfg.ny}x{cfg.nz} grid, FP64 "
-                      f"sweep + J ({upd:.3e} updates in {dt:.1f} s)"}
+                      f"sweep + J ({upd:.3e} updates in {dt:.1f} s)",
+            "single_thread_value": 2 * cfg.npoints / dt1,
+            "single_thread_sample": f"2 of those pairs on one thread ({dt1:.1f} s)"}
 
 
 def main():
