@@ -81,11 +81,11 @@ def sweep_launch_bytes(cfg, nrb, elem):
 def adjoint_launch_bytes(cfg, nrb, elem):
     """Algorithmic HBM bytes of one plane launch of the adjoint kernel: per update the
     adjoint of the plane above (or the seed) and the forward state of the plane below
-    read and the new adjoint written; per node and ray the 33 FP64 partials written;
-    three planes of the 13 transfer coefficients."""
+    read and the new adjoint written; per node and ray the 33 partials written (in the
+    sweep precision); three planes of the 13 transfer coefficients."""
     np_ = cfg.nx * cfg.ny
     updates = nrb * cfg.nfreq * np_
-    return updates * 12 * elem + nrb * np_ * 33 * 8 + 3 * np_ * 13 * elem, updates
+    return updates * 12 * elem + nrb * np_ * 33 * elem + 3 * np_ * 13 * elem, updates
 
 
 KERNEL_SYMBOLS = {
