@@ -295,7 +295,12 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * `checkpoint_stride` planes (1..nz-1) instead of being stored.  With
  * `checkpoints` NULL the call first sweeps the upward rays to make them
  * (workspace kind PORTA_WS_ADJOINT); otherwise they are the ones porta_fs_sweep
- * wrote for these fields with the same stride (kind PORTA_WS_ADJOINT_CKPT).
+ * wrote for these fields with the same stride, the same options' ray range and a
+ * buffer of porta_checkpoint_size() bytes (kind PORTA_WS_ADJOINT_CKPT); the
+ * library cannot check that pairing.  With a ray range in the options only its
+ * upward rays are differentiated, and the gradients add up over calls.  Stride 1
+ * keeps every plane, so nothing is recomputed.  The per-(node, ray) partials
+ * are formed and summed in FP64 and stored in between in the sweep precision.
  * Only interp = PORTA_INTERP_BILINEAR is differentiated; PORTA_INTERP_BEZIER2D
  * returns PORTA_EUNSUPPORTED.
  */
