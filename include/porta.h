@@ -177,12 +177,14 @@ size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int
  *                   the upward rays' states every checkpoint_stride planes for a
  *                   later porta_fs_adjoint of the same fields (no extra traffic:
  *                   those planes are written there instead of the workspace)
+ *   checkpoint_bytes : size of that buffer; below porta_checkpoint_size() the
+ *                   call returns PORTA_ENOMEM before any launch
  *   workspace     : device, >= porta_workspace_size(..., PORTA_WS_SWEEP, ...)
  */
 int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                    int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
-                   void* i_top, void* checkpoints, int checkpoint_stride, void* workspace,
-                   size_t ws_bytes, void* stream);
+                   void* i_top, void* checkpoints, size_t checkpoint_bytes,
+                   int checkpoint_stride, void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Eq. 1 (and the Lambda* average) from a stored block of Stokes vectors:
@@ -295,9 +297,10 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * `checkpoint_stride` planes (1..nz-1) instead of being stored.  With
  * `checkpoints` NULL the call first sweeps the upward rays to make them
  * (workspace kind PORTA_WS_ADJOINT); otherwise they are the ones porta_fs_sweep
- * wrote for these fields with the same stride, the same options' ray range and a
- * buffer of porta_checkpoint_size() bytes (kind PORTA_WS_ADJOINT_CKPT); the
- * library cannot check that pairing.  With a ray range in the options only its
+ * wrote for these fields with the same stride and the same options' ray range
+ * (kind PORTA_WS_ADJOINT_CKPT); checkpoint_bytes is the buffer's size, and below
+ * porta_checkpoint_size() the call returns PORTA_ENOMEM before any launch (that
+ * the contents come from such a sweep is the caller's to ensure).  With a ray range in the options only its
  * upward rays are differentiated, and the gradients add up over calls.  Stride 1
  * keeps every plane, so nothing is recomputed.  The per-(node, ray) partials
  * are formed and summed in FP64 and stored in between in the sweep precision.
@@ -306,9 +309,9 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  */
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,
-                     const void* checkpoints, int checkpoint_stride, void* g_kappa,
-                     void* g_propmat, void* g_emis, void* workspace, size_t ws_bytes,
-                     void* stream);
+                     const void* checkpoints, size_t checkpoint_bytes, int checkpoint_stride,
+                     void* g_kappa, void* g_propmat, void* g_emis, void* workspace,
+                     size_t ws_bytes, void* stream);
 
 /* Text of a porta_status. */
 const char* porta_strerror(int status);

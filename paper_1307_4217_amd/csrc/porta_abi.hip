@@ -620,8 +620,8 @@ size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int
 
 int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                    int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
-                   void* i_top, void* checkpoints, int checkpoint_stride, void* workspace,
-                   size_t ws_bytes, void* stream) {
+                   void* i_top, void* checkpoints, size_t ck_bytes, int checkpoint_stride,
+                   void* workspace, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
       (rc = validate_interp(interp)))
@@ -637,6 +637,12 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
+  if (checkpoints) {
+    const size_t need = checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
+    if (ck_bytes < need)
+      return fail(PORTA_ENOMEM, "checkpoint buffer of %zu bytes is smaller than the %zu required",
+                  ck_bytes, need);
+  }
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
   const Layout L = sweep_layout(grid, quad, prec, opts);
   if (ws_bytes < L.total)
@@ -694,9 +700,9 @@ int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray
 
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,
-                     const void* checkpoints, int checkpoint_stride, void* g_kappa,
-                     void* g_propmat, void* g_emis, void* workspace, size_t ws_bytes,
-                     void* stream) {
+                     const void* checkpoints, size_t ck_bytes, int checkpoint_stride,
+                     void* g_kappa, void* g_propmat, void* g_emis, void* workspace,
+                     size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
       (rc = validate_interp(interp)))
@@ -710,6 +716,12 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
   if (nstokes(opts) == 1)
     return fail(PORTA_EUNSUPPORTED, "the adjoint is for the Stokes-vector sweep");
+  if (checkpoints) {
+    const size_t need = checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
+    if (ck_bytes < need)
+      return fail(PORTA_ENOMEM, "checkpoint buffer of %zu bytes is smaller than the %zu required",
+                  ck_bytes, need);
+  }
   if (interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");

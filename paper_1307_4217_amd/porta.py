@@ -74,7 +74,7 @@ def lib():
             L.porta_workspace_size.restype = sz
             L.porta_fs_sweep.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
                                          C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
-                                         vp, C.c_int, vp, sz, vp]
+                                         vp, sz, C.c_int, vp, sz, vp]
             L.porta_checkpoint_size.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int,
                                                 C.c_int, C.POINTER(Options)]
             L.porta_checkpoint_size.restype = sz
@@ -91,8 +91,8 @@ def lib():
             L.porta_rel_change.argtypes = [C.c_int64, vp, vp, vp, vp, sz, vp]
             L.porta_emissivity.argtypes = [C.c_int64, ci, vp, vp, vp, ci, vp]
             L.porta_fs_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
-                                           C.c_int, C.c_int, C.POINTER(Options), vp, vp, C.c_int,
-                                           vp, vp, vp, vp, sz, vp]
+                                           C.c_int, C.c_int, C.POINTER(Options), vp, vp, sz,
+                                           C.c_int, vp, vp, vp, vp, sz, vp]
             L.porta_strerror.argtypes = [C.c_int]
             L.porta_strerror.restype = C.c_char_p
             L.porta_last_error.restype = C.c_char_p
@@ -122,6 +122,15 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return t.ctypes.data
     return t.data_ptr()
+
+
+def _nbytes(t):
+    """Size in bytes of a tensor/array (0 for None)."""
+    if t is None:
+        return 0
+    if isinstance(t, np.ndarray):
+        return int(t.nbytes)
+    return int(t.numel()) * int(t.element_size())
 
 
 def _stream(stream=None):
@@ -214,7 +223,7 @@ def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, int
                               int(interp), C.byref(opts) if opts else None,
                               _ptr(jkq) if want_jkq else None, int(bool(accumulate)),
                               _ptr(i_top) if want_itop else None, _ptr(checkpoints),
-                              int(checkpoint_stride), _ptr(workspace), workspace.numel(),
+                              _nbytes(checkpoints), int(checkpoint_stride), _ptr(workspace), workspace.numel(),
                               _stream(stream))
     _check("porta_fs_sweep", st)
     return (jkq if want_jkq else None), (i_top if want_itop else None)
@@ -361,7 +370,8 @@ def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, p
     f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))
     st = lib().porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), int(prec),
                                 int(interp), C.byref(opts) if opts else None, _ptr(dl_ditop),
-                                _ptr(checkpoints), int(checkpoint_stride), _ptr(g_kappa),
+                                _ptr(checkpoints), _nbytes(checkpoints),
+                                int(checkpoint_stride), _ptr(g_kappa),
                                 _ptr(g_propmat),
                                 _ptr(g_emis), _ptr(workspace), workspace.numel(), _stream(stream))
     _check("porta_fs_adjoint", st)

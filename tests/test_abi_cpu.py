@@ -41,7 +41,7 @@ def call_sweep(hg, prec=porta.F64, interp=porta.BILINEAR, ws_bytes=None, fields=
     f = porta.Fields(dummy.ctypes.data if fields else None, dummy.ctypes.data,
                      dummy.ctypes.data, 1.0, 1.0)
     return L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), prec, interp, None,
-                            None, 0, None, None, 0, dummy.ctypes.data if ws else None,
+                            None, 0, None, None, 0, 0, dummy.ctypes.data if ws else None,
                             0 if ws_bytes is None else ws_bytes, None)
 
 
@@ -113,12 +113,13 @@ def test_other_entry_points_validate():
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
     for stride in (0, 32):   # must be in 1..nz-1
         assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None,
-                                  dummy.ctypes.data, None, stride, dummy.ctypes.data,
+                                  dummy.ctypes.data, None, 0, stride, dummy.ctypes.data,
                                   dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
                                   1 << 40, None) == -1
     # a checkpoint buffer needs a valid stride
     assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, None, None, 0,
-                            None, dummy.ctypes.data, 0, dummy.ctypes.data, 1 << 40, None) == -1
+                            None, dummy.ctypes.data, 1 << 40, 0, dummy.ctypes.data, 1 << 40,
+                            None) == -1
     assert porta.checkpoint_size(hg, porta.F32, 4) == (30 // 4) * 40 * 21 * 256 * 16
     assert porta.checkpoint_size(hg, porta.F64, 31) == 0
     assert (porta.workspace_size(hg, porta.F32, porta.WS_ADJOINT_CKPT, 4)
@@ -132,7 +133,7 @@ def test_adjoint_rejects_bezier_mode():
     dummy = np.zeros(8)
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
     assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0,
-                              porta.BEZIER2D, None, dummy.ctypes.data, None, 4,
+                              porta.BEZIER2D, None, dummy.ctypes.data, None, 0, 4,
                               dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
                               dummy.ctypes.data, 1 << 40, None) == -2
 
@@ -181,10 +182,10 @@ def test_unknown_control_point_rule_rejected():
     f = porta.Fields(d, d, d, 1.0, 1.0)
     bad = porta.options(control=2)
     assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, C.byref(bad),
-                            d, 0, d, None, 0, d, 1 << 40, None) == -1
+                            d, 0, d, None, 0, 0, d, 1 << 40, None) == -1
     assert b"control" in L.porta_last_error()
     assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
-                              C.byref(bad), d, None, 2, d, d, d, d, 1 << 40, None) == -1
+                              C.byref(bad), d, None, 0, 2, d, d, d, d, 1 << 40, None) == -1
 
 
 def test_intensity_only_option_checks():
@@ -193,14 +194,15 @@ def test_intensity_only_option_checks():
     d = np.zeros(8).ctypes.data
     f = porta.Fields(d, d, d, 1.0, 1.0)
     args = lambda o, interp=0, ck=None, stride=0: (C.byref(hg.grid), C.byref(hg.quad), C.byref(f),
-                                                   0, interp, C.byref(o), d, 0, d, ck, stride, d,
-                                                   1 << 40, None)
+                                                   0, interp, C.byref(o), d, 0, d, ck,
+                                                   1 << 40 if ck else 0, stride, d, 1 << 40,
+                                                   None)
     assert L.porta_fs_sweep(*args(porta.options(stokes=2))) == -1
     assert L.porta_fs_sweep(*args(porta.options(stokes=1), interp=1)) == -2
     assert L.porta_fs_sweep(*args(porta.options(stokes=1), ck=d, stride=2)) == -2
     assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
-                              C.byref(porta.options(stokes=1)), d, None, 2, d, d, d, d, 1 << 40,
-                              None) == -2
+                              C.byref(porta.options(stokes=1)), d, None, 0, 2, d, d, d, d,
+                              1 << 40, None) == -2
     # the workspace of the intensity-only sweep holds a quarter of the plane states
     w4 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1, porta.options(ray_batch=4))
     w1 = porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1,
@@ -219,9 +221,9 @@ def test_ray_range_checks_and_sizes():
     for first, count in ((0, 2 * nh + 1), (2 * nh - 5, 6), (-1, 2), (0, -1)):
         o = porta.options(ray_first=first, ray_count=count)
         assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
-                                C.byref(o), d, 0, d, None, 0, d, 1 << 40, None) == -1
+                                C.byref(o), d, 0, d, None, 0, 0, d, 1 << 40, None) == -1
         assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0,
-                                  C.byref(o), d, None, 2, d, d, d, d, 1 << 40, None) == -1
+                                  C.byref(o), d, None, 0, 2, d, d, d, d, 1 << 40, None) == -1
         assert porta.checkpoint_size(hg, porta.F32, 4, o) == 0
     full = porta.checkpoint_size(hg, porta.F32, 4)
     # only the upward rays of the range are kept: 10 of [30, 50), none of the downward
@@ -238,3 +240,21 @@ def test_ray_range_checks_and_sizes():
         assert sub == porta.workspace_size(hg, porta.F32, kind, stride,
                                            porta.options(ray_batch=8))
         assert sub < porta.workspace_size(hg, porta.F32, kind, stride)
+
+
+def test_short_checkpoint_buffer_rejected():
+    """A checkpoint buffer below porta_checkpoint_size() for the call's stride and ray
+    range is refused with PORTA_ENOMEM by the sweep and the adjoint before any launch."""
+    L = porta.lib()
+    hg = small_hg()
+    d = np.zeros(8).ctypes.data
+    f = porta.Fields(d, d, d, 1.0, 1.0)
+    for o in (None, porta.options(ray_first=4, ray_count=10)):
+        need = porta.checkpoint_size(hg, porta.F32, 3, o)
+        ob = C.byref(o) if o else None
+        assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 1, 0, ob, d, 0,
+                                d, d, need - 1, 3, d, 1 << 40, None) == -3
+        assert b"checkpoint buffer" in L.porta_last_error()
+        assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 1, 0, ob, d,
+                                  d, need - 1, 3, d, d, d, d, 1 << 40, None) == -3
+        assert b"checkpoint buffer" in L.porta_last_error()
