@@ -300,9 +300,10 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * wrote for these fields with the same stride and the same options' ray range
  * (kind PORTA_WS_ADJOINT_CKPT); checkpoint_bytes is the buffer's size, and below
  * porta_checkpoint_size() the call returns PORTA_ENOMEM before any launch (that
- * the contents come from such a sweep is the caller's to ensure).  With a ray range in the options only its
- * upward rays are differentiated, and the gradients add up over calls.  Stride 1
- * keeps every plane, so nothing is recomputed.  The per-(node, ray) partials
+ * the contents come from such a sweep is the caller's to ensure).  With a ray
+ * range in the options only its upward rays are differentiated, and the
+ * gradients add up over calls.  Stride 1 keeps every plane, so nothing is
+ * recomputed.  The per-(node, ray) partials
  * are formed and summed in FP64 and stored in between in the sweep precision.
  * Only interp = PORTA_INTERP_BILINEAR is differentiated; PORTA_INTERP_BEZIER2D
  * returns PORTA_EUNSUPPORTED.

@@ -733,13 +733,13 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   char* ws = static_cast<char*>(workspace);
   if (prec == PORTA_F64)
     return adjoint_impl<double>(grid, quad, fields, opts, static_cast<const double*>(dl_ditop),
-                                static_cast<const double*>(checkpoints), checkpoint_stride, static_cast<double*>(g_kappa),
-                                static_cast<double*>(g_propmat), static_cast<double*>(g_emis), ws,
-                                L, st);
+                                static_cast<const double*>(checkpoints), checkpoint_stride,
+                                static_cast<double*>(g_kappa), static_cast<double*>(g_propmat),
+                                static_cast<double*>(g_emis), ws, L, st);
   return adjoint_impl<float>(grid, quad, fields, opts, static_cast<const float*>(dl_ditop),
-                             static_cast<const float*>(checkpoints), checkpoint_stride, static_cast<float*>(g_kappa),
-                             static_cast<float*>(g_propmat), static_cast<float*>(g_emis), ws, L,
-                             st);
+                             static_cast<const float*>(checkpoints), checkpoint_stride,
+                             static_cast<float*>(g_kappa), static_cast<float*>(g_propmat),
+                             static_cast<float*>(g_emis), ws, L, st);
 }
 
 }  // extern "C"

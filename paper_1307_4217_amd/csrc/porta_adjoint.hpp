@@ -120,9 +120,9 @@ k_adjoint_plane(const AdjArgs<T> a) {
   T aKM[6] = {0, 0, 0, 0, 0, 0}, aKO[6] = {0, 0, 0, 0, 0, 0};
   // The corner values of one frequency: the adjoint of the plane above (or the seed)
   // and the forward state of the plane below.  In FP32 they are loaded one frequency
-  // ahead, so that a frequency's arithmetic covers the latency of the next one's loads.  The
-  // loop is instantiated for the presence of the plane above (HL) and below (HI),
-  // which is the same for every thread of a launch.
+  // ahead, so that a frequency's arithmetic covers the latency of the next one's
+  // loads.  The loop is instantiated for the presence of the plane above (HL) and
+  // below (HI), which is the same for every thread of a launch.
   struct Corners {
     T l[4][4], m[4][4];
   };
@@ -146,66 +146,67 @@ k_adjoint_plane(const AdjArgs<T> a) {
       }
     };
     auto body = [&](int f, const Corners& c) __attribute__((always_inline)) {
-    const size_t fo = (size_t)f * fstride;
-    T lam[4];
-    if constexpr (HL) {
+      const size_t fo = (size_t)f * fstride;
+      T lam[4];
+      if constexpr (HL) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          lam[s] = n00 * c.l[0][s] + n10 * c.l[1][s] + n01 * c.l[2][s] + n11 * c.l[3][s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lam[s] = c.l[0][s];
+      }
+      T IM[4];
+      if constexpr (HI) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          IM[s] = w00 * c.m[0][s] + w10 * c.m[1][s] + w01 * c.m[2][s] + w11 * c.m[3][s];
+      } else {
+        IM[0] = a.ibound;
+        IM[1] = IM[2] = IM[3] = T(0);
+      }
+      const T ph = s_phi[f];
+      const T tau = tau0 * ph;
+      const Coefs<T> cf = coefficients(tau);
+      // the forward update at O again (Eq. fsbez), instead of reading the stored I_O
+      T KIM[4], b[4], IO[4];
+      kprime_apply(eMv, rMv, IM, KIM);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        lam[s] = n00 * c.l[0][s] + n10 * c.l[1][s] + n01 * c.l[2][s] + n11 * c.l[3][s];
-    } else {
+        b[s] = cf.e * IM[s] - cf.psiM * KIM[s] + cf.omM * SMt[s] + cf.omO * SOt[s] +
+               cf.omC * cMt[s];
+      const StokesFreq<T> F = stokes_freq(KO, cf.psiO);
+      stokes_solve<1>(KO, F, b, IO);
+      // lambda_b = (1 + psi'_O K'_O)^-T lambda
+      T lb[4];
+      stokes_solve<-1>(KO, F, lam, lb);
+      T KIO[4];
+      kprime_apply(eOv, rOv, IO, KIO);
+      T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) lam[s] = c.l[0][s];
-    }
-    T IM[4];
-    if constexpr (HI) {
+      for (int s = 0; s < 4; ++s) {
+        gE += lb[s] * IM[s];
+        gPM -= lb[s] * KIM[s];
+        gPO -= lb[s] * KIO[s];
+        gOM += lb[s] * SMt[s];
+        gOO += lb[s] * SOt[s];
+        gOC += lb[s] * cMt[s];
+        aSM[s] += cf.omM * lb[s];
+        aSO[s] += cf.omO * lb[s];
+        aCM[s] += cf.omC * lb[s];
+      }
+      aT += ph * coef_tau_grad(cf, gE, gPM, gPO, gOM, gOO, gOC);
+      kprime_outer(cf.psiM, lb, IM, aKM);
+      kprime_outer(cf.psiO, lb, IO, aKO);
+      if (lo) {
+        // Lambda = (e - psi'_M K'_M)^T lambda_b
+        T KT[4];
+        kprime_apply(eMv, rMn, lb, KT);
+        T out[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        IM[s] = w00 * c.m[0][s] + w10 * c.m[1][s] + w01 * c.m[2][s] + w11 * c.m[3][s];
-    } else {
-      IM[0] = a.ibound;
-      IM[1] = IM[2] = IM[3] = T(0);
-    }
-    const T ph = s_phi[f];
-    const T tau = tau0 * ph;
-    const Coefs<T> cf = coefficients(tau);
-    // the forward update at O again (Eq. fsbez), instead of reading the stored I_O
-    T KIM[4], b[4], IO[4];
-    kprime_apply(eMv, rMv, IM, KIM);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-      b[s] = cf.e * IM[s] - cf.psiM * KIM[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
-    const StokesFreq<T> F = stokes_freq(KO, cf.psiO);
-    stokes_solve<1>(KO, F, b, IO);
-    // lambda_b = (1 + psi'_O K'_O)^-T lambda
-    T lb[4];
-    stokes_solve<-1>(KO, F, lam, lb);
-    T KIO[4];
-    kprime_apply(eOv, rOv, IO, KIO);
-    T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      gE += lb[s] * IM[s];
-      gPM -= lb[s] * KIM[s];
-      gPO -= lb[s] * KIO[s];
-      gOM += lb[s] * SMt[s];
-      gOO += lb[s] * SOt[s];
-      gOC += lb[s] * cMt[s];
-      aSM[s] += cf.omM * lb[s];
-      aSO[s] += cf.omO * lb[s];
-      aCM[s] += cf.omC * lb[s];
-    }
-    aT += ph * coef_tau_grad(cf, gE, gPM, gPO, gOM, gOO, gOC);
-    kprime_outer(cf.psiM, lb, IM, aKM);
-    kprime_outer(cf.psiO, lb, IO, aKO);
-    if (lo) {
-      // Lambda = (e - psi'_M K'_M)^T lambda_b
-      T KT[4];
-      kprime_apply(eMv, rMn, lb, KT);
-      T out[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) out[s] = cf.e * lb[s] - cf.psiM * KT[s];
-      store4(lo + fo, out);
-    }
+        for (int s = 0; s < 4; ++s) out[s] = cf.e * lb[s] - cf.psiM * KT[s];
+        store4(lo + fo, out);
+      }
     };
     if constexpr (sizeof(T) == 4) {
       Corners cA, cB;
