@@ -212,6 +212,7 @@ def main():
     import numpy as np
     import torch
     from paper_1307_4217_amd import inputs, porta
+    from paper_1307_4217_amd import schedule as schedule_mod
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
@@ -236,45 +237,32 @@ def main():
     ws_bytes = porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, opts)
     nh = hg.nray_up
     schedule = "shared" if args.no_adjoint else args.schedule
+    inter = None
     if schedule in ("auto", "interleaved"):
         # rays per range: checkpoints of every plane for them, plus the adjoint's
         # workspace beyond the sweep's, must fit beside what is already resident
         fixed = (2 * hg.nray_up * cfg.nfreq * cfg.npoints // cfg.nz * 4 * elem   # I_top, target
                  + 26 * cfg.npoints * (elem + 8) + ws_bytes)
         free = torch.cuda.mem_get_info()[0] - fixed - (8 << 30)
-        want = [args.range_rays] if args.range_rays > 0 else range(min(16, nh), 0, -1)
-        range_rays = 0
-        for n in want:
-            o = porta.options(ray_batch=n, block=args.block, xcd_remap=args.xcd_remap, ray_count=n)
-            need = (porta.checkpoint_size(hg, prec, 1, o)
-                    + max(0, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1, o)
-                          - ws_bytes))
-            if need <= free:
-                range_rays = n
-                break
+        range_rays = schedule_mod.fitting_range_rays(
+            hg, prec, free, ws_bytes, limit=args.range_rays or 16, block=args.block,
+            xcd_remap=args.xcd_remap)
         if range_rays:
             schedule = "interleaved"
         elif schedule == "interleaved":
-            sys.exit(f"the interleaved schedule needs more device memory than is free")
+            sys.exit("the interleaved schedule needs more device memory than is free")
         else:
             schedule = "shared"
     if schedule == "interleaved":
-        ranges = [(r, min(range_rays, nh - r)) for r in range(0, nh, range_rays)]
-        range_opts = [porta.options(ray_batch=range_rays, block=args.block,
-                                    xcd_remap=args.xcd_remap, ray_first=r, ray_count=n)
-                      for r, n in ranges]
-        down_opts = porta.options(ray_batch=args.ray_batch, block=args.block,
-                                  xcd_remap=args.xcd_remap, ray_first=nh, ray_count=nh)
-        # the sweep of a range and its adjoint run one after the other and share one
-        # workspace with the sweep of the downward rays
-        ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1,
-                                                      range_opts[0]),
-                       porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, range_opts[0]))
+        # one workspace for every sweep and adjoint call, checkpoints for one range
+        inter = schedule_mod.InterleavedSweep(hg, prec, range_rays, ray_batch=args.ray_batch,
+                                              block=args.block, xcd_remap=args.xcd_remap,
+                                              device=dev)
     elif not args.no_adjoint:
         # the sweep and the adjoint run one after the other and share one workspace
         ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
                                                       args.checkpoint_stride, adj_opts))
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ws = inter.workspace if inter else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ws_see = torch.empty(8 * ((cfg.npoints + 255) // 256) + 256, dtype=torch.uint8, device=dev)
     jkq = torch.empty((10, cfg.npoints), dtype=torch.float64, device=dev)
     itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=tdt, device=dev)
@@ -288,17 +276,15 @@ def main():
         tk, tp, te = t(tatm.kappa, tdt), t(tatm.propmat, tdt), t(tatm.emis, tdt)
         # swept with the launches of one step, so that a profile of the whole run holds
         # the step's mix of launch shapes
-        for o in (range_opts + [down_opts] if schedule == "interleaved" else [opts]):
+        for o in (inter.range_opts + [inter.down_opts] if inter else [opts]):
             porta.fs_sweep(hg, tk, tp, te, atm.i_bottom, atm.w2, prec=prec, want_jkq=False,
                            i_top=target, opts=o, workspace=ws)
         del tatm, tk, tp, te
         # 2 x target, so that the seed 2 (I_top - target) = lerp(I_top, 2 target, -1) is
         # one pass over I_top
         target2 = target.mul_(2.0)
-        if schedule == "interleaved":
-            # every plane of one range of upward rays, reused range after range
-            ckpt = torch.empty(porta.checkpoint_size(hg, prec, 1, range_opts[0]) + 256,
-                               dtype=torch.uint8, device=dev)
+        if inter:
+            ckpt = inter.checkpoints
         else:
             # the forward sweep of each step keeps the upward rays' checkpoint planes for
             # the adjoint, which then only recomputes the planes between checkpoints
@@ -308,7 +294,7 @@ def main():
         g_k, g_p, g_e = torch.empty_like(kappa), torch.empty_like(prop), torch.empty_like(emis)
         log(f"{schedule} schedule: sweep/adjoint workspace {ws.numel() / 1e9:.2f} GB, "
             f"checkpoints {ckpt.numel() / 1e9:.2f} GB "
-            + (f"(every plane of {range_rays} rays at a time)" if schedule == "interleaved"
+            + (f"(every plane of {inter.range_rays} rays at a time)" if inter
                else f"(stride {args.checkpoint_stride})"))
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -322,40 +308,35 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    class Mark:
+        """HIP events around one library call, on torch's current stream."""
+
+        def __init__(self, kind, marks):
+            self.kind, self.marks = kind, marks
+
+        def __enter__(self):
+            self.a = ev()
+            self.a.record()
+
+        def __exit__(self, *exc):
+            b = ev()
+            b.record()
+            self.marks.append((self.kind, self.a, b))
+
+    def seed_rows(r, n, rows):
+        # dL/dI_top of L = sum (I_top - target)^2 for these rows, in place
+        rows.lerp_(target2[r:r + n], -1.0)
+
     def step_interleaved(times):
-        # per step: [sweep ms, SEE ms, adjoint ms] from events around every call
         emis_cur = state["emis"]
         marks = []
         g_k.zero_(), g_p.zero_(), g_e.zero_()
-        for i, (r, n) in enumerate(ranges):
-            e = [ev() for _ in range(4)]
-            e[0].record()
-            porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
-                           accumulate=i > 0, i_top=itop, opts=range_opts[i], workspace=ws,
-                           checkpoints=ckpt, checkpoint_stride=1)
-            e[1].record()
-            # dL/dI_top of L = sum (I_top - target)^2 for this range's rows, in place
-            seed = itop[r:r + n].lerp_(target2[r:r + n], -1.0)
-            e[2].record()
-            porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, itop, atm.w2, prec=prec,
-                             checkpoint_stride=1, g_kappa=g_k, g_propmat=g_p, g_emis=g_e,
-                             opts=range_opts[i], workspace=ws_adj, checkpoints=ckpt)
-            e[3].record()
-            marks.append(("sweep", e[0], e[1]))
-            marks.append(("seed", e[1], e[2]))
-            marks.append(("adjoint", e[2], e[3]))
-            del seed
-        e = [ev() for _ in range(3)]
-        e[0].record()
-        porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
-                       accumulate=True, want_itop=False, opts=down_opts, workspace=ws)
-        e[1].record()
-        porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck, hanle,
-                         bhat, kappa=kappa, emis_out=state["emis_next"], prec=prec,
-                         s_new=state["s_new"], rc=rc, workspace=ws_see)
-        e[2].record()
-        marks.append(("sweep", e[0], e[1]))
-        marks.append(("see", e[1], e[2]))
+        inter.run(kappa, prop, emis_cur, atm.i_bottom, atm.w2, jkq, itop, seed_rows, g_k, g_p,
+                  g_e, timer=lambda kind: Mark(kind, marks))
+        with Mark("see", marks):
+            porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck,
+                             hanle, bhat, kappa=kappa, emis_out=state["emis_next"], prec=prec,
+                             s_new=state["s_new"], rc=rc, workspace=ws_see)
         state["s_old"], state["s_new"] = state["s_new"], state["s_old"]
         state["emis"], state["emis_next"] = state["emis_next"], state["emis"]
         times.append(marks)
@@ -423,8 +404,8 @@ def main():
     value = (cfg.updates + adj_updates) * args.steps / wall
 
     # every plane launch of the sweep kernel in one step: its rays and algorithmic bytes
-    if schedule == "interleaved":
-        shapes = [n for _, n in ranges] + [min(nrb, nh - r) for r in range(0, nh, nrb)]
+    if inter:
+        shapes = inter.launch_ray_counts()
     else:
         shapes = [min(nrb, nh - r) for r in range(0, nh, nrb)] * 2
     launches = (cfg.nz - 1) * len(shapes)
@@ -434,7 +415,7 @@ def main():
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
     kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
     workload = counter_workload(cfg, args.prec, schedule, nrb,
-                                range_rays if schedule == "interleaved" else 0)
+                                inter.range_rays if inter else 0)
     counters = (measured_counters(kname, workload) if args.block in (0, 256)
                 and args.xcd_remap == -1 else None)
     traffic = None if counters is None else counters["traffic_bytes_per_launch"]
@@ -447,7 +428,7 @@ def main():
     if adj:
         # the adjoint kernel beside it: its launches carry the ray ranges (or adjoint
         # batches); the calls also hold the gathers of the partials, so this is a floor
-        ashapes = ([n for _, n in ranges] if schedule == "interleaved" else
+        ashapes = ([n for _, n in inter.ranges] if inter else
                    [min(adj_opts.ray_batch or nh, nh - r)
                     for r in range(0, nh, adj_opts.ray_batch or nh)])
         alaunches = (cfg.nz - 1) * len(ashapes)
@@ -477,6 +458,7 @@ def main():
         del ws
         if adj:
             del ws_adj, ckpt
+        inter = None   # holds the workspace and checkpoints of the interleaved schedule
         torch.cuda.empty_cache()
         k64, p64, e64 = t(atm.kappa, torch.float64), t(atm.propmat, torch.float64), t(
             atm.emis, torch.float64)
@@ -523,8 +505,7 @@ def main():
                    "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
                    "ray_batch": nrb, "schedule": schedule,
                    "checkpoint_stride": 1 if schedule == "interleaved" else args.checkpoint_stride,
-                   "adjoint_ray_batch": (range_rays if schedule == "interleaved"
-                                         else adj_opts.ray_batch),
+                   "adjoint_ray_batch": (inter.range_rays if inter else adj_opts.ray_batch),
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -342,3 +342,45 @@ def test_adjoint_over_ray_ranges(prec):
         for a, b in zip(g, ref):
             err = float((a.double() - b.double()).abs().max()) / scale
             assert err <= tol, err
+
+
+@pytest.mark.parametrize("prec, range_rays", [(porta.F64, 3), (porta.F32, 5)])
+def test_interleaved_schedule_matches_separate_calls(prec, range_rays):
+    """schedule.InterleavedSweep (ranges of upward rays swept with every plane kept and
+    reversed at once, downward rays last) against one sweep of all rays and one adjoint
+    call: J, I_top before the seed, the seed rows handed to the callback, and the
+    gradients of L = sum (I_top - target)^2."""
+    torch = require_gpu()
+    from paper_1307_4217_amd import schedule
+    atm, q = tiny_case(prec, seed=33, nx=5, ny=4, nz=7)
+    case = Case(atm, q, prec)
+    hg = case.hg
+    ref_j, ref_t = case.sweep()
+    target = to_dev(ref_t * 0.9 + 0.01, case.dt)
+    seed_ref = 2 * (to_dev(ref_t, case.dt) - target)
+    g_ref = porta.fs_adjoint(hg, case.kappa, case.prop, case.emis, atm.i_bottom, seed_ref,
+                             atm.w2, prec=prec, checkpoint_stride=2)
+    inter = schedule.InterleavedSweep(hg, prec, range_rays, ray_batch=3)
+    jkq = torch.full((10, hg.N), float("nan"), dtype=torch.float64, device="cuda")
+    itop = torch.full(ref_t.shape, float("nan"), dtype=case.dt, device="cuda")
+    g = [torch.zeros_like(x) for x in g_ref]
+    seen = []
+
+    def seed(r, n, rows):
+        seen.append((r, n, rows.cpu().numpy().copy()))
+        rows.sub_(target[r:r + n]).mul_(2.0)
+
+    inter.run(case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2, jkq, itop, seed, *g)
+    torch.cuda.synchronize()
+    assert [(r, n) for r, n, _ in seen] == inter.ranges
+    assert sum(n for _, n in inter.ranges) == hg.nray_up
+    for r, n, rows in seen:
+        assert np.array_equal(rows, ref_t[r:r + n])
+    np.testing.assert_allclose(jkq.cpu().numpy(), ref_j, rtol=1e-13,
+                               atol=1e-15 * np.abs(ref_j).max())
+    np.testing.assert_allclose(itop.cpu().numpy(), seed_ref.cpu().numpy(), rtol=0, atol=0)
+    scale = max(float(x.abs().max()) for x in g_ref)
+    tol = 1e-13 if prec == porta.F64 else 2e-6
+    for a, b in zip(g, g_ref):
+        assert float((a.double() - b.double()).abs().max()) / scale <= tol
+    assert inter.launch_ray_counts() == [n for _, n in inter.ranges] + [3, 3, 2]
