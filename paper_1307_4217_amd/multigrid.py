@@ -248,6 +248,7 @@ def main(argv=None):
                              order=3 if args.cubic else 1)
     work = solver.fine_sweeps_per_cycle()
     t0 = time.perf_counter()
+    rc = None   # no cycle run (--cycles 0, e.g. to time Jacobi alone)
     for c in range(args.cycles):
         rc = float((solver.nested() if (args.nested and c == 0) else solver.vcycle()).item())
         print(json.dumps({"cycle": c + 1, "R_c": rc, "fine_sweeps": round(work * (c + 1), 2),
