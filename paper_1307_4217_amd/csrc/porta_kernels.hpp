@@ -1,7 +1,7 @@
 // porta_kernels.hpp -- HIP kernels of the forward path for gfx950: table
 // preparation, the plane step of the short-characteristics sweep, the
-// ray/frequency reduction of J^K_Q, the stand-alone J accumulation and the
-// statistical-equilibrium update.
+// ray/frequency reduction of J^K_Q and the stand-alone J accumulation (the
+// statistical-equilibrium update is in porta_see.hpp).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -355,7 +355,9 @@ def fs_adjoint(hg: HostGrid, kappa, propmat, emis, i_bottom, dl_ditop, w2=1.0, p
                interp=BILINEAR, checkpoint_stride=8, g_kappa=None, g_propmat=None, g_emis=None,
                opts=None, workspace=None, stream=None, checkpoints=None):
     """porta_fs_adjoint; gradients are added to g_* (allocated as zeros if None).
-    `checkpoints`: the buffer fs_sweep filled with the same stride, or None."""
+    `checkpoints`: the buffer fs_sweep filled with the same stride and ray range (its
+    size is passed along and checked), or None.  With a ray range in `opts` only its
+    upward rays are differentiated."""
     import torch
     dev = kappa.device
     if g_kappa is None:
