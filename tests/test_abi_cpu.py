@@ -258,3 +258,24 @@ def test_short_checkpoint_buffer_rejected():
         assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 1, 0, ob, d,
                                   d, need - 1, 3, d, d, d, d, 1 << 40, None) == -3
         assert b"checkpoint buffer" in L.porta_last_error()
+
+
+def test_interleaved_schedule_range_size():
+    """schedule.fitting_range_rays: the largest number of rays per range (up to the
+    limit) whose stride-1 checkpoints and extra adjoint workspace fit the budget."""
+    from paper_1307_4217_amd import schedule
+    hg = small_hg()
+    prec = porta.F32
+    base = porta.workspace_size(hg, prec, porta.WS_SWEEP, 1, porta.options(ray_batch=40))
+
+    def need(n):
+        o = porta.options(ray_batch=n, ray_count=n)
+        return (porta.checkpoint_size(hg, prec, 1, o)
+                + max(0, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT, 1, o) - base))
+
+    assert schedule.fitting_range_rays(hg, prec, 1 << 50, base) == 16
+    assert schedule.fitting_range_rays(hg, prec, 1 << 50, base, limit=100) == hg.nray_up
+    assert schedule.fitting_range_rays(hg, prec, need(1) - 1, base) == 0
+    for n in (1, 5, 11):
+        assert schedule.fitting_range_rays(hg, prec, need(n), base) == n
+        assert schedule.fitting_range_rays(hg, prec, need(n + 1) - 1, base) == n
