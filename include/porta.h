@@ -60,7 +60,9 @@ typedef enum {
   PORTA_EINVAL = -1,       /* invalid argument (shape, pointer, range) */
   PORTA_EUNSUPPORTED = -2, /* valid but not implemented combination */
   PORTA_ENOMEM = -3,       /* workspace smaller than porta_workspace_size() */
-  PORTA_EDEVICE = -4       /* a HIP call failed */
+  PORTA_EDEVICE = -4,      /* a HIP call failed */
+  PORTA_ENONFINITE = -5    /* opts->check_inputs: a transfer coefficient is not finite,
+                              or eta_I <= 0 somewhere */
 } porta_status;
 
 typedef enum { PORTA_F64 = 0, PORTA_F32 = 1 } porta_prec;   /* sweep precision */
@@ -145,6 +147,12 @@ typedef struct {
                                porta_fs_adjoint takes only their upward part; i_top and
                                dl_ditop keep the layout of all upward rays; checkpoints
                                hold only the upward rays of the range */
+  int32_t check_inputs;     /* 1: porta_fs_sweep and porta_fs_adjoint first check that every
+                               kappa is finite and > 0 and every propmat and emis entry is
+                               finite, returning PORTA_ENONFINITE before any other launch
+                               if not.  The check reads the fields once and waits on the
+                               stream for its result (so it cannot be captured in a HIP
+                               graph); 0 (default): no check, no wait */
 } porta_options;
 
 typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;

@@ -126,6 +126,8 @@ int validate_options(const porta_options* o) {
     return fail(PORTA_EINVAL, "stokes must be 0 or 4 (Stokes vector) or 1 (intensity only)");
   if (o->ray_count < 0 || o->ray_first < 0)
     return fail(PORTA_EINVAL, "ray_first and ray_count must be >= 0");
+  if (o->check_inputs != 0 && o->check_inputs != 1)
+    return fail(PORTA_EINVAL, "check_inputs must be 0 or 1");
   return PORTA_OK;
 }
 
@@ -167,6 +169,7 @@ struct Layout {
   size_t rays;      // RayConsts[nrays]
   size_t phiT;      // T[nfreq]
   size_t wn;        // double[nfreq]
+  size_t flag;      // int: result of the optional input check
   size_t end_tables;
   size_t stateA, stateB;   // sweep plane states
   size_t jpart;
@@ -188,6 +191,8 @@ Layout tables_layout(const porta_quad* q, int prec) {
   off = align_up(off + elem(prec) * q->nfreq);
   L.wn = off;
   off = align_up(off + sizeof(double) * q->nfreq);
+  L.flag = off;
+  off = align_up(off + sizeof(int));
   L.end_tables = off;
   L.total = off;
   return L;
@@ -288,6 +293,29 @@ int fill(double* p, size_t n, double v, hipStream_t st) {
   const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
   return check_launch("fill");
+}
+
+// The opt-in input check: one pass over the fields, then a wait on the stream for
+// its verdict.
+template <class T>
+int check_inputs(const porta_grid* g, const porta_fields* f, char* ws, const Layout& L,
+                 hipStream_t st) {
+  const size_t N = (size_t)g->nx * g->ny * g->nz;
+  int* flag = reinterpret_cast<int*>(ws + L.flag);
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, flag);
+  int rc;
+  if ((rc = check_launch("zero_flag"))) return rc;
+  const size_t blocks = std::min<size_t>((N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_check_fields<T>, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const T*>(f->kappa), static_cast<const T*>(f->propmat),
+                     static_cast<const T*>(f->emis), N, flag);
+  if ((rc = check_launch("check_fields"))) return rc;
+  int h = 0;
+  if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(PORTA_EDEVICE, "reading the input check failed");
+  if (h) return fail(PORTA_ENONFINITE, "a transfer coefficient is not finite, or eta_I <= 0");
+  return PORTA_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -574,6 +602,7 @@ const char* porta_strerror(int status) {
     case PORTA_EUNSUPPORTED: return "unsupported combination of arguments";
     case PORTA_ENOMEM: return "workspace too small";
     case PORTA_EDEVICE: return "HIP device error";
+    case PORTA_ENONFINITE: return "non-finite transfer coefficient or eta_I <= 0";
     default: return "unknown status";
   }
 }
@@ -650,6 +679,10 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
                 L.total);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
+  if (opts && opts->check_inputs &&
+      (rc = (prec == PORTA_F64) ? check_inputs<double>(grid, fields, ws, L, st)
+                                : check_inputs<float>(grid, fields, ws, L, st)))
+    return rc;
   if (prec == PORTA_F64)
     return sweep_impl<double>(grid, quad, fields, interp, opts, jkq, accumulate,
                               static_cast<double*>(i_top), static_cast<double*>(checkpoints),
@@ -731,6 +764,10 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
                 L.total);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
+  if (opts && opts->check_inputs &&
+      (rc = (prec == PORTA_F64) ? check_inputs<double>(grid, fields, ws, L, st)
+                                : check_inputs<float>(grid, fields, ws, L, st)))
+    return rc;
   if (prec == PORTA_F64)
     return adjoint_impl<double>(grid, quad, fields, opts, static_cast<const double*>(dl_ditop),
                                 static_cast<const double*>(checkpoints), checkpoint_stride,

@@ -32,6 +32,27 @@ __global__ void k_upload(const UploadChunk c) {
   if (t < c.n) c.dst[t] = c.v[t];
 }
 
+// Opt-in validity check of the transfer coefficients: flag[0] = 1 if some eta_I is
+// not finite or not > 0, or some propagation-matrix or emission entry is not finite.
+// Every writer stores the same value, so the unordered stores agree.
+__global__ void k_zero_flag(int* flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_check_fields(const T* __restrict__ kappa,
+                                                      const T* __restrict__ prop,
+                                                      const T* __restrict__ emis, size_t N,
+                                                      int* flag) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (size_t)gridDim.x * blockDim.x) {
+    bool bad = !(kappa[p] > T(0)) || !isfinite(kappa[p]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) bad = bad || !isfinite(prop[c * N + p]) || !isfinite(emis[c * N + p]);
+    if (bad) flag[0] = 1;
+  }
+}
+
 __global__ void k_fill_f64(double* __restrict__ p, size_t n, double v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)

@@ -279,3 +279,16 @@ def test_interleaved_schedule_range_size():
     for n in (1, 5, 11):
         assert schedule.fitting_range_rays(hg, prec, need(n), base) == n
         assert schedule.fitting_range_rays(hg, prec, need(n + 1) - 1, base) == n
+
+
+def test_check_inputs_option_is_validated():
+    L = porta.lib()
+    hg = small_hg()
+    d = np.zeros(8).ctypes.data
+    f = porta.Fields(d, d, d, 1.0, 1.0)
+    bad = porta.Options(0, 0, -1, 0, 4, 0, 0, 2)
+    assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, 0, C.byref(bad),
+                            d, 0, d, None, 0, 0, d, 1 << 40, None) == porta.EINVAL
+    assert b"check_inputs" in L.porta_last_error()
+    assert L.porta_strerror(porta.ENONFINITE).startswith(b"non-finite")
+    assert porta.options(check_inputs=True).check_inputs == 1

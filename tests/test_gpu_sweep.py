@@ -299,3 +299,44 @@ def test_ray_ranges_sum_to_the_full_sweep(prec):
                    i_top=itop2, want_jkq=False, opts=porta.options(ray_first=nh, ray_count=nh))
     torch.cuda.synchronize()
     assert torch.equal(itop, itop2)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_check_inputs_option(prec):
+    """opts.check_inputs: valid fields pass and give the unchecked result; a NaN
+    emissivity, an infinite propagation-matrix entry or eta_I <= 0 at one point make
+    the sweep and the adjoint return PORTA_ENONFINITE before any other launch; without
+    the option nothing is checked."""
+    torch = require_gpu()
+    atm, q, _ = oracle_full("C1", 0, "f64")
+    case = Case(atm, q, prec)
+    chk = porta.options(check_inputs=True)
+    j0, t0 = case.sweep()
+    j1, t1 = case.sweep(opts=chk)
+    assert np.array_equal(j0, j1) and np.array_equal(t0, t1)
+    seed = torch.ones_like(torch.as_tensor(t0, device="cuda"))
+    porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, seed, atm.w2,
+                     prec=prec, checkpoint_stride=4, opts=chk)
+    p = 1234
+    for name, field, value in (("emis", case.emis, float("nan")),
+                               ("propmat", case.prop, float("inf")),
+                               ("kappa", case.kappa, 0.0)):
+        saved = field.clone()
+        field.view(-1)[p] = value
+        for call in ("sweep", "adjoint"):
+            with pytest.raises(porta.PortaError) as err:
+                if call == "sweep":
+                    porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                   atm.w2, prec=prec, opts=chk)
+                else:
+                    porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                     seed, atm.w2, prec=prec, checkpoint_stride=4, opts=chk)
+            assert err.value.status == porta.ENONFINITE, (name, call)
+        if name == "emis":
+            # unchecked, the sweep runs and the NaN reaches J
+            j, _ = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                  atm.w2, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.isnan(j).any()
+        field.copy_(saved)
+    torch.cuda.synchronize()
