@@ -16,7 +16,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "porta_oracle.cpp")
-LIB = os.path.join(HERE, "liboracle.so")
+# PORTA_ORACLE_LIB names another build of the same source (the sanitizer test uses it)
+LIB = os.environ.get("PORTA_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lock = threading.Lock()
 _lib = None
