@@ -6,7 +6,13 @@ statistical-equilibrium update (porta_see_update) that rewrites the
 emissivities for the next sweep.  The convergence measure is
 R_c = max |dS00| / S00, read back once per iteration.
 
-    python -m paper_1307_4217_amd.jacobi --config C2 --prec f64 --iters 50
+The iterate (S^K_Q, the emissivities of the next sweep, the iteration count and
+the R_c history) can be saved and the iteration resumed from it: the paper's
+restart from a stored, partially converged solution (the radiation field itself
+is never stored).
+
+    python -m paper_1307_4217_amd.jacobi --config C2 --prec f64 --iters 50 [--save s.npz]
+    python -m paper_1307_4217_amd.jacobi --config C2 --prec f64 --iters 20 --resume s.npz
 """
 from __future__ import annotations
 
@@ -46,6 +52,7 @@ class JacobiSolver:
         self.ws_see = torch.empty(8 * ((atm.npoints + 255) // 256) + 256, dtype=torch.uint8,
                                   device=self.dev)
         self.iteration = 0
+        self.history = []
 
     @property
     def source(self):
@@ -71,11 +78,36 @@ class JacobiSolver:
         for _ in range(max_iter):
             rc = float(self.step().item())
             hist.append(rc)
+            self.history.append(rc)
             if callback:
                 callback(self.iteration, rc)
             if rc < tol:
                 break
         return hist
+
+    def save(self, path):
+        """Write the iterate to an .npz file: S^K_Q (FP64), the emissivities of the next
+        sweep (sweep precision), the iteration count, the R_c history and the shapes
+        it belongs to."""
+        a = self.atm
+        np.savez(path, source=self.S[0].cpu().numpy(), emis=self.emis.cpu().numpy(),
+                 iteration=self.iteration, history=np.asarray(self.history, dtype=np.float64),
+                 shape=np.asarray([a.nx, a.ny, a.nz, self.hg.nrays, self.hg.nfreq]),
+                 prec=self.prec)
+
+    def load(self, path):
+        """Resume from a file written by save() for the same grid, quadrature and
+        precision; the next step() continues the iteration exactly."""
+        with np.load(path, allow_pickle=False) as f:
+            a = self.atm
+            want = [a.nx, a.ny, a.nz, self.hg.nrays, self.hg.nfreq]
+            if list(f["shape"]) != want or int(f["prec"]) != self.prec:
+                raise ValueError(f"{path} holds an iterate of shape {list(f['shape'])} "
+                                 f"(prec {int(f['prec'])}), not {want} (prec {self.prec})")
+            self.S[0].copy_(self.torch.as_tensor(f["source"]))
+            self.emis.copy_(self.torch.as_tensor(f["emis"]))
+            self.iteration = int(f["iteration"])
+            self.history = [float(x) for x in f["history"]]
 
 
 def main(argv=None):
@@ -85,12 +117,16 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--ray-batch", type=int, default=0)
+    ap.add_argument("--save", default="", help="write the final iterate to this .npz file")
+    ap.add_argument("--resume", default="", help="start from an iterate written by --save")
     args = ap.parse_args(argv)
     cfg = inputs.CONFIGS[args.config]
     atm = inputs.make_atmosphere(cfg, seed=0)
     q = inputs.make_quadrature(cfg)
     prec = porta.F64 if args.prec == "f64" else porta.F32
     solver = JacobiSolver(atm, q, prec, opts=porta.options(ray_batch=args.ray_batch))
+    if args.resume:
+        solver.load(args.resume)
     t0 = time.perf_counter()
 
     def report(it, rc):
@@ -102,7 +138,10 @@ def main(argv=None):
                       "freqs": cfg.nfreq, "prec": args.prec, "iterations": len(hist),
                       "final_R_c": hist[-1], "converged": hist[-1] < args.tol,
                       "seconds": round(dt, 2),
-                      "updates_per_s": cfg.updates * len(hist) / dt}), flush=True)
+                      "updates_per_s": cfg.updates * len(hist) / dt,
+                      "total_iterations": solver.iteration}), flush=True)
+    if args.save:
+        solver.save(args.save)
     return 0
 
 

@@ -340,3 +340,33 @@ def test_check_inputs_option(prec):
             assert torch.isnan(j).any()
         field.copy_(saved)
     torch.cuda.synchronize()
+
+
+def test_jacobi_save_and_resume_is_exact(tmp_path):
+    """Six Jacobi iterations in one go equal three, a save to disk, a fresh solver
+    loading the file and three more: S^K_Q, emissivities and the R_c history bitwise
+    (the iteration is deterministic).  A file for another grid is refused."""
+    torch = require_gpu()
+    from paper_1307_4217_amd.jacobi import JacobiSolver
+    atm, q, _ = oracle_full("C1", 0, "f64")
+    for prec in (porta.F64, porta.F32):
+        a = JacobiSolver(atm, q, prec)
+        a.solve(6, tol=0.0)
+        b = JacobiSolver(atm, q, prec)
+        b.solve(3, tol=0.0)
+        path = str(tmp_path / f"it{prec}.npz")
+        b.save(path)
+        c = JacobiSolver(atm, q, prec)
+        c.load(path)
+        assert c.iteration == 3
+        c.solve(3, tol=0.0)
+        torch.cuda.synchronize()
+        assert torch.equal(a.source, c.source) and torch.equal(a.emis, c.emis)
+        assert a.history == c.history and c.iteration == 6
+    other = dataclasses.replace(atm, nx=atm.nx // 2, kappa=atm.kappa[: atm.npoints // 2],
+                                propmat=atm.propmat[:, : atm.npoints // 2],
+                                emis=atm.emis[:, : atm.npoints // 2],
+                                source=atm.source[:, : atm.npoints // 2],
+                                hanle=None, bhat=None)
+    with pytest.raises(ValueError):
+        JacobiSolver(other, q, porta.F32).load(path)
