@@ -505,7 +505,8 @@ def main():
                    "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
                    "ray_batch": nrb, "schedule": schedule,
                    "checkpoint_stride": 1 if schedule == "interleaved" else args.checkpoint_stride,
-                   "adjoint_ray_batch": (inter.range_rays if inter else adj_opts.ray_batch),
+                   "adjoint_ray_batch": range_rays if schedule == "interleaved"
+                   else adj_opts.ray_batch,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
