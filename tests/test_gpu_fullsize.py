@@ -249,3 +249,53 @@ def test_c5_fp32_against_fp64_first_iteration():
     assert ej < 2e-5
     assert es < 2e-5 / atm.eps_c
     assert rc32 == pytest.approx(rc64, rel=2e-5 / atm.eps_c)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_c3_variants_full_size_sampled_pairs(orc, prec):
+    """The forward variants at 256x256x128 (160 rays, 101 frequencies) on sampled
+    (ray, frequency) pairs over the whole top surface: the 9-point Bezier interpolation
+    (against the oracle's mode 1; in FP32 Q/I, U/I, V/I to 1e-7 on 99.9% of the outputs
+    and 1e-6 at most, the conditioning of that mode) and the intensity-only sweep
+    (against the oracle with K' = 0 and the K = 2 emission zero)."""
+    torch = require_gpu()
+    torch.cuda.empty_cache()
+    cfg = inputs.CONFIGS["C3"]
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    rays, freqs = [9, 66], [50]
+    case = Case(atm, q, prec)
+    # 9-point Bezier
+    _, itop = case.sweep(interp=porta.BEZIER2D, want_jkq=False, opts=porta.options(ray_batch=40))
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, interp=1), rays=rays, freqs=freqs,
+                       want_j=False)["itop"]
+    got = itop[rays][:, freqs]
+    if prec == porta.F64:
+        ei, ep = compare_stokes(got, ref, 1e-10, 1e-12, "C3 bezier2d")
+    else:
+        ei = float((np.abs(got[..., 0] - ref[..., 0]) / np.abs(ref[..., 0])).max())
+        assert ei <= 2e-5, ei
+        ep = 0.0
+        for s in (1, 2, 3):
+            d = np.abs(got[..., s] / got[..., 0] - ref[..., s] / ref[..., 0])
+            assert np.quantile(d, 0.999) <= 1e-7 and d.max() <= 1e-6, (s, d.max())
+            ep = max(ep, float(d.max()))
+    print(f"C3 {'FP32' if prec == porta.F32 else 'FP64'} 9-point Bezier: I {ei:.2e}, "
+          f"Q/I.. max {ep:.2e}")
+    del itop
+    # intensity only
+    _, it1 = case.sweep(want_jkq=False, opts=porta.options(ray_batch=40, stokes=1))
+    emis0 = atm.emis.copy()
+    emis0[1:] = 0.0
+    ref1 = orc.fs_sweep(orc.OracleProblem(dataclasses.replace(atm, propmat=0 * atm.propmat,
+                                                              emis=emis0), q),
+                        rays=rays, freqs=freqs, want_j=False)["itop"]
+    assert np.abs(ref1[..., 1:]).max() == 0.0
+    tol = 1e-10 if prec == porta.F64 else 2e-5
+    e1 = float((np.abs(it1[rays][:, freqs] - ref1[..., 0]) / np.abs(ref1[..., 0])).max())
+    print(f"C3 {'FP32' if prec == porta.F32 else 'FP64'} intensity only: I {e1:.2e}")
+    assert e1 <= tol
+    del case
+    torch.cuda.empty_cache()
