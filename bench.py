@@ -480,6 +480,35 @@ def main():
         extra["fp64_sweep_updates_per_s"] = cfg.updates / (ms64 * 1e-3)
         extra["fp32_over_fp64_rate"] = round(ms64 / sweep_ms, 3)
         log(f"FP64 sweep {ms64:.1f} ms")
+        if adj:
+            # FP64 adjoint on a range of 4 upward rays, reversed from the stride-1
+            # checkpoints of its own sweep (the interleaved schedule's pattern; every plane
+            # of 4 rays in FP64 is 107 GB at 256x256x128)
+            del ws64
+            torch.cuda.empty_cache()
+            o64 = porta.options(ray_batch=4, block=args.block, xcd_remap=args.xcd_remap,
+                                ray_first=0, ray_count=4)
+            ck64 = torch.empty(porta.checkpoint_size(hg, porta.F64, 1, o64) + 256,
+                               dtype=torch.uint8, device=dev)
+            porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64,
+                           want_jkq=False, i_top=it64, opts=o64, checkpoints=ck64,
+                           checkpoint_stride=1)
+            gk64 = torch.zeros_like(k64)
+            gp64, ge64 = torch.zeros_like(p64), torch.zeros_like(e64)
+            a, b = ev(), ev()
+            a.record()
+            porta.fs_adjoint(hg, k64, p64, e64, atm.i_bottom, it64, atm.w2, prec=porta.F64,
+                             checkpoint_stride=1, g_kappa=gk64, g_propmat=gp64, g_emis=ge64,
+                             opts=o64, checkpoints=ck64)
+            b.record()
+            torch.cuda.synchronize()
+            ms_a64 = a.elapsed_time(b)
+            upd_a64 = 4 * cfg.nfreq * cfg.npoints
+            extra["fp64_adjoint_updates_per_s"] = upd_a64 / (ms_a64 * 1e-3)
+            extra["fp64_adjoint_sample"] = (f"4 upward rays from stride-1 checkpoints: "
+                                            f"{ms_a64:.1f} ms")
+            log(f"FP64 adjoint (4 rays) {ms_a64:.1f} ms")
+            del ck64
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the workload ...")
