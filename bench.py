@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12   # unpacked FP32 VALU, lane instructions/s
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -438,12 +439,24 @@ def main():
         aname = f"k_adjoint_plane<{'float' if elem == 4 else 'double'}>"
         acounters = (measured_counters(aname, workload) if args.block in (0, 256)
                      and args.xcd_remap == -1 else None)
+        # The adjoint kernel is bound by its vector ALU: its rate is the VALU instructions
+        # of one launch (counted by rocprofv3 for this machine code) times 64 lanes over
+        # the live launch time, against the unpacked FP32 issue peak of the part (one
+        # lane instruction per lane per cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz);
+        # its HBM rate is reported beside it.
+        insts = None if acounters is None else acounters.get("sq_insts_valu_per_dispatch")
+        lane_rate = None if insts is None else insts * 64 / (alaunch_ms * 1e-3) / 1e12
         roofline_adjoint = {
-            "bound": "hbm", "kernel": aname,
-            "achieved": round(abytes / (alaunch_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(abytes / (alaunch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": None if acounters is None else acounters["traffic_bytes_per_launch"],
+            "bound": "alu", "kernel": aname,
+            "achieved": None if lane_rate is None else round(lane_rate, 2),
+            "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instructions/s",
+            "frac": None if lane_rate is None else round(lane_rate / VALU_PEAK_TLANE, 4),
             "valu_busy_pct": None if acounters is None else acounters.get("valu_busy_pct"),
+            "hbm": {"achieved": round(abytes / (alaunch_ms * 1e-3) / 1e9, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(abytes / (alaunch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "traffic": (None if acounters is None
+                                else acounters["traffic_bytes_per_launch"])},
             "call_ms_per_launch": round(alaunch_ms, 4), "bytes_per_launch": abytes}
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
              "seed_ms": round(sum(m["seed"] for m in per) / args.steps, 2),

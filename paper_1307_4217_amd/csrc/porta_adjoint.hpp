@@ -51,15 +51,26 @@ struct AdjArgs {
   T ibound;
 };
 
+// The bilinear form l^T K' x is linear in the six entries (e_Q, e_U, e_V, r_Q, r_U,
+// r_V) of K' (kprime_apply's layout); q[c] is its partial in entry c, so that
+// l^T K' x = sum_c entry_c q[c].
+template <class T>
+__device__ inline void kprime_forms(const T l[4], const T x[4], T q[6]) {
+  q[0] = l[0] * x[1] + l[1] * x[0];
+  q[1] = l[0] * x[2] + l[2] * x[0];
+  q[2] = l[0] * x[3] + l[3] * x[0];
+  q[3] = l[2] * x[3] - l[3] * x[2];
+  q[4] = l[3] * x[1] - l[1] * x[3];
+  q[5] = l[1] * x[2] - l[2] * x[1];
+}
+
 // Partials of b's K' I term: dL/d(e_Q, e_U, e_V, r_Q, r_U, r_V) of -psi lambda^T K' x.
 template <class T>
 __device__ inline void kprime_outer(T psi, const T l[4], const T x[4], T g[6]) {
-  g[0] -= psi * (l[0] * x[1] + l[1] * x[0]);
-  g[1] -= psi * (l[0] * x[2] + l[2] * x[0]);
-  g[2] -= psi * (l[0] * x[3] + l[3] * x[0]);
-  g[3] -= psi * (l[2] * x[3] - l[3] * x[2]);
-  g[4] -= psi * (l[3] * x[1] - l[1] * x[3]);
-  g[5] -= psi * (l[1] * x[2] - l[2] * x[1]);
+  T q[6];
+  kprime_forms(l, x, q);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) g[c] -= psi * q[c];
 }
 
 // FP32: two waves per SIMD (256 VGPRs), which leaves room for the loads of the next
@@ -180,14 +191,19 @@ k_adjoint_plane(const AdjArgs<T> a) {
       // lambda_b = (1 + psi'_O K'_O)^-T lambda
       T lb[4];
       stokes_solve<-1>(KO, F, lam, lb);
-      T KIO[4];
-      kprime_apply(eOv, rOv, IO, KIO);
-      T gE = 0, gPM = 0, gPO = 0, gOM = 0, gOO = 0, gOC = 0;
+      // lambda_b^T K'_O I_O is linear in the six entries of K'_O: its partials QO[c]
+      // give both the psi'_O term and the K'_O partials
+      T QO[6];
+      kprime_forms(lb, IO, QO);
+      T gPO = -(eOv[0] * QO[0] + eOv[1] * QO[1] + eOv[2] * QO[2] + rOv[0] * QO[3] +
+                rOv[1] * QO[4] + rOv[2] * QO[5]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) aKO[c] -= cf.psiO * QO[c];
+      T gE = 0, gPM = 0, gOM = 0, gOO = 0, gOC = 0;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         gE += lb[s] * IM[s];
         gPM -= lb[s] * KIM[s];
-        gPO -= lb[s] * KIO[s];
         gOM += lb[s] * SMt[s];
         gOO += lb[s] * SOt[s];
         gOC += lb[s] * cMt[s];
@@ -197,7 +213,6 @@ k_adjoint_plane(const AdjArgs<T> a) {
       }
       aT += ph * coef_tau_grad(cf, gE, gPM, gPO, gOM, gOO, gOC);
       kprime_outer(cf.psiM, lb, IM, aKM);
-      kprime_outer(cf.psiO, lb, IO, aKO);
       if (lo) {
         // Lambda = (e - psi'_M K'_M)^T lambda_b
         T KT[4];
