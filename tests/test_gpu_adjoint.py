@@ -5,7 +5,8 @@ import dataclasses
 import numpy as np
 import pytest
 
-from gpu_common import Case, require_gpu, rounded, to_dev
+from gpu_common import (Case, compare_jkq, compare_stokes, require_gpu, rounded, to_dev,
+                        up_rays)
 from paper_1307_4217_amd import inputs, porta
 
 pytestmark = pytest.mark.gpu
@@ -100,6 +101,34 @@ def test_adjoint_dot_product_c1(orc, prec, tol):
         got = np.sum(gk * v_k) + np.sum(gp * v_p) + np.sum(ge * v_e)
         ref = oracle_directional(orc, atm, q, w, v_k, v_p, v_e)
         assert got == pytest.approx(ref, rel=tol), (trial, got, ref)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_single_frequency_and_single_inclination(orc, prec):
+    """One frequency (the FP32 frequency loops take two per trip) and one inclination per
+    hemisphere (4 rays): the forward I_top and J, and the adjoint along random
+    directions, against the oracle."""
+    cfg = inputs.Config("one", 5, 4, 6, 1, 2, 1, True)
+    atm = dataclasses.replace(inputs.make_atmosphere(cfg, seed=21), lx=800.0, ly=600.0,
+                              z=np.linspace(0, 1200, 6))
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q))
+    case = Case(atm, q, prec)
+    jkq, itop = case.sweep()
+    tol_i, tol_p = (1e-10, 1e-12) if prec == porta.F64 else (2e-5, 1e-7)
+    compare_stokes(itop, up_rays(ref["itop"], q), tol_i, tol_p, "itop")
+    compare_jkq(jkq, ref["jkq"], tol_i, "jkq")
+    rng = np.random.default_rng(22)
+    w = seed_for(case, rng)
+    for stride in (1, 2):
+        g = gpu_grad(case, w, stride=stride)
+        v = [rng.normal(size=atm.npoints) * atm.kappa,
+             rng.normal(size=(6, atm.npoints)) * atm.kappa,
+             rng.normal(size=(6, atm.npoints)) * atm.emis.std(axis=1, keepdims=True)]
+        got = sum(np.sum(a * b) for a, b in zip(g, v))
+        assert got == pytest.approx(oracle_directional(orc, atm, q, w, *v), rel=tol_i), stride
 
 
 def test_adjoint_ragged_batches_and_strides(orc):
