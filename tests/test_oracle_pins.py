@@ -741,6 +741,58 @@ def test_see_vertical_field_and_destruction_limits(orc):
     np.testing.assert_array_equal(s3[1:], 0.0)
 
 
+def test_hanle_rotation_sense_against_the_classical_oscillator(orc):
+    """The sense and size of the Hanle rotation, pinned to classical electrodynamics
+    (the J = 0 -> 1 line with g = 1 is the damped electron oscillator).  A beam along +x
+    excites the dipole along y (its z part does not radiate towards +z); with B along +z
+    the Lorentz force on the electron, -e v x B, turns the oscillation plane about +z,
+    and the light scattered towards +z is the energy-weighted average over the decay
+    (rate A) of the rotating dipole direction.  The oracle's chain (J of the single beam
+    by Eq. 1 with its T^K_Q, the SEE with H_u = omega_L g / A, the emission towards +z)
+    must give the same Q and U in the frame e_a = x, e_b = y of the ray mu = 1, chi = 0
+    (Q > 0 along e_a, U > 0 along (e_a + e_b)/sqrt 2)."""
+    t_in = orc.tkq(0.0, 0.0)[0]            # T^K_Q(I, beam along +x): mu = 0, chi = 0
+    jkq = np.zeros((10, 1))
+    jkq[0, 0] = t_in[0].real
+    jkq[1, 0] = t_in[2].real                     # K = 1, Q = 0
+    jkq[2, 0], jkq[3, 0] = t_in[3].real, t_in[3].imag
+    jkq[4, 0] = t_in[6].real                     # K = 2, Q = 0
+    jkq[5, 0], jkq[6, 0] = t_in[7].real, t_in[7].imag
+    jkq[7, 0], jkq[8, 0] = t_in[8].real, t_in[8].imag
+    # direction in which the Lorentz force on a negative charge turns a velocity along y
+    # about B = +z, as a rotation sense about +z
+    force = -np.cross([0.0, 1.0, 0.0], [0.0, 0.0, 1.0])
+    sense = np.sign(np.cross([0.0, 1.0, 0.0], force)[2])
+    A = 1.0
+    res = {}
+    for H in (0.0, 0.1, 0.45, 1.7):
+        atm = types.SimpleNamespace(eps_c=0.0, delta2=0.0, w2=1.0, planck=1.0,
+                                    hanle=np.array([H]), bhat=np.array([[0.0], [0.0], [1.0]]),
+                                    kappa=np.ones(1))
+        s_new, _, _ = orc.see_update(jkq, np.ones((6, 1)), atm)
+        iquv = orc.emission(1.0, 0.0, s_new[:, 0], 1.0)
+        # classical: dipole direction (-sin wt, cos wt) for sense +1, energy weight e^-At
+        w = sense * H * A
+        dx = lambda t: -math.sin(w * t)
+        dy = lambda t: math.cos(w * t)
+        qc = quad(lambda t: math.exp(-A * t) * (dx(t) ** 2 - dy(t) ** 2), 0, 60, limit=400)[0]
+        uc = quad(lambda t: math.exp(-A * t) * 2 * dx(t) * dy(t), 0, 60, limit=400)[0]
+        res[H] = (iquv, qc, uc)
+        assert abs(iquv[3]) < 1e-15
+        if H == 0.0:
+            assert iquv[1] < 0 and abs(iquv[2]) < 1e-15     # polarized along e_b = y
+        # same polarization angle: U/Q
+        assert iquv[2] / iquv[1] == pytest.approx(uc / qc, rel=1e-9, abs=1e-12), H
+        assert uc / qc == pytest.approx(2 * H, rel=1e-9, abs=1e-12)
+    # the degree of polarization falls as cos(2 alpha), like the classical one
+    p0 = math.hypot(res[0.0][0][1], res[0.0][0][2])
+    c0 = math.hypot(res[0.0][1], res[0.0][2])
+    for H in (0.1, 0.45, 1.7):
+        iquv, qc, uc = res[H]
+        assert math.hypot(iquv[1], iquv[2]) / p0 == pytest.approx(math.hypot(qc, uc) / c0,
+                                                                  rel=1e-9)
+
+
 def test_see_rotational_covariance(orc):
     """Rotating radiation field and magnetic field by alpha about z rotates the atomic
     multipoles: J^2_Q -> e^{iQa} J^2_Q implies S^2_Q -> e^{-iQa} S^2_Q."""
