@@ -19,7 +19,7 @@ class PortaSweep(torch.autograd.Function):
                 keep_checkpoints):
         ck = None
         if keep_checkpoints:
-            n = porta.checkpoint_size(hg, prec, checkpoint_stride)
+            n = porta.checkpoint_size(hg, prec, checkpoint_stride, opts)
             ck = torch.empty(max(n, 256), dtype=torch.uint8, device=kappa.device)
         _, itop = porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec,
                                  want_jkq=False, opts=opts, checkpoints=ck,

@@ -271,6 +271,14 @@ def test_autograd_function_uses_the_adjoint(orc):
                                   checkpoint_stride=2)
     torch.cuda.synchronize()
     assert torch.equal(k.grad, gk) and torch.equal(pm.grad, gp) and torch.equal(e.grad, ge)
+    # the same with the forward sweep keeping the checkpoints for the backward pass
+    k2, pm2, e2 = (x.detach().clone().requires_grad_(True) for x in (k, pm, e))
+    itop2 = emergent_stokes(case.hg, k2, pm2, e2, atm.i_bottom, atm.w2, prec=porta.F64,
+                            checkpoint_stride=2, keep_checkpoints=True)
+    ((itop2 - target) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.equal(itop2, itop)
+    assert torch.equal(k2.grad, gk) and torch.equal(pm2.grad, gp) and torch.equal(e2.grad, ge)
     # the autograd gradient against complex-step derivatives of the oracle
     rng = np.random.default_rng(22)
     v = [rng.normal(size=atm.npoints), rng.normal(size=(6, atm.npoints)),
