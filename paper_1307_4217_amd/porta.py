@@ -56,7 +56,6 @@ class PortaError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn} failed with status {status}: {msg}")
         self.status = status
-        self.status = status
 
 
 _lock = threading.Lock()
