@@ -206,9 +206,9 @@ def cpu_baseline(cfg, atm, q, pairs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sweep would "
-              "shard by frequency across GPUs with one FP64 all-reduce of J per iteration, "
-              "which this build does not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "has no multi-GPU path (the sweep would shard by frequency across GPUs with one "
+              "FP64 all-reduce of J per iteration).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -292,3 +292,15 @@ def test_check_inputs_option_is_validated():
     assert b"check_inputs" in L.porta_last_error()
     assert L.porta_strerror(porta.ENONFINITE).startswith(b"non-finite")
     assert porta.options(check_inputs=True).check_inputs == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for several it exits at once with status 2 and
+    says why, before touching the GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
