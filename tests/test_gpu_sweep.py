@@ -52,6 +52,27 @@ def test_sweep_ragged_grid_batches_and_blocks(orc, prec, ray_batch, block):
     compare_jkq(jkq, ref["jkq"], tol_i, "jkq")
 
 
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+@pytest.mark.parametrize("scale", [1e-7, 1e3])
+def test_extreme_optical_depths(orc, prec, scale):
+    """The whole model scaled to optical steps of 1e-17..1e-2 (every coefficient from
+    its Taylor branch) or of up to 6e7 at line centre on the most inclined rays
+    (e^-tau underflows, I_O -> S_O): eta and eps scaled together, so the source
+    functions are unchanged."""
+    cfg = inputs.Config("ext", 6, 5, 8, 2, 3, 5, True)
+    atm = inputs.make_atmosphere(cfg, seed=14)
+    atm = dataclasses.replace(atm, kappa=atm.kappa * scale, propmat=atm.propmat * scale,
+                              emis=atm.emis * scale)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q))
+    jkq, itop = Case(atm, q, prec).sweep()
+    tol_i, tol_p = (1e-10, 1e-12) if prec == porta.F64 else (2e-5, 1e-7)
+    compare_stokes(itop, up_rays(ref["itop"], q), tol_i, tol_p, f"itop x{scale:g}")
+    compare_jkq(jkq, ref["jkq"], tol_i, f"jkq x{scale:g}")
+
+
 def test_single_plane_pair_and_single_column(orc):
     """Degenerate grids: nz = 2 (boundary + last plane only) and a 1x1 column."""
     for (nx, ny, nz) in ((4, 3, 2), (1, 1, 6)):
