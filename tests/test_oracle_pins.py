@@ -373,6 +373,41 @@ def test_j_of_isotropic_and_polynomial_fields(orc):
     np.testing.assert_allclose(J[[2, 3, 5, 6, 7, 8]], 0.0, atol=1e-15)
 
 
+def test_j_of_azimuthal_fields_every_q(orc):
+    """J^K_Q with Q != 0 (the slots Re/Im J11, J21, J22) from fields with cos/sin chi and
+    cos/sin 2chi dependence, against the integrals of Eq. 1 done by hand with the
+    textbook T^K_Q (Q along e_a, U along (e_a + e_b)/sqrt 2):
+      I = sin^2(th) cos 2chi -> J22 = sqrt3/15;   I = sin^2(th) sin 2chi -> Im J22 = sqrt3/15
+      I = mu sin(th) cos chi -> J21 = -sqrt3/30;  I = mu sin(th) sin chi -> Im J21 = -sqrt3/30
+      V = sin(th) cos chi -> J11 = -sqrt3/6;      V = sin(th) sin chi -> Im J11 = -sqrt3/6
+      Q = cos 2chi -> J22 = -sqrt3/6;             U = mu sin 2chi -> J22 = sqrt3/12
+    (5 Gauss inclinations per hemisphere and 8 azimuths integrate all of them exactly)."""
+    mu, w = gl_hemi(5)
+    q = mk_quad(mu, w, 8, phi=[0.2, 1.0, 0.2], wfreq=[0.5, 1.0, 0.5])
+    atm = mk_atm(2, 2, 2, 1, 1, [0, 1], np.ones(8))
+    op = orc.OracleProblem(atm, q)
+    rt = orc.ray_table(op)
+    r3 = math.sqrt(3.0)
+    cases = [  # (Stokes index, field(mu, sin theta, chi), slot, expected)
+        (0, lambda m, s, c: s * s * math.cos(2 * c), 7, r3 / 15),
+        (0, lambda m, s, c: s * s * math.sin(2 * c), 8, r3 / 15),
+        (0, lambda m, s, c: m * s * math.cos(c), 5, -r3 / 30),
+        (0, lambda m, s, c: m * s * math.sin(c), 6, -r3 / 30),
+        (3, lambda m, s, c: s * math.cos(c), 2, -r3 / 6),
+        (3, lambda m, s, c: s * math.sin(c), 3, -r3 / 6),
+        (1, lambda m, s, c: math.cos(2 * c), 7, -r3 / 6),
+        (2, lambda m, s, c: m * math.sin(2 * c), 7, r3 / 12),
+    ]
+    for i, field, slot, expect in cases:
+        st = np.zeros((op.nrays, 3, 8, 4))
+        for r, (m, chi, _) in enumerate(rt):
+            st[r, :, :, i] = field(m, math.sqrt(1 - m * m), chi)
+        J = orc.jkq_accumulate(op, 0, 0, st)
+        np.testing.assert_allclose(J[slot], expect, rtol=1e-13, err_msg=f"{i} {slot}")
+        others = [c for c in range(9) if c != slot]
+        np.testing.assert_allclose(J[others], 0.0, atol=1e-15, err_msg=f"{i} {slot}")
+
+
 # --------------------------------------------------------------------------- P3 slabs
 def test_homogeneous_slab_closed_form(orc):
     nz = 12
