@@ -828,6 +828,32 @@ def test_hanle_rotation_sense_against_the_classical_oscillator(orc):
                                                                   rel=1e-9)
 
 
+def test_scattered_light_is_polarized_across_the_scattering_plane(orc):
+    """Dipole scattering at 90 degrees with no field: a beam in the horizontal plane at
+    azimuth chi_b, scattered towards +z, is linearly polarized perpendicular to the
+    scattering plane, i.e. along (-sin chi_b, cos chi_b, 0), at the angle chi_b + 90
+    degrees from e_a = x (Q proportional to -cos 2 chi_b, U to -sin 2 chi_b).  With beams
+    off the axes J^2_2 is complex, so this also fixes the conjugation of J^2_Q on the
+    right-hand side of the SEE."""
+    for chi_b in (0.0, 0.5236, 0.7854, 1.7453, 2.9):
+        t_in = orc.tkq(0.0, chi_b)[0]
+        jkq = np.zeros((10, 1))
+        jkq[0, 0] = t_in[0].real
+        jkq[1, 0] = t_in[2].real
+        jkq[2, 0], jkq[3, 0] = t_in[3].real, t_in[3].imag
+        jkq[4, 0] = t_in[6].real
+        jkq[5, 0], jkq[6, 0] = t_in[7].real, t_in[7].imag
+        jkq[7, 0], jkq[8, 0] = t_in[8].real, t_in[8].imag
+        atm = types.SimpleNamespace(eps_c=0.0, delta2=0.0, w2=1.0, planck=1.0, hanle=None,
+                                    bhat=None, kappa=np.ones(1))
+        s_new, _, _ = orc.see_update(jkq, np.ones((6, 1)), atm)
+        i, qq, u, v = orc.emission(1.0, 0.0, s_new[:, 0], 1.0)
+        p = math.hypot(qq, u)
+        assert p > 0.1 * i and abs(v) < 1e-15
+        np.testing.assert_allclose([qq / p, u / p], [-math.cos(2 * chi_b), -math.sin(2 * chi_b)],
+                                   atol=1e-12, err_msg=f"chi_b {chi_b}")
+
+
 def test_see_rotational_covariance(orc):
     """Rotating radiation field and magnetic field by alpha about z rotates the atomic
     multipoles: J^2_Q -> e^{iQa} J^2_Q implies S^2_Q -> e^{-iQa} S^2_Q."""
