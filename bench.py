@@ -56,6 +56,15 @@ def parse():
                     help="upward rays per range of the interleaved schedule (0: the most, up "
                          "to 16, whose checkpoints fit)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--interp", default="bilinear", choices=["bilinear", "bezier2d"],
+                    help="upwind/downwind interpolation (bezier2d: the 9-point monotonic "
+                         "Bezier; sweep only, with --no-adjoint)")
+    ap.add_argument("--stokes", type=int, default=4, choices=[4, 1],
+                    help="4: Stokes-vector transfer; 1: the unpolarized (intensity-only) "
+                         "problem (sweep only, with --no-adjoint)")
+    ap.add_argument("--control", default="besser", choices=["besser", "parabolic"],
+                    help="control point of the Bezier step: BESSER or the parabolic "
+                         "(DELOPAR) rule (sweep only, with --no-adjoint)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1,
                     help="row tiles per XCD per round (-1: the library default)")
@@ -69,14 +78,14 @@ def parse():
     return ap.parse_args()
 
 
-def sweep_launch_bytes(cfg, nrb, elem):
+def sweep_launch_bytes(cfg, nrb, elem, nst=4):
     """Algorithmic HBM bytes of one plane launch of the sweep kernel: the upwind
-    Stokes vector read and the new one written per update, three planes of the
-    13 transfer coefficients, and the FP64 read-modify-write of the 10 J values
-    of the previous plane."""
+    Stokes vector (nst components) read and the new one written per update, three
+    planes of the 13 transfer coefficients, and the FP64 read-modify-write of the 10 J
+    values of the previous plane."""
     np_ = cfg.nx * cfg.ny
     updates = nrb * cfg.nfreq * np_
-    return updates * 8 * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
+    return updates * 2 * nst * elem + 3 * np_ * 13 * elem + np_ * 10 * 8 * 2, updates
 
 
 def adjoint_launch_bytes(cfg, nrb, elem):
@@ -231,7 +240,14 @@ def main():
                                                           device=dev)
     hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
-    opts = porta.options(ray_batch=args.ray_batch, block=args.block, xcd_remap=args.xcd_remap)
+    variant = (args.interp != "bilinear" or args.stokes != 4 or args.control != "besser")
+    if variant and not args.no_adjoint:
+        sys.exit("--interp, --stokes and --control time the sweep alone: add --no-adjoint")
+    interp = porta.BEZIER2D if args.interp == "bezier2d" else porta.BILINEAR
+    control = porta.CONTROL_PARABOLIC if args.control == "parabolic" else porta.CONTROL_BESSER
+    nst = args.stokes
+    opts = porta.options(ray_batch=args.ray_batch, block=args.block, xcd_remap=args.xcd_remap,
+                         control=control, stokes=nst)
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
     adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block,
                              xcd_remap=args.xcd_remap)
@@ -266,7 +282,8 @@ def main():
     ws = inter.workspace if inter else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ws_see = torch.empty(8 * ((cfg.npoints + 255) // 256) + 256, dtype=torch.uint8, device=dev)
     jkq = torch.empty((10, cfg.npoints), dtype=torch.float64, device=dev)
-    itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=tdt, device=dev)
+    itop = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx) + ((4,) if nst == 4 else ()),
+                       dtype=tdt, device=dev)
     rc = torch.empty((), dtype=torch.float64, device=dev)
     log(f"workspace {ws.numel() / 1e9:.2f} GB, i_top {itop.numel() * elem / 1e9:.2f} GB")
     adj = not args.no_adjoint
@@ -348,8 +365,8 @@ def main():
         e = [ev() for _ in range(5)]
         emis_cur = state["emis"]
         e[0].record()
-        porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec, jkq=jkq,
-                       i_top=itop, opts=opts, workspace=ws,
+        porta.fs_sweep(hg, kappa, prop, emis_cur, atm.i_bottom, atm.w2, prec=prec,
+                       interp=interp, jkq=jkq, i_top=itop, opts=opts, workspace=ws,
                        checkpoints=ckpt if adj else None,
                        checkpoint_stride=args.checkpoint_stride if adj else 0)
         e[1].record()
@@ -410,11 +427,14 @@ def main():
     else:
         shapes = [min(nrb, nh - r) for r in range(0, nh, nrb)] * 2
     launches = (cfg.nz - 1) * len(shapes)
-    lbytes = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, elem)[0] for n in shapes) / launches
+    lbytes = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, elem, nst)[0]
+                                for n in shapes) / launches
     lupd = cfg.updates / launches
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
-    kname = f"k_sweep_plane<{'float' if elem == 4 else 'double'}, 0>"
+    tname = "float" if elem == 4 else "double"
+    kname = (f"k_sweep_plane_i<{tname}>" if nst == 1 else
+             f"k_sweep_plane<{tname}, {1 if interp == porta.BEZIER2D else 0}>")
     workload = counter_workload(cfg, args.prec, schedule, nrb,
                                 inter.range_rays if inter else 0)
     counters = (measured_counters(kname, workload) if args.block in (0, 256)
@@ -479,13 +499,13 @@ def main():
                            dtype=torch.uint8, device=dev)
         it64 = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=torch.float64,
                            device=dev)
-        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, jkq=jkq,
-                       i_top=it64, opts=opts, workspace=ws64)
+        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, interp=interp,
+                       jkq=jkq, i_top=it64, opts=opts, workspace=ws64)
         torch.cuda.synchronize()
         a, b = ev(), ev()
         a.record()
-        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, jkq=jkq,
-                       i_top=it64, opts=opts, workspace=ws64)
+        porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, interp=interp,
+                       jkq=jkq, i_top=it64, opts=opts, workspace=ws64)
         b.record()
         torch.cuda.synchronize()
         ms64 = a.elapsed_time(b)
@@ -542,7 +562,12 @@ def main():
         "data": "synthetic (seeded two-level atmosphere with the paper's box geometry)",
         "config": {"workload": f"{cfg.nx}x{cfg.ny}x{cfg.nz} grid, {cfg.nrays} rays, "
                                f"{cfg.nfreq} freqs: Jacobi step (sweep+J+SEE)"
-                               + (" + adjoint of the emergent-Stokes loss" if adj else ""),
+                               + (" + adjoint of the emergent-Stokes loss" if adj else "")
+                               + "".join(f", {v}" for v, on in (
+                                   ("9-point Bezier interpolation", interp == porta.BEZIER2D),
+                                   ("unpolarized (intensity only)", nst == 1),
+                                   ("parabolic control point", args.control == "parabolic"))
+                                   if on),
                    "updates_per_step": cfg.updates + adj_updates,
                    "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
                    "ray_batch": nrb, "schedule": schedule,
