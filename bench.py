@@ -27,6 +27,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12   # unpacked FP32 VALU, lane instructions/s
+# kernels whose rocprofv3 VALU-busy figure shows them bound by the vector ALU rather than
+# by HBM (the 9-point Bezier sweep, 78% busy at 3.2 TB/s); the others are reported
+# against HBM
+ALU_BOUND_KERNELS = ("k_sweep_plane<float, 1>",)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -103,6 +107,8 @@ KERNEL_SYMBOLS = {
     "k_sweep_plane<double, 0>": "_ZN5porta13k_sweep_planeIdLi0EEEvNS_9PlaneArgsIT_EE",
     "k_adjoint_plane<float>": "_ZN5porta15k_adjoint_planeIfEEvNS_7AdjArgsIT_EE",
     "k_adjoint_gather<float>": "_ZN5porta16k_adjoint_gatherIfEEvNS_10GatherArgsIT_EE",
+    "k_sweep_plane<float, 1>": "_ZN5porta13k_sweep_planeIfLi1EEEvNS_9PlaneArgsIT_EE",
+    "k_sweep_plane_i<float>": "_ZN5porta15k_sweep_plane_iIfEEvNS_9PlaneArgsIT_EE",
 }
 
 
@@ -446,6 +452,15 @@ def main():
                 "valu_busy_pct": None if counters is None else counters.get("valu_busy_pct"),
                 "launch_ms": round(launch_ms, 4), "bytes_per_launch": lbytes,
                 "updates_per_launch": lupd}
+    if kname in ALU_BOUND_KERNELS:
+        # measured VALU-bound: the rate against the VALU issue peak, HBM beside it
+        insts = None if counters is None else counters.get("sq_insts_valu_per_dispatch")
+        lane = None if insts is None else insts * 64 / (launch_ms * 1e-3) / 1e12
+        roofline.update({"bound": "alu", "achieved": None if lane is None else round(lane, 2),
+                         "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instructions/s",
+                         "frac": None if lane is None else round(lane / VALU_PEAK_TLANE, 4),
+                         "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}})
     if adj:
         # the adjoint kernel beside it: its launches carry the ray ranges (or adjoint
         # batches); the calls also hold the gathers of the partials, so this is a floor
