@@ -527,6 +527,22 @@ def main():
         extra["fp64_sweep_ms"] = round(ms64, 2)
         extra["fp64_sweep_updates_per_s"] = cfg.updates / (ms64 * 1e-3)
         extra["fp32_over_fp64_rate"] = round(ms64 / sweep_ms, 3)
+        # the FP64 sweep kernel against HBM: its launches (ray batches of `nrb`), their
+        # algorithmic bytes and, where committed, its counters
+        shapes64 = [min(nrb, nh - r) for r in range(0, nh, nrb)] * 2
+        n64 = (cfg.nz - 1) * len(shapes64)
+        b64 = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, 8, nst)[0] for n in shapes64) / n64
+        a64 = b64 / (ms64 / n64 * 1e-3) / 1e9
+        k64name = ("k_sweep_plane_i<double>" if nst == 1 else
+                   f"k_sweep_plane<double, {1 if interp == porta.BEZIER2D else 0}>")
+        c64 = (measured_counters(k64name, counter_workload(cfg, "f64", "shared", nrb, 0))
+               if args.block in (0, 256) and args.xcd_remap == -1 else None)
+        extra["fp64_roofline"] = {
+            "bound": "hbm", "kernel": k64name, "achieved": round(a64, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(a64 / HBM_PEAK_GBS, 4),
+            "traffic": None if c64 is None else c64["traffic_bytes_per_launch"],
+            "valu_busy_pct": None if c64 is None else c64.get("valu_busy_pct"),
+            "launch_ms": round(ms64 / n64, 4), "bytes_per_launch": b64}
         log(f"FP64 sweep {ms64:.1f} ms")
         if adj:
             # FP64 adjoint on a range of 4 upward rays, reversed from the stride-1
