@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (IEEE double, no fast-math)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", SRC, "-o", tmp])
         os.replace(tmp, LIB)
     return LIB
@@ -57,6 +57,8 @@ def lib():
             L.oracle_fs_sweep_cs.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, _dp, _dp,
                                              C.c_double, C.c_int, _ip, C.c_int, _ip, _dp, _dp,
                                              C.c_int]
+            L.oracle_fs_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int, _ip,
+                                            C.c_int, _ip, _dp, _dp, _dp, _dp, C.c_int]
             L.oracle_lc_sweep.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int, _ip,
                                           C.c_int, _ip, _dp]
             L.oracle_jkq_accumulate.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, C.c_int,
@@ -182,6 +184,26 @@ def fs_sweep_cs(op: OracleProblem, dkappa, dprop, demis, h=1e-30, rays=None, fre
     if rc != 0:
         raise ValueError("oracle_fs_sweep_cs rejected its inputs")
     return re, im
+
+
+def fs_adjoint(op: OracleProblem, seed, rays=None, freqs=None, nthreads: int = 0):
+    """Reverse-mode gradient of L = sum(seed * I_top) over the selected upward rays and
+    frequencies; seed [nr][nf][ny][nx][4].  Returns (g_kappa [N], g_prop [6][N],
+    g_emis [6][N])."""
+    L = lib()
+    rays = np.arange(op.nrays // 2, dtype=np.int32) if rays is None else np.asarray(rays, np.int32)
+    freqs = np.arange(op.nfreq, dtype=np.int32) if freqs is None else np.asarray(freqs, np.int32)
+    seed = _f64(seed)
+    if seed.shape != (len(rays), len(freqs), op.ny, op.nx, 4):
+        raise ValueError(f"seed shape {seed.shape} does not match the selection")
+    gk, gp, ge = np.zeros(op.N), np.zeros((6, op.N)), np.zeros((6, op.N))
+    rc = L.oracle_fs_adjoint(C.byref(op.struct), _d(op.kappa), _d(op.prop), _d(op.emis),
+                             len(rays), rays.ctypes.data_as(_ip), len(freqs),
+                             freqs.ctypes.data_as(_ip), _d(seed), _d(gk), _d(gp), _d(ge),
+                             int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_fs_adjoint rejected its inputs")
+    return gk, gp, ge
 
 
 def lc_sweep(op: OracleProblem, rays, freqs):

@@ -18,7 +18,10 @@
  *     J_l = 0 -> J_u = 1 atom with Hanle rotation (Sect. 2, Eq. nonlte;
  *     Sect. 5 for the Jacobi scheme and the convergence measure R_c);
  *   - long characteristics along the same rays (brute force check);
- *   - complex-step directional derivatives of the emergent Stokes vector.
+ *   - complex-step directional derivatives of the emergent Stokes vector;
+ *   - the reverse-mode gradient of a loss on the emergent Stokes vector with
+ *     respect to every transfer coefficient (recorded node updates, walked
+ *     backward plane by plane).
  *
  * Readings where the paper is silent (same numbering as the design notes):
  *   A1 M and P always lie on the neighbouring horizontal grid planes.
@@ -61,9 +64,10 @@ template <class T>
 struct Cx {
   T re, im;
 };
+/* Real part of the product a b. */
 template <class T>
-inline Cx<T> cmul(const Cx<double>& a, const Cx<T>& b) {
-  return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+inline T cmul_re(const Cx<double>& a, const Cx<T>& b) {
+  return a.re * b.re - a.im * b.im;
 }
 
 /* -------------------------------------------------------------------------- */
@@ -170,9 +174,10 @@ constexpr double kThreshPsi = 0.10;     // reading A6
 
 template <class T>
 Coef<T> coefficients(const T& tau) {
+  using std::exp;
   Coef<T> c;
   const double t = rp(tau);
-  c.e = std::exp(-tau);
+  c.e = exp(-tau);
   /* at tau = 0 the series branch gives e = 1 and all other coefficients 0 */
   const T t2 = tau * tau;
   /* Taylor series about tau = 0, 8 terms each, n = 0..7 */
@@ -329,7 +334,8 @@ T emission(const Cx<double> t[4][9], int i, const T e[6], double w2) {
   for (int K = 0; K <= 2; ++K)
     for (int Q = -K; Q <= K; ++Q) {
       const double wk = (K == 0) ? 1.0 : (K == 2 ? w2 : 0.0);
-      sum += wk * cmul(t[i][kq(K, Q)], ek[kq(K, Q)]).re;
+      if (wk == 0.0) continue;
+      sum += wk * cmul_re(t[i][kq(K, Q)], ek[kq(K, Q)]);
     }
   return sum;
 }
@@ -376,104 +382,186 @@ struct FieldsT {
   const T* emis;   // [6][N]
 };
 
-/* Formal solution for one ray and one frequency over the whole grid.
- * Writes I ([4][N], one Stokes component after the other) and Lambda* (N). */
+/* One step of the formal solution: the Stokes vector at node O = (i, j) of plane k
+ * of the ray, from the upwind plane k - s already held in I ([4][N], one Stokes
+ * component after the other).  Writes I_O into I and, if lam is given, Lambda* at O. */
 template <class T>
-void sweep_one(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray, int jf,
-               T* I, double* lam) {
+void node_update(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray,
+                 const Cx<double> t[4][9], double phi, int k, int i, int j, T* I, double* lam) {
   const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
   const size_t np = (size_t)nx * ny;
   const size_t N = np * nz;
   const double dx = pb.lx / nx, dy = pb.ly / ny;
-  const double phi = pb.phi[jf];
-  Cx<double> t[4][9];
-  tkq(ray.mu, ray.chi, t);
   const int s = ray.up ? 1 : -1;
-  const int kb = ray.up ? 0 : nz - 1;   // boundary plane
-  /* boundary condition */
+  const int kup = k - s, kdn = k + s;
+  const bool hasP = (kdn >= 0 && kdn < nz);
+  const double dsM = (pb.z[k] - pb.z[kup]) / ray.mu;
+  const double dsP = hasP ? (pb.z[kdn] - pb.z[k]) / ray.mu : 0.0;
+  const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+  /* M on the upwind plane, P on the downwind plane (reading A1) */
+  const double fxM = i - dsM * ray.sx / dx, fyM = j - dsM * ray.sy / dy;
+  const double fxP = i + dsP * ray.sx / dx, fyP = j + dsP * ray.sy / dy;
+  auto atM = [&](const T* arr) {
+    return interp_plane(arr + (size_t)kup * np, nx, ny, fxM, fyM, pb.interp);
+  };
+  auto atP = [&](const T* arr) {
+    return interp_plane(arr + (size_t)kdn * np, nx, ny, fxP, fyP, pb.interp);
+  };
+  /* absorption and emission at M, O, P (reading A3) */
+  T kapM = atM(f.kappa), kapO = f.kappa[pO], kapP(0.0);
+  T etaM[6], etaO[6], epsM[6], epsO[6], epsP[6];
+  for (int c = 0; c < 6; ++c) {
+    etaM[c] = atM(f.prop + c * N);
+    etaO[c] = f.prop[c * N + pO];
+    epsM[c] = atM(f.emis + c * N);
+    epsO[c] = f.emis[c * N + pO];
+    epsP[c] = T(0.0);
+  }
+  if (hasP) {
+    kapP = atP(f.kappa);
+    for (int c = 0; c < 6; ++c) epsP[c] = atP(f.emis + c * N);
+  }
+  /* Stokes vector at M, interpolated from the upwind plane */
+  T IM[4];
+  for (int st = 0; st < 4; ++st) IM[st] = atM(I + st * N);
+  /* monochromatic coefficients: eta_I(nu) = kappa * phi, eps(nu) = eps * phi */
+  const T etaIM = kapM * phi, etaIO = kapO * phi, etaIP = kapP * phi;
+  T eM[6], eO[6], eP[6], nM[6], nO[6];
+  for (int c = 0; c < 6; ++c) {
+    eM[c] = epsM[c] * phi; eO[c] = epsO[c] * phi; eP[c] = epsP[c] * phi;
+    nM[c] = etaM[c] * phi; nO[c] = etaO[c] * phi;
+  }
+  /* optical paths (reading A4) */
+  const T tauMO = 0.5 * (etaIM + etaIO) * std::fabs(dsM);
+  const T tauOP = 0.5 * (etaIO + etaIP) * std::fabs(dsP);
+  /* source vectors S = eps / eta_I */
+  T SM[4], SO[4], SP[4], cM[4];
+  for (int st = 0; st < 4; ++st) {
+    SM[st] = emission(t, st, eM, pb.w2) / etaIM;
+    SO[st] = emission(t, st, eO, pb.w2) / etaIO;
+    SP[st] = hasP ? emission(t, st, eP, pb.w2) / etaIP : T(0.0);
+    cM[st] = hasP ? control_point(pb.control, SM[st], SO[st], SP[st], tauMO, tauOP)
+                  : 0.5 * (SM[st] + SO[st]);   // reading A5
+  }
+  T KM[4][4], KO[4][4];
+  kprime(nM, etaIM, KM);
+  kprime(nO, etaIO, KO);
+  const Coef<T> cf = coefficients(tauMO);
+  /* Eq. fsbez right-hand side */
+  T b[4];
+  for (int a = 0; a < 4; ++a) {
+    T acc = cf.e * IM[a];
+    for (int c = 0; c < 4; ++c) acc -= cf.psiM * KM[a][c] * IM[c];
+    acc += cf.omM * SM[a] + cf.omO * SO[a] + cf.omC * cM[a];
+    b[a] = acc;
+  }
+  /* Eq. kappa: kappa^{-1} = 1 + psi'_O K'_O; solve kappa^{-1} I_O = b */
+  T A[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) A[a][c] = (a == c ? T(1.0) : T(0.0)) + cf.psiO * KO[a][c];
+  T IO[4];
+  gauss_solve<T, 4>(A, b, IO);
+  for (int st = 0; st < 4; ++st) I[st * N + pO] = IO[st];
+  /* Eq. 14: I_O for S_O = 1 and zero elsewhere; the unit source is a local
+   * maximum (c_M = 1) except on the last plane, where reading A5 gives c_M = 1/2 */
+  if (lam) lam[pO] = rp(cf.omO + (hasP ? 1.0 : 0.5) * cf.omC);
+}
+
+/* Boundary plane of a ray (entering intensity; Lambda* = 0 there). */
+template <class T>
+void boundary_plane(const oracle_problem& pb, const Ray& ray, T* I, double* lam) {
+  const size_t np = (size_t)pb.nx * pb.ny;
+  const size_t N = np * pb.nz;
+  const int kb = ray.up ? 0 : pb.nz - 1;
   for (size_t p = 0; p < np; ++p) {
     I[0 * N + kb * np + p] = T(ray.up ? pb.i_bottom : 0.0);
     I[1 * N + kb * np + p] = I[2 * N + kb * np + p] = I[3 * N + kb * np + p] = T(0.0);
     if (lam) lam[kb * np + p] = 0.0;
   }
-  for (int step = 1; step < nz; ++step) {
+}
+
+/* Formal solution for one ray and one frequency over the whole grid.
+ * Writes I ([4][N], one Stokes component after the other) and Lambda* (N). */
+template <class T>
+void sweep_one(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray, int jf,
+               T* I, double* lam) {
+  Cx<double> t[4][9];
+  tkq(ray.mu, ray.chi, t);
+  const int s = ray.up ? 1 : -1;
+  const int kb = ray.up ? 0 : pb.nz - 1;   // boundary plane
+  boundary_plane(pb, ray, I, lam);
+  for (int step = 1; step < pb.nz; ++step) {
     const int k = kb + s * step;
-    const int kup = k - s, kdn = k + s;
-    const bool hasP = (kdn >= 0 && kdn < nz);
-    const double dsM = (pb.z[k] - pb.z[kup]) / ray.mu;
-    const double dsP = hasP ? (pb.z[kdn] - pb.z[k]) / ray.mu : 0.0;
-    for (int j = 0; j < ny; ++j) {
-      for (int i = 0; i < nx; ++i) {
-        const size_t pO = (size_t)k * np + (size_t)j * nx + i;
-        /* M on the upwind plane, P on the downwind plane (reading A1) */
-        const double fxM = i - dsM * ray.sx / dx, fyM = j - dsM * ray.sy / dy;
-        const double fxP = i + dsP * ray.sx / dx, fyP = j + dsP * ray.sy / dy;
-        auto atM = [&](const T* arr) {
-          return interp_plane(arr + (size_t)kup * np, nx, ny, fxM, fyM, pb.interp);
-        };
-        auto atP = [&](const T* arr) {
-          return interp_plane(arr + (size_t)kdn * np, nx, ny, fxP, fyP, pb.interp);
-        };
-        /* absorption and emission at M, O, P (reading A3) */
-        T kapM = atM(f.kappa), kapO = f.kappa[pO], kapP(0.0);
-        T etaM[6], etaO[6], epsM[6], epsO[6], epsP[6];
-        for (int c = 0; c < 6; ++c) {
-          etaM[c] = atM(f.prop + c * N);
-          etaO[c] = f.prop[c * N + pO];
-          epsM[c] = atM(f.emis + c * N);
-          epsO[c] = f.emis[c * N + pO];
-          epsP[c] = T(0.0);
-        }
-        if (hasP) {
-          kapP = atP(f.kappa);
-          for (int c = 0; c < 6; ++c) epsP[c] = atP(f.emis + c * N);
-        }
-        /* Stokes vector at M, interpolated from the upwind plane */
-        T IM[4];
-        for (int st = 0; st < 4; ++st) IM[st] = atM(I + st * N);
-        /* monochromatic coefficients: eta_I(nu) = kappa * phi, eps(nu) = eps * phi */
-        const T etaIM = kapM * phi, etaIO = kapO * phi, etaIP = kapP * phi;
-        T eM[6], eO[6], eP[6], nM[6], nO[6];
-        for (int c = 0; c < 6; ++c) {
-          eM[c] = epsM[c] * phi; eO[c] = epsO[c] * phi; eP[c] = epsP[c] * phi;
-          nM[c] = etaM[c] * phi; nO[c] = etaO[c] * phi;
-        }
-        /* optical paths (reading A4) */
-        const T tauMO = 0.5 * (etaIM + etaIO) * std::fabs(dsM);
-        const T tauOP = 0.5 * (etaIO + etaIP) * std::fabs(dsP);
-        /* source vectors S = eps / eta_I */
-        T SM[4], SO[4], SP[4], cM[4];
-        for (int st = 0; st < 4; ++st) {
-          SM[st] = emission(t, st, eM, pb.w2) / etaIM;
-          SO[st] = emission(t, st, eO, pb.w2) / etaIO;
-          SP[st] = hasP ? emission(t, st, eP, pb.w2) / etaIP : T(0.0);
-          cM[st] = hasP ? control_point(pb.control, SM[st], SO[st], SP[st], tauMO, tauOP)
-                        : 0.5 * (SM[st] + SO[st]);   // reading A5
-        }
-        T KM[4][4], KO[4][4];
-        kprime(nM, etaIM, KM);
-        kprime(nO, etaIO, KO);
-        const Coef<T> cf = coefficients(tauMO);
-        /* Eq. fsbez right-hand side */
-        T b[4];
-        for (int a = 0; a < 4; ++a) {
-          T acc = cf.e * IM[a];
-          for (int c = 0; c < 4; ++c) acc -= cf.psiM * KM[a][c] * IM[c];
-          acc += cf.omM * SM[a] + cf.omO * SO[a] + cf.omC * cM[a];
-          b[a] = acc;
-        }
-        /* Eq. kappa: kappa^{-1} = 1 + psi'_O K'_O; solve kappa^{-1} I_O = b */
-        T A[4][4];
-        for (int a = 0; a < 4; ++a)
-          for (int c = 0; c < 4; ++c) A[a][c] = (a == c ? T(1.0) : T(0.0)) + cf.psiO * KO[a][c];
-        T IO[4];
-        gauss_solve<T, 4>(A, b, IO);
-        for (int st = 0; st < 4; ++st) I[st * N + pO] = IO[st];
-        /* Eq. 14: I_O for S_O = 1 and zero elsewhere; the unit source is a local
-         * maximum (c_M = 1) except on the last plane, where reading A5 gives c_M = 1/2 */
-        if (lam) lam[pO] = rp(cf.omO + (hasP ? 1.0 : 0.5) * cf.omC);
-      }
-    }
+    for (int j = 0; j < pb.ny; ++j)
+      for (int i = 0; i < pb.nx; ++i) node_update(pb, f, ray, t, pb.phi[jf], k, i, j, I, lam);
+  }
+}
+
+/* -------------------------------------------------------------------------- */
+/* Reverse-mode differentiation of the formal solution.                       */
+/* -------------------------------------------------------------------------- */
+/* A real number that records every operation applied to it on the calling
+ * thread's tape, so that one backward pass over the tape gives the derivative of
+ * a result with respect to each input (reverse-mode automatic differentiation).
+ * Inputs ("leaves") carry ids 0 .. nleaf-1 and are not on the tape; the k-th
+ * recorded operation has id nleaf + k; id -1 marks a constant. */
+struct Tape {
+  struct Op {
+    int a, b;        // ids of the operands (-1: none or constant)
+    double da, db;   // partial derivatives of the result with respect to them
+  };
+  std::vector<Op> ops;
+  int nleaf = 0;
+};
+static thread_local Tape* g_tape __attribute__((tls_model("initial-exec"))) = nullptr;
+
+struct Rv {
+  double v = 0.0;
+  int id = -1;
+  Rv() = default;
+  Rv(double x) : v(x), id(-1) {}
+};
+inline double rp(const Rv& x) { return x.v; }
+
+inline Rv record(double v, int a, double da, int b, double db) {
+  Rv r(v);
+  if (a < 0 && b < 0) return r;
+  g_tape->ops.push_back({a, b, da, db});
+  r.id = g_tape->nleaf + (int)g_tape->ops.size() - 1;
+  return r;
+}
+inline Rv operator+(const Rv& x, const Rv& y) { return record(x.v + y.v, x.id, 1.0, y.id, 1.0); }
+inline Rv operator-(const Rv& x, const Rv& y) { return record(x.v - y.v, x.id, 1.0, y.id, -1.0); }
+inline Rv operator*(const Rv& x, const Rv& y) { return record(x.v * y.v, x.id, y.v, y.id, x.v); }
+inline Rv operator/(const Rv& x, const Rv& y) {
+  const double q = x.v / y.v;
+  return record(q, x.id, 1.0 / y.v, y.id, -q / y.v);
+}
+inline Rv operator-(const Rv& x) { return record(-x.v, x.id, -1.0, -1, 0.0); }
+inline Rv& operator+=(Rv& x, const Rv& y) { return x = x + y; }
+inline Rv& operator-=(Rv& x, const Rv& y) { return x = x - y; }
+inline Rv exp(const Rv& x) {
+  const double e = std::exp(x.v);
+  return record(e, x.id, e, -1, 0.0);
+}
+
+/* Backward pass over the tape: adj_out holds dL/d(result) for each recorded
+ * operation on entry (indexed id - nleaf); the derivatives reaching the inputs are
+ * added to leafadj (indexed by id). */
+void backward(const Tape& tape, std::vector<double>& adj, double* leafadj) {
+  auto send = [&](int id, double v) {
+    if (id < 0) return;
+    if (id < tape.nleaf)
+      leafadj[id] += v;
+    else
+      adj[id - tape.nleaf] += v;
+  };
+  for (long k = (long)tape.ops.size() - 1; k >= 0; --k) {
+    const double a = adj[k];
+    if (a == 0.0) continue;
+    const Tape::Op& op = tape.ops[k];
+    send(op.a, a * op.da);
+    send(op.b, a * op.db);
   }
 }
 
@@ -711,6 +799,130 @@ int oracle_fs_sweep_cs(const oracle_problem* pb, const double* kappa, const doub
         }
     }
   }
+  return 0;
+}
+
+/* Reverse-mode derivative of L = sum over the selected (ray, frequency) pairs, top
+ * nodes and Stokes parameters of seed * I_top, with respect to every transfer
+ * coefficient (the function differentiated is the formal solution of Sect. 3.3,
+ * Eqs. fsbez and kappa, with its BESSER control points and Table 1 branches).  For
+ * each upward (ray, frequency) pair the forward sweep stores the whole Stokes field;
+ * the planes are then walked from the top down, and on each plane every node update
+ * (node_update, the same code as the forward solution) is recorded on a tape whose
+ * inputs are the upwind plane's Stokes vectors and the coefficients of the upwind,
+ * own and downwind planes; one backward pass per node sends dL/dI_O to those inputs,
+ * so dL/dI reaches the upwind plane before that plane is walked.  Branches (control
+ * point, series or closed form, pivots) are those of the forward evaluation.
+ *   seed   [nray_sel][nfreq_sel][ny][nx][4]  (entries of downward rays are ignored)
+ *   g_kappa [N], g_prop [6][N], g_emis [6][N] are added to.
+ * Returns 0, or -1 for an invalid problem. */
+int oracle_fs_adjoint(const oracle_problem* pb, const double* kappa, const double* prop,
+                      const double* emis, int nray_sel, const int* rays, int nfreq_sel,
+                      const int* freqs, const double* seed, double* g_kappa, double* g_prop,
+                      double* g_emis, int nthreads) {
+  if (!valid_problem(pb) || !kappa || !prop || !emis || !seed || !g_kappa || !g_prop ||
+      !g_emis || nray_sel < 0 || nfreq_sel < 0)
+    return -1;
+  const int nrays = 2 * pb->nmu * pb->nchi;
+  for (int r = 0; r < nray_sel; ++r)
+    if (rays[r] < 0 || rays[r] >= nrays) return -1;
+  for (int q = 0; q < nfreq_sel; ++q)
+    if (freqs[q] < 0 || freqs[q] >= pb->nfreq) return -1;
+  const int nx = pb->nx, ny = pb->ny, nz = pb->nz;
+  const size_t np = (size_t)nx * ny, N = np * nz;
+  const FieldsT<double> f{kappa, prop, emis};
+  const int nt = nthreads_of(nthreads);
+  const long npairs = (long)nray_sel * nfreq_sel;
+  /* gradient rows: 0 kappa, 1..6 propagation matrix, 7..12 emissivities */
+  std::vector<std::vector<double>> gpart(nt);
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double>& g = gpart[tid];
+    g.assign(13 * N, 0.0);
+    std::vector<double> I(4 * N), lamI(4 * N);
+    std::vector<Rv> Ir(4 * N), kr(N), pr(6 * N), er(6 * N);
+    Tape tape;
+    g_tape = &tape;
+    /* leaf ids of one plane step: Stokes vectors of the upwind plane [4][np], then the
+     * 13 coefficients of the upwind, own and downwind planes [3][13][np] */
+    tape.nleaf = (int)(43 * np);
+    std::vector<double> leafadj(43 * np), adj;
+    auto leaf_coef = [&](int pl, int c, size_t q) { return (int)((4 + 13 * pl + c) * np + q); };
+#pragma omp for schedule(static)
+    for (long pair = 0; pair < npairs; ++pair) {
+      const int r = rays[pair / nfreq_sel], jf = freqs[pair % nfreq_sel];
+      const Ray ray = make_ray(*pb, r);
+      if (!ray.up) continue;
+      sweep_one<double>(*pb, f, ray, jf, I.data(), nullptr);
+      for (size_t p = 0; p < 4 * N; ++p) Ir[p] = Rv(I[p]);
+      for (size_t p = 0; p < N; ++p) kr[p] = Rv(kappa[p]);
+      for (size_t p = 0; p < 6 * N; ++p) {
+        pr[p] = Rv(prop[p]);
+        er[p] = Rv(emis[p]);
+      }
+      const FieldsT<Rv> fr{kr.data(), pr.data(), er.data()};
+      std::fill(lamI.begin(), lamI.end(), 0.0);
+      for (size_t q = 0; q < np; ++q)
+        for (int st = 0; st < 4; ++st)
+          lamI[st * N + (size_t)(nz - 1) * np + q] = seed[(pair * np + q) * 4 + st];
+      Cx<double> t[4][9];
+      tkq(ray.mu, ray.chi, t);
+      for (int k = nz - 1; k >= 1; --k) {
+        for (size_t q = 0; q < np; ++q) {
+          for (int st = 0; st < 4; ++st) Ir[st * N + (size_t)(k - 1) * np + q].id = (int)(st * np + q);
+          for (int pl = 0; pl < 3; ++pl) {
+            const int kk = k - 1 + pl;
+            if (kk >= nz) continue;
+            const size_t pk = (size_t)kk * np + q;
+            kr[pk].id = leaf_coef(pl, 0, q);
+            for (int c = 0; c < 6; ++c) {
+              pr[c * N + pk].id = leaf_coef(pl, 1 + c, q);
+              er[c * N + pk].id = leaf_coef(pl, 7 + c, q);
+            }
+          }
+        }
+        std::fill(leafadj.begin(), leafadj.end(), 0.0);
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i < nx; ++i) {
+            const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+            tape.ops.clear();
+            node_update<Rv>(*pb, fr, ray, t, pb->phi[jf], k, i, j, Ir.data(), nullptr);
+            adj.assign(tape.ops.size(), 0.0);
+            for (int st = 0; st < 4; ++st) {
+              const int id = Ir[st * N + pO].id;
+              const double l = lamI[st * N + pO];
+              if (id >= tape.nleaf)
+                adj[id - tape.nleaf] += l;
+              else if (id >= 0)
+                leafadj[id] += l;
+            }
+            backward(tape, adj, leafadj.data());
+          }
+        for (size_t q = 0; q < np; ++q) {
+          for (int st = 0; st < 4; ++st)
+            lamI[st * N + (size_t)(k - 1) * np + q] += leafadj[st * np + q];
+          for (int pl = 0; pl < 3; ++pl) {
+            const int kk = k - 1 + pl;
+            if (kk >= nz) continue;
+            const size_t pk = (size_t)kk * np + q;
+            for (int c = 0; c < 13; ++c) g[c * N + pk] += leafadj[leaf_coef(pl, c, q)];
+          }
+        }
+      }
+    }
+  }
+  for (int th = 0; th < nt; ++th)
+    for (size_t p = 0; p < N; ++p) {
+      g_kappa[p] += gpart[th][p];
+      for (int c = 0; c < 6; ++c) {
+        g_prop[c * N + p] += gpart[th][(1 + c) * N + p];
+        g_emis[c * N + p] += gpart[th][(7 + c) * N + p];
+      }
+    }
   return 0;
 }
 
