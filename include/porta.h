@@ -184,7 +184,9 @@ size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int
  *   checkpoints   : device, porta_checkpoint_size() bytes, or NULL; filled with
  *                   the upward rays' states every checkpoint_stride planes for a
  *                   later porta_fs_adjoint of the same fields (no extra traffic:
- *                   those planes are written there instead of the workspace)
+ *                   those planes are written there instead of the workspace).
+ *                   Only with PORTA_INTERP_BILINEAR (the interpolation the adjoint
+ *                   differentiates); PORTA_EUNSUPPORTED otherwise
  *   checkpoint_bytes : size of that buffer; below porta_checkpoint_size() the
  *                   call returns PORTA_ENOMEM before any launch
  *   workspace     : device, >= porta_workspace_size(..., PORTA_WS_SWEEP, ...)
@@ -298,7 +300,10 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
 
 /*
  * Reverse-mode derivative of a scalar loss L(i_top) through the sweep of the
- * upward rays: given dL/d i_top (same layout and precision as i_top), adds
+ * upward rays, i.e. of the formal solution of Sect. 3.3 (Eqs. fsbez and kappa, the
+ * BESSER or parabolic control point of Sect. 3.2, Table 1 for small tau_MO, the
+ * bilinear interpolation of Sect. 3.1): given dL/d i_top (same layout and precision
+ * as i_top), adds
  * dL/dkappa, dL/dpropmat and dL/demis (each in the layout of its field, in
  * the sweep precision) to g_kappa [N], g_propmat [6][N], g_emis [6][N].
  * The intensity field is recomputed from plane checkpoints every
@@ -311,8 +316,10 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * the contents come from such a sweep is the caller's to ensure).  With a ray
  * range in the options only its upward rays are differentiated, and the
  * gradients add up over calls.  Stride 1 keeps every plane, so nothing is
- * recomputed.  The per-(node, ray) partials
- * are formed and summed in FP64 and stored in between in the sweep precision.
+ * recomputed.  The per-frequency partials of each (node, ray) are summed over the
+ * frequencies in the sweep precision, taken through the node's set-up (interpolation,
+ * S = eps/eta_I, K', control point) in FP64, stored between launches in the sweep
+ * precision and gathered onto the coefficients in FP64.
  * Only interp = PORTA_INTERP_BILINEAR is differentiated; PORTA_INTERP_BEZIER2D
  * returns PORTA_EUNSUPPORTED.
  */

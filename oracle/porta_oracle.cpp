@@ -32,8 +32,9 @@
  *   A6 series thresholds: omega_M 0.14, omega_O and omega_C 0.18 (Table 1),
  *      psi'_M and psi'_O 0.1.
  *   A7 Lambda* is the response of I_O to a unit S_O (Stokes I only): omega_O +
- *      omega_C, or omega_O + omega_C/2 on the last plane (A5); zero on the
- *      boundary plane.
+ *      c omega_C with c the control point of that unit source (1 with BESSER,
+ *      (1 + tau_MO/tau_OP)/2 with the parabolic rule, 1/2 on the last plane, A5);
+ *      zero on the boundary plane.
  *   A8 K = 2 multipoles are updated by plain Lambda iteration.
  *   A9/O7 T^K_Q(i, Omega) with reference direction gamma = 0, see tkq().
  *
@@ -462,9 +463,15 @@ void node_update(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray,
   T IO[4];
   gauss_solve<T, 4>(A, b, IO);
   for (int st = 0; st < 4; ++st) I[st * N + pO] = IO[st];
-  /* Eq. 14: I_O for S_O = 1 and zero elsewhere; the unit source is a local
-   * maximum (c_M = 1) except on the last plane, where reading A5 gives c_M = 1/2 */
-  if (lam) lam[pO] = rp(cf.omO + (hasP ? 1.0 : 0.5) * cf.omC);
+  /* Eq. 14: I_O for S_O = 1 and zero elsewhere, i.e. omega_O + omega_C c_M with c_M
+   * the control point of that unit source (1 for BESSER, whose step 2 finds the
+   * extremum at O; (1 + tau_MO/tau_OP)/2 for the parabola; 1/2 on the last plane,
+   * reading A5) */
+  if (lam) {
+    const double cunit =
+        hasP ? rp(control_point(pb.control, T(0.0), T(1.0), T(0.0), tauMO, tauOP)) : 0.5;
+    lam[pO] = rp(cf.omO + cunit * cf.omC);
+  }
 }
 
 /* Boundary plane of a ray (entering intensity; Lambda* = 0 there). */

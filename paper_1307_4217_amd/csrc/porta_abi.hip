@@ -664,6 +664,9 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
     return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
   if (nstokes(opts) == 1 && checkpoints)
     return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
+  if (checkpoints && interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED,
+                "checkpoints are for the adjoint, which differentiates the bilinear sweep");
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (checkpoints) {

@@ -480,7 +480,9 @@ k_sweep_plane(const PlaneArgs<T> a) {
   const double* SO = ps.SO;
   const double* cM = ps.cM;
   const double tau0M = ps.tau0M;
-  const double lamfac = ps.hasP ? 1.0 : 0.5;
+  // Lambda* = omega_O + omega_C c_M for a unit source at O alone (Eq. 14): c_M is 1 for
+  // BESSER, (1 + ratio)/2 for the parabola, 1/2 without a downwind point
+  const double lamfac = ps.hasP ? control_cm(0.0, 1.0, 0.0, ps.ratio, a.parabolic != 0) : 0.5;
 
   // frequency-independent pieces in the sweep precision
   const T eMv[3] = {(T)(etaM[0] * ikM), (T)(etaM[1] * ikM), (T)(etaM[2] * ikM)};

@@ -46,8 +46,9 @@ __global__ void __launch_bounds__(256) k_sweep_plane_i(const PlaneArgs<T> a) {
     const size_t bP = (size_t)a.kP * a.np;
     const double kapP = bil(a.kappa + bP, sP);
     const double SP = bil(a.emis + bP, sP) / kapP;
-    cM = control_cm(SM, SO, SP, tau0M / (0.5 * (kapO + kapP) * dsP), a.parabolic != 0);
-    lamfac = 1.0;
+    const double ratio = tau0M / (0.5 * (kapO + kapP) * dsP);
+    cM = control_cm(SM, SO, SP, ratio, a.parabolic != 0);
+    lamfac = control_cm(0.0, 1.0, 0.0, ratio, a.parabolic != 0);   // unit source at O
   }
   const T SMt = (T)SM, SOt = (T)SO, cMt = (T)cM, tau0 = (T)tau0M, lf = (T)lamfac;
   const T w00 = (T)sM.w00, w10 = (T)sM.w10, w01 = (T)sM.w01, w11 = (T)sM.w11;

@@ -304,3 +304,17 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120, cwd=root)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_checkpoints_rejected_with_the_bezier_mode():
+    """The adjoint differentiates the bilinear sweep only, so a sweep in the 9-point mode
+    may not leave checkpoints for it (they would hold the states of another forward
+    model)."""
+    L = porta.lib()
+    hg = small_hg()
+    dummy = np.zeros(8)
+    f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
+    assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, porta.BEZIER2D,
+                            None, None, 0, None, dummy.ctypes.data, 1 << 40, 4,
+                            dummy.ctypes.data, 1 << 40, None) == porta.EUNSUPPORTED
+    assert "bilinear" in L.porta_last_error().decode()

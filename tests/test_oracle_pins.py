@@ -106,20 +106,41 @@ def test_lambda_star_range_and_limits(orc):
     assert orc.besser_cm(0.0, 1.0, 0.0, 0.7, 2.3) == 1.0
 
 
-def test_lambda_star_is_response_to_unit_source(orc):
-    """Lambda* of the sweep equals I_O for S = delta_O with nothing incident (Sect. 3.3)."""
+@pytest.mark.parametrize("control", [0, 1])
+def test_lambda_star_is_response_to_unit_source(orc, control):
+    """Lambda* of the sweep is I_O of Eq. fsbez with I_M = S_M = S_P = 0 and S_O = 1
+    (Sect. 3.3), on unequal steps (so that the parabolic rule's control point, (1 + r)/2
+    for a unit source, differs from BESSER's 1).  Each node k is made the first interior
+    node of the slab of planes k-1 .. nz-1, whose boundary enters nothing, so that I_M
+    is zero and I_O is that response."""
     nz = 9
-    z = np.linspace(0, 8, nz)
-    kap = np.full(nz, 0.37)
+    z = np.cumsum(np.r_[0.0, 0.5 * 1.4 ** np.arange(nz - 1)])
+    kap = 0.37 * np.exp(-0.8 * np.arange(nz))
     q = mk_quad([1.0], [1.0], 1)
-    base = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap), q), rays=[0],
-                        want_j=False, want_itop=False, want_lambda=True)["lam"][0, 0]
+    base = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap), q, control=control),
+                        rays=[0], want_j=False, want_itop=False, want_lambda=True)["lam"][0, 0]
     for k in range(1, nz):
-        e = np.zeros((6, nz))
-        e[0, k] = kap[k]          # S00 = 1 at node k only
-        out = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap, emis=e), q),
+        m = nz - (k - 1)
+        e = np.zeros((6, m))
+        e[0, 1] = kap[k]          # S00 = 1 at node k only
+        out = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, m, 1, 1, z[k - 1:], kap[k - 1:],
+                                                    emis=e), q, control=control),
                            rays=[0], want_j=False, want_itop=False, want_full=True)
-        assert out["ifull"][0, 0, k, 0] == pytest.approx(base[k], rel=1e-13)
+        assert out["ifull"][0, 0, 1, 0] == pytest.approx(base[k], rel=1e-13)
+        if control == 0:
+            # BESSER needs nothing from the preceding point: the unit source leaves the
+            # upwind node dark (its control point sits at its own zero), so the response
+            # inside the whole slab is the same
+            e = np.zeros((6, nz))
+            e[0, k] = kap[k]
+            out = orc.fs_sweep(orc.OracleProblem(mk_atm(1, 1, nz, 1, 1, z, kap, emis=e), q),
+                               rays=[0], want_j=False, want_itop=False, want_full=True)
+            assert out["ifull"][0, 0, k, 0] == pytest.approx(base[k], rel=1e-13)
+    if control == 1:
+        r = (0.5 * (kap[1] + kap[2]) * (z[2] - z[1])) / (0.5 * (kap[2] + kap[3]) * (z[3] - z[2]))
+        c = orc.coefficients(0.5 * (kap[1] + kap[2]) * (z[2] - z[1]))
+        assert base[2] == pytest.approx(c[4] + c[5] * (1 + r) / 2, rel=1e-14)
+        assert abs(r - 1) > 0.1
 
 
 # --------------------------------------------------------------------------- BESSER control points
