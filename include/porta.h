@@ -197,6 +197,27 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
                    int checkpoint_stride, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * porta_fs_sweep without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  The call allocates nothing: its workspace is a static array of
+ * 64 MiB (64 << 20 bytes) in the library's device code, one per device, held until
+ * the process ends; its device address is looked up once per device on the first
+ * call with that device current.  Arguments are those of porta_fs_sweep with the
+ * same meaning, minus the checkpoints and the workspace; the work goes to the
+ * current device, to which `stream` must belong.  A problem whose sweep workspace
+ * (porta_workspace_size(..., PORTA_WS_SWEEP, ...) with the same options) exceeds
+ * 64 MiB returns PORTA_ENOMEM before anything is enqueued; a smaller
+ * opts->ray_batch shrinks it.  Nothing in the array needs to start at zero.  Every
+ * call on one device shares that device's array: calls whose work overlaps in time
+ * on one device (different streams, or different host threads) race and give wrong
+ * results; calls ordered on one stream do not.
+ */
+int porta_fs_sweep_noalloc(const porta_grid* grid, const porta_quad* quad,
+                           const porta_fields* fields, int prec, int interp,
+                           const porta_options* opts, double* jkq, int accumulate, void* i_top,
+                           void* stream);
+
+/*
  * Eq. 1 (and the Lambda* average) from a stored block of Stokes vectors:
  *   stokes      : device [nray][nf][N][4] (sweep precision) for rays
  *                 ray0..ray0+nray-1 and frequencies f0..f0+nf-1

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/porta.h"
@@ -14,6 +15,11 @@
 #include "porta_host.hpp"
 #include "porta_kernels.hpp"
 #include "porta_unpol.hpp"
+
+// Workspace of porta_fs_sweep_noalloc, one copy on every device the library runs on,
+// held until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace porta {
 namespace host {
@@ -587,6 +593,94 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
 }
 
 
+// ---------------------------------------------------------------------------
+// Static scratch of porta_fs_sweep_noalloc: one array per device, the workspace of
+// that entry point.  Host code never uses the symbol itself as an address: the
+// device address is looked up once per device (with that device current) and kept.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+    return fail(PORTA_EDEVICE, "no current HIP device");
+  if (dev >= kMaxDevices) return fail(PORTA_EUNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PORTA_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PORTA_OK;
+}
+
+// Validation and launch of a forward sweep.  With use_scratch the workspace is this
+// device's static scratch array instead of the caller's buffer.
+int sweep_entry(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
+                int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
+                void* i_top, void* checkpoints, size_t ck_bytes, int checkpoint_stride,
+                void* workspace, size_t ws_bytes, bool use_scratch, void* stream) {
+  int rc;
+  if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
+      (rc = validate_interp(interp)))
+    return rc;
+  if (!fields || !fields->kappa || !fields->propmat || !fields->emis)
+    return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
+  if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
+    return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
+  if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
+  if (nstokes(opts) == 1 && interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
+  if (nstokes(opts) == 1 && checkpoints)
+    return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
+  if (checkpoints && interp != PORTA_INTERP_BILINEAR)
+    return fail(PORTA_EUNSUPPORTED,
+                "checkpoints are for the adjoint, which differentiates the bilinear sweep");
+  if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
+    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
+  if (checkpoints) {
+    const size_t need = checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
+    if (ck_bytes < need)
+      return fail(PORTA_ENOMEM, "checkpoint buffer of %zu bytes is smaller than the %zu required",
+                  ck_bytes, need);
+  }
+  if (!use_scratch && !workspace) return fail(PORTA_EINVAL, "workspace is NULL");
+  const Layout L = sweep_layout(grid, quad, prec, opts);
+  if (use_scratch) {
+    if (L.total > kScratchBytes)
+      return fail(PORTA_ENOMEM,
+                  "this sweep needs %zu bytes of workspace; the static scratch holds %zu "
+                  "(use a smaller opts->ray_batch, or porta_fs_sweep)",
+                  L.total, kScratchBytes);
+    if ((rc = scratch_address(&workspace))) return rc;
+    ws_bytes = kScratchBytes;
+  }
+  if (ws_bytes < L.total)
+    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                L.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  if (opts && opts->check_inputs &&
+      (rc = (prec == PORTA_F64) ? check_inputs<double>(grid, fields, ws, L, st)
+                                : check_inputs<float>(grid, fields, ws, L, st)))
+    return rc;
+  if (prec == PORTA_F64)
+    return sweep_impl<double>(grid, quad, fields, interp, opts, jkq, accumulate,
+                              static_cast<double*>(i_top), static_cast<double*>(checkpoints),
+                              checkpoint_stride, ws, L, st);
+  return sweep_impl<float>(grid, quad, fields, interp, opts, jkq, accumulate,
+                           static_cast<float*>(i_top),
+                           static_cast<float*>(checkpoints), checkpoint_stride, ws, L, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -651,48 +745,16 @@ int porta_fs_sweep(const porta_grid* grid, const porta_quad* quad, const porta_f
                    int prec, int interp, const porta_options* opts, double* jkq, int accumulate,
                    void* i_top, void* checkpoints, size_t ck_bytes, int checkpoint_stride,
                    void* workspace, size_t ws_bytes, void* stream) {
-  int rc;
-  if ((rc = validate_grid(grid)) || (rc = validate_quad(quad)) || (rc = validate_prec(prec)) ||
-      (rc = validate_interp(interp)))
-    return rc;
-  if (!fields || !fields->kappa || !fields->propmat || !fields->emis)
-    return fail(PORTA_EINVAL, "fields and their arrays must not be NULL");
-  if (!std::isfinite(fields->i_bottom) || !std::isfinite(fields->w2))
-    return fail(PORTA_EINVAL, "i_bottom and w2 must be finite");
-  if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
-  if (nstokes(opts) == 1 && interp != PORTA_INTERP_BILINEAR)
-    return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
-  if (nstokes(opts) == 1 && checkpoints)
-    return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
-  if (checkpoints && interp != PORTA_INTERP_BILINEAR)
-    return fail(PORTA_EUNSUPPORTED,
-                "checkpoints are for the adjoint, which differentiates the bilinear sweep");
-  if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
-    return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
-  if (checkpoints) {
-    const size_t need = checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
-    if (ck_bytes < need)
-      return fail(PORTA_ENOMEM, "checkpoint buffer of %zu bytes is smaller than the %zu required",
-                  ck_bytes, need);
-  }
-  if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
-  const Layout L = sweep_layout(grid, quad, prec, opts);
-  if (ws_bytes < L.total)
-    return fail(PORTA_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
-                L.total);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* ws = static_cast<char*>(workspace);
-  if (opts && opts->check_inputs &&
-      (rc = (prec == PORTA_F64) ? check_inputs<double>(grid, fields, ws, L, st)
-                                : check_inputs<float>(grid, fields, ws, L, st)))
-    return rc;
-  if (prec == PORTA_F64)
-    return sweep_impl<double>(grid, quad, fields, interp, opts, jkq, accumulate,
-                              static_cast<double*>(i_top), static_cast<double*>(checkpoints),
-                              checkpoint_stride, ws, L, st);
-  return sweep_impl<float>(grid, quad, fields, interp, opts, jkq, accumulate,
-                           static_cast<float*>(i_top),
-                           static_cast<float*>(checkpoints), checkpoint_stride, ws, L, st);
+  return sweep_entry(grid, quad, fields, prec, interp, opts, jkq, accumulate, i_top, checkpoints,
+                     ck_bytes, checkpoint_stride, workspace, ws_bytes, false, stream);
+}
+
+int porta_fs_sweep_noalloc(const porta_grid* grid, const porta_quad* quad,
+                           const porta_fields* fields, int prec, int interp,
+                           const porta_options* opts, double* jkq, int accumulate, void* i_top,
+                           void* stream) {
+  return sweep_entry(grid, quad, fields, prec, interp, opts, jkq, accumulate, i_top, nullptr, 0,
+                     0, nullptr, 0, true, stream);
 }
 
 int porta_jkq_accumulate(const porta_grid* grid, const porta_quad* quad, int ray0, int nray,

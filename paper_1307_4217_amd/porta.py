@@ -78,6 +78,9 @@ def lib():
             L.porta_fs_sweep.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.POINTER(Fields),
                                          C.c_int, C.c_int, C.POINTER(Options), vp, C.c_int, vp,
                                          vp, sz, C.c_int, vp, sz, vp]
+            L.porta_fs_sweep_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Quad),
+                                                 C.POINTER(Fields), C.c_int, C.c_int,
+                                                 C.POINTER(Options), vp, C.c_int, vp, vp]
             L.porta_checkpoint_size.argtypes = [C.POINTER(Grid), C.POINTER(Quad), C.c_int,
                                                 C.c_int, C.POINTER(Options)]
             L.porta_checkpoint_size.restype = sz
@@ -105,6 +108,7 @@ def lib():
 
 
 EXPORTED = ("porta_workspace_size", "porta_checkpoint_size", "porta_fs_sweep",
+            "porta_fs_sweep_noalloc",
             "porta_jkq_accumulate", "porta_see_update", "porta_see_operator",
             "porta_mg_restrict", "porta_mg_prolong", "porta_mg_inject", "porta_rel_change",
             "porta_emissivity",
@@ -232,6 +236,20 @@ def fs_sweep(hg: HostGrid, kappa, propmat, emis, i_bottom, w2=1.0, prec=F64, int
                               _stream(stream))
     _check("porta_fs_sweep", st)
     return (jkq if want_jkq else None), (i_top if want_itop else None)
+
+
+def fs_sweep_noalloc(hg: HostGrid, kappa, propmat, emis, i_bottom, jkq, i_top, w2=1.0,
+                     prec=F64, interp=BILINEAR, accumulate=False, opts=None, stream=None):
+    """porta_fs_sweep_noalloc: fs_sweep with the library's static device scratch as its
+    workspace.  The caller passes the outputs (jkq [10][N] float64 or None, i_top or
+    None); nothing is allocated.  Returns (jkq, i_top)."""
+    f = Fields(_ptr(kappa), _ptr(propmat), _ptr(emis), float(i_bottom), float(w2))
+    st = lib().porta_fs_sweep_noalloc(C.byref(hg.grid), C.byref(hg.quad), C.byref(f),
+                                      int(prec), int(interp), C.byref(opts) if opts else None,
+                                      _ptr(jkq), int(bool(accumulate)), _ptr(i_top),
+                                      _stream(stream))
+    _check("porta_fs_sweep_noalloc", st)
+    return jkq, i_top
 
 
 def jkq_accumulate(hg: HostGrid, ray0, f0, stokes, lambda_star=None, jkq=None, prec=F64,

@@ -306,6 +306,25 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU only" in r.stderr and r.stdout == ""
 
 
+def test_noalloc_sweep_validates_before_touching_the_device():
+    """porta_fs_sweep_noalloc checks its arguments, and that the sweep's workspace fits its
+    64 MiB static scratch, on the host before any HIP call."""
+    L = porta.lib()
+    dummy = np.zeros(8)
+    f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
+    hg = small_hg()
+    big = small_hg(nx=256, ny=256)
+    assert porta.workspace_size(big, porta.F32, porta.WS_SWEEP) > 64 << 20
+    assert L.porta_fs_sweep_noalloc(C.byref(big.grid), C.byref(big.quad), C.byref(f), 1, 0,
+                                    None, None, 0, None, None) == porta.ENOMEM
+    msg = L.porta_last_error().decode()
+    assert "static scratch" in msg and str(64 << 20) in msg
+    assert L.porta_fs_sweep_noalloc(C.byref(hg.grid), C.byref(hg.quad), None, 1, 0, None, None,
+                                    0, None, None) == porta.EINVAL
+    assert L.porta_fs_sweep_noalloc(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 5, 0, None,
+                                    None, 0, None, None) == porta.EINVAL
+
+
 def test_checkpoints_rejected_with_the_bezier_mode():
     """The adjoint differentiates the bilinear sweep only, so a sweep in the 9-point mode
     may not leave checkpoints for it (they would hold the states of another forward
