@@ -1,0 +1,130 @@
+"""GPU adjoint (porta_fs_adjoint) against the oracle's FP64 reverse-mode gradient,
+element by element.
+
+The loss is L = sum (I_top - target)^2 over top nodes, upward rays, frequencies and
+Stokes parameters, with the target the oracle's emergent Stokes vector of a seeded
+perturbed atmosphere; both sides get the same seed dL/dI_top = 2 (I_top - target)
+(the oracle's forward, rounded to the sweep precision) and the same inputs (rounded
+to FP32 for the FP32 path).  Bars (the gradient tolerances are not stated by the
+method; these follow from the FP32 rounding of 30-64 plane steps):
+  FP64: every component within 1e-10 of the largest gradient of its field
+        (eta_I, propagation matrix, emissivities), and within 1e-8 relative where it
+        is above 1e-6 of that largest one;
+  FP32: l2 relative error 1e-4 per field, and 1e-3 relative on every component above
+        1e-3 of the largest one.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import Case, require_gpu, rounded, to_dev
+from paper_1307_4217_amd import inputs, porta
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("eta_I", "propmat", "emis")
+
+
+def _blocks(gk, gp, ge):
+    return [np.asarray(gk)[None], np.asarray(gp), np.asarray(ge)]
+
+
+def _problem(cfg_name, prec, freqs):
+    """Inputs, quadrature, seed [nray_up][nfreq][ny][nx][4] (zero off `freqs`)."""
+    from oracle import oracle as orc
+    cfg = inputs.CONFIGS[cfg_name]
+    atm = inputs.make_atmosphere(cfg, seed=0)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    nh = len(q.mu) * q.nchi
+    tgt = inputs.perturbed_target_atmosphere(atm, seed=5)
+    rays = np.arange(nh)
+    it = orc.fs_sweep(orc.OracleProblem(atm, q), rays=rays, freqs=freqs, want_j=False)["itop"]
+    it_t = orc.fs_sweep(orc.OracleProblem(tgt, q), rays=rays, freqs=freqs,
+                        want_j=False)["itop"]
+    dt = np.float64 if prec == porta.F64 else np.float32
+    seed_sel = (2.0 * (it - it_t)).astype(dt).astype(np.float64)
+    seed = np.zeros((nh, cfg.nfreq, atm.ny, atm.nx, 4))
+    seed[:, freqs] = seed_sel
+    return atm, q, rays, seed, seed_sel
+
+
+def _oracle_grad(atm, q, rays, freqs, seed_sel, chunk=5):
+    """The gradient is a sum over (ray, frequency) pairs: taken a few frequencies at a
+    time, with a progress line after each."""
+    from oracle import oracle as orc
+    op = orc.OracleProblem(atm, q)
+    total = None
+    for c0 in range(0, len(freqs), chunk):
+        g = _blocks(*orc.fs_adjoint(op, seed_sel[:, c0:c0 + chunk], rays=rays,
+                                    freqs=freqs[c0:c0 + chunk]))
+        total = g if total is None else [a + b for a, b in zip(total, g)]
+        print(f"  oracle gradient: {min(c0 + chunk, len(freqs))}/{len(freqs)} frequencies",
+              flush=True)
+    return total
+
+
+def _gpu_grad(atm, q, prec, seed, stride):
+    torch = require_gpu()
+    case = Case(atm, q, prec)
+    g = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                         to_dev(seed, case.dt), atm.w2, prec=prec, checkpoint_stride=stride)
+    torch.cuda.synchronize()
+    return _blocks(*[x.cpu().numpy().astype(np.float64) for x in g])
+
+
+def _compare(got, ref, prec, what):
+    report = []
+    for name, a, b in zip(FIELDS, got, ref):
+        scale = np.abs(b).max()
+        assert scale > 0 and np.isfinite(a).all(), (what, name)
+        d = np.abs(a - b)
+        if prec == porta.F64:
+            big = np.abs(b) > 1e-6 * scale
+            worst = float(d.max() / scale)
+            rel = float((d[big] / np.abs(b[big])).max())
+            report.append(f"{name}: max {worst:.1e} of max, rel {rel:.1e}")
+            assert worst <= 1e-10 and rel <= 1e-8, (what, name, worst, rel)
+        else:
+            big = np.abs(b) > 1e-3 * scale
+            l2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            rel = float((d[big] / np.abs(b[big])).max())
+            report.append(f"{name}: l2 {l2:.1e}, rel {rel:.1e}")
+            assert l2 <= 1e-4 and rel <= 1e-3, (what, name, l2, rel)
+    print(what, "; ".join(report), flush=True)
+
+
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_c1_adjoint_equals_oracle_gradient_everywhere(prec):
+    """16x16x32, 80 rays, 21 frequencies: the gradient of the loss over every upward ray
+    and frequency, all 13 x 8192 components, stride-4 checkpoints."""
+    freqs = np.arange(inputs.CONFIGS["C1"].nfreq)
+    atm, q, rays, seed, seed_sel = _problem("C1", prec, freqs)
+    ref = _oracle_grad(atm, q, rays, freqs, seed_sel)
+    got = _gpu_grad(atm, q, prec, seed, stride=4)
+    _compare(got, ref, prec, f"C1 {'FP64' if prec == porta.F64 else 'FP32'}")
+
+
+def _c4_freqs():
+    # every frequency on request; otherwise the two wings (x = -4, +4), line centre and
+    # the two half-way frequencies, so that every branch of the coefficients is taken
+    if os.environ.get("PORTA_ORACLE_ALL_FREQS") == "1":
+        return np.arange(inputs.CONFIGS["C4"].nfreq)
+    return np.array([0, 10, 20, 30, 40])
+
+
+@pytest.mark.parametrize("prec", [porta.F32, porta.F64])
+def test_c4_adjoint_equals_oracle_gradient_everywhere(prec):
+    """Differentiation instance, 64x64x64, 80 rays, 41 frequencies: the gradient of the
+    loss summed over every top node and upward ray at the frequencies of _c4_freqs,
+    all 13 x 262144 components, stride-8 checkpoints (the instance's own)."""
+    freqs = _c4_freqs()
+    print(f"C4 oracle gradient: 40 rays x {len(freqs)} frequencies", flush=True)
+    atm, q, rays, seed, seed_sel = _problem("C4", prec, freqs)
+    ref = _oracle_grad(atm, q, rays, freqs, seed_sel)
+    print("C4 oracle gradient done", flush=True)
+    got = _gpu_grad(atm, q, prec, seed, stride=8)
+    _compare(got, ref, prec, f"C4 {'FP64' if prec == porta.F64 else 'FP32'} "
+                             f"({len(freqs)} frequencies)")
