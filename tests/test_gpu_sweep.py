@@ -193,13 +193,9 @@ def test_jacobi_iterations_c1_match_oracle(orc):
 @pytest.mark.parametrize("prec", [porta.F64, porta.F32])
 def test_bezier2d_mode_matches_oracle(orc, prec):
     """Mode B (9-point monotonic Bezier at M and P) on the 16x16x32 instance and a ragged
-    plane, against the oracle's interpolation mode 1.
-
-    Single precision: the clamps act on each Stokes component and multipole separately, so
-    at a few outputs the emergent Q/I, U/I, V/I respond to input rounding about a hundred
-    times more than in the bilinear mode (the oracle itself moves Q/I by 1.7e-7 at this
-    case when its emissivities take one single-precision rounding).  The 1e-7 bound holds
-    for 99.9% of the outputs; the rest are capped at 1e-6."""
+    plane, against the oracle's interpolation mode 1: FP64 to the FP64 bars, FP32 on
+    Stokes I (2e-5) and J (2e-5 of J00).  The FP32 bar on Q/I, U/I, V/I (1e-7) is not met
+    in this mode; test_bezier2d_mode_fp32_polarization_bar records that."""
     import torch
     for cfg, seed in ((inputs.CONFIGS["C1"], 0), (inputs.Config("rag", 7, 5, 9, 2, 3, 5, True), 4)):
         atm = inputs.make_atmosphere(cfg, seed=seed)
@@ -218,15 +214,30 @@ def test_bezier2d_mode_matches_oracle(orc, prec):
         else:
             rel = np.abs(itop[..., 0] - want[..., 0]) / np.abs(want[..., 0])
             assert rel.max() <= 2e-5, f"{what} Stokes I max rel err {rel.max():.3e}"
-            for s_, name in ((1, "Q/I"), (2, "U/I"), (3, "V/I")):
-                d = np.abs(itop[..., s_] / itop[..., 0] - want[..., s_] / want[..., 0])
-                print(f"{what} {name}: max {d.max():.3e}, 99.9% {np.quantile(d, 0.999):.3e}")
-                assert np.quantile(d, 0.999) <= 1e-7 and d.max() <= 1e-6, f"{what} {name}"
             compare_jkq(jkq, ref["jkq"], 2e-5, what)
         # and it is a different interpolation from the bilinear one
         _, it_bl = Case(atm, q, prec).sweep()
         assert np.abs(it_bl - itop).max() > 1e-6
         torch.cuda.synchronize()
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "FP32 9-point Bezier mode misses the 1e-7 bar on Q/I, U/I, V/I (measured up to 4.2e-7; "
+    "2.8e-7 with the interpolation evaluated in FP64 on the FP32 plane states): the "
+    "per-component clamps amplify the rounding of the FP32 plane states, so the bar needs "
+    "FP64 states, i.e. the FP64 sweep"))
+def test_bezier2d_mode_fp32_polarization_bar(orc):
+    """The FP32 bar of Q/I, U/I, V/I (1e-7 absolute against the oracle on the same
+    FP32-rounded inputs) in the 9-point Bezier mode, 16x16x32 instance."""
+    cfg = inputs.CONFIGS["C1"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    ref = up_rays(orc.fs_sweep(orc.OracleProblem(atm, q, interp=1), want_j=False)["itop"], q)
+    _, itop = Case(atm, q, porta.F32).sweep(interp=porta.BEZIER2D, want_jkq=False)
+    worst = max(float(np.abs(itop[..., s] / itop[..., 0] - ref[..., s] / ref[..., 0]).max())
+                for s in (1, 2, 3))
+    print(f"bezier2d FP32 Q/I, U/I, V/I max abs err {worst:.3e}")
+    assert worst <= 1e-7
 
 
 @pytest.mark.parametrize("prec", [porta.F64, porta.F32])
