@@ -189,10 +189,29 @@ def measured_counters(kernel, workload):
     return None
 
 
+def host_cpus():
+    """Threads the CPU baseline may use: the process's CPU share (OMP_NUM_THREADS where the
+    job sets it, else the CPUs this process may run on), and a description of the host."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    share = int(os.environ.get("OMP_NUM_THREADS") or 0) or avail or 1
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(share, avail or share), {"nproc": os.cpu_count(), "affinity": avail,
+                                        "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+                                        "cpu_model": model}
+
+
 def cpu_baseline(cfg, atm, q, pairs):
     from oracle import oracle as orc
     import numpy as np
-    nthreads = max(1, min(16, os.cpu_count() or 1, pairs))
+    share, host = host_cpus()
+    nthreads = max(1, min(share, pairs))
     rays = np.linspace(0, cfg.nrays - 1, pairs).round().astype(np.int32)
     freqs = np.linspace(0, cfg.nfreq - 1, pairs).round().astype(np.int32)
     op = orc.OracleProblem(atm, q)
@@ -205,7 +224,8 @@ def cpu_baseline(cfg, atm, q, pairs):
         orc.fs_sweep(op, rays=rs, freqs=fs, want_j=True, want_itop=True, nthreads=nthreads)
         done += len(rs) * len(fs)
     dt = time.perf_counter() - t0
-    upd = done * cfg.npoints
+    per_pair = cfg.nx * cfg.ny * (cfg.nz - 1)     # node updates of one (ray, freq) pair
+    upd = done * per_pair
     # and one thread on two of the pairs
     t1 = time.perf_counter()
     orc.fs_sweep(op, rays=rays[:2], freqs=freqs[:1], want_j=True, want_itop=True, nthreads=1)
@@ -213,9 +233,11 @@ def cpu_baseline(cfg, atm, q, pairs):
     return {"value": upd / dt, "unit": "point*ray*freq updates/s", "cores": nthreads,
             "kind": "oracle",
             "sample": f"{done} (ray, freq) pairs of the {cfg.nx}x{cfg.ny}x{cfg.nz} grid, FP64 "
-                      f"sweep + J ({upd:.3e} updates in {dt:.1f} s)",
-            "single_thread_value": 2 * cfg.npoints / dt1,
-            "single_thread_sample": f"2 of those pairs on one thread ({dt1:.1f} s)"}
+                      f"sweep + J ({upd:.3e} updates in {dt:.1f} s) on the {nthreads} "
+                      f"threads of this job's CPU share",
+            "single_thread_value": 2 * per_pair / dt1,
+            "single_thread_sample": f"2 of those pairs on one thread ({dt1:.1f} s)",
+            "host": host}
 
 
 def main():
@@ -424,8 +446,12 @@ def main():
     see_ms = sum(m["see"] for m in per) / args.steps
     adj_ms = sum(m["adjoint"] for m in per) / args.steps
     step_ms = wall * 1e3 / args.steps
-    adj_updates = cfg.npoints * (cfg.nrays // 2) * cfg.nfreq if adj else 0
-    value = (cfg.updates + adj_updates) * args.steps / wall
+    # updates: one per node, ray and frequency on the nz - 1 planes after each ray's
+    # boundary plane (the boundary plane is set, not solved)
+    per_ray_freq = cfg.nx * cfg.ny * (cfg.nz - 1)
+    fwd_updates = per_ray_freq * cfg.nrays * cfg.nfreq
+    adj_updates = per_ray_freq * (cfg.nrays // 2) * cfg.nfreq if adj else 0
+    value = (fwd_updates + adj_updates) * args.steps / wall
 
     # every plane launch of the sweep kernel in one step: its rays and algorithmic bytes
     if inter:
@@ -435,7 +461,7 @@ def main():
     launches = (cfg.nz - 1) * len(shapes)
     lbytes = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, elem, nst)[0]
                                 for n in shapes) / launches
-    lupd = cfg.updates / launches
+    lupd = fwd_updates / launches
     launch_ms = sweep_ms / launches
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
     tname = "float" if elem == 4 else "double"
@@ -496,8 +522,8 @@ def main():
     extra = {"sweep_ms": round(sweep_ms, 2), "see_ms": round(see_ms, 3),
              "seed_ms": round(sum(m["seed"] for m in per) / args.steps, 2),
              "roofline_adjoint": roofline_adjoint if adj else None,
-             "sweep_updates_per_s": cfg.updates / (sweep_ms * 1e-3),
-             "effective_hbm_frac_34B": round(cfg.updates / (sweep_ms * 1e-3) * 34 / 8e12, 4),
+             "sweep_updates_per_s": fwd_updates / (sweep_ms * 1e-3),
+             "effective_hbm_frac_34B": round(fwd_updates / (sweep_ms * 1e-3) * 34 / 8e12, 4),
              "adjoint_ms": round(adj_ms, 2),
              "adjoint_updates_per_s": (adj_updates / (adj_ms * 1e-3)) if adj else None,
              "adjoint_over_forward_time": round(adj_ms / sweep_ms, 3) if adj else None,
@@ -525,7 +551,7 @@ def main():
         torch.cuda.synchronize()
         ms64 = a.elapsed_time(b)
         extra["fp64_sweep_ms"] = round(ms64, 2)
-        extra["fp64_sweep_updates_per_s"] = cfg.updates / (ms64 * 1e-3)
+        extra["fp64_sweep_updates_per_s"] = fwd_updates / (ms64 * 1e-3)
         extra["fp32_over_fp64_rate"] = round(ms64 / sweep_ms, 3)
         # the FP64 sweep kernel against HBM: its launches (ray batches of `nrb`), their
         # algorithmic bytes and, where committed, its counters
@@ -545,34 +571,47 @@ def main():
             "launch_ms": round(ms64 / n64, 4), "bytes_per_launch": b64}
         log(f"FP64 sweep {ms64:.1f} ms")
         if adj:
-            # FP64 adjoint on a range of 4 upward rays, reversed from the stride-1
-            # checkpoints of its own sweep (the interleaved schedule's pattern; every plane
-            # of 4 rays in FP64 is 107 GB at 256x256x128)
+            # One FP64 step of the same schedule: the upward rays in ranges of 4 (every
+            # plane of 4 rays in FP64 is 107 GB at 256x256x128), each swept keeping every
+            # plane and reversed at once, the downward rays in batches, then the SEE
             del ws64
             torch.cuda.empty_cache()
-            o64 = porta.options(ray_batch=4, block=args.block, xcd_remap=args.xcd_remap,
-                                ray_first=0, ray_count=4)
-            ck64 = torch.empty(porta.checkpoint_size(hg, porta.F64, 1, o64) + 256,
-                               dtype=torch.uint8, device=dev)
-            porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64,
-                           want_jkq=False, i_top=it64, opts=o64, checkpoints=ck64,
-                           checkpoint_stride=1)
-            gk64 = torch.zeros_like(k64)
-            gp64, ge64 = torch.zeros_like(p64), torch.zeros_like(e64)
-            a, b = ev(), ev()
-            a.record()
-            porta.fs_adjoint(hg, k64, p64, e64, atm.i_bottom, it64, atm.w2, prec=porta.F64,
-                             checkpoint_stride=1, g_kappa=gk64, g_propmat=gp64, g_emis=ge64,
-                             opts=o64, checkpoints=ck64)
-            b.record()
+            inter64 = schedule_mod.InterleavedSweep(hg, porta.F64, 4, ray_batch=args.ray_batch,
+                                                    block=args.block,
+                                                    xcd_remap=args.xcd_remap, device=dev)
+            target2_64 = target2.double()
+            gk64, gp64, ge64 = (torch.zeros_like(k64), torch.zeros_like(p64),
+                                torch.zeros_like(e64))
+            e64_next = torch.empty_like(e64)
+            s64_new = torch.empty_like(state["s_old"])
+            marks64 = []
+
+            def seed64(r, n, rows):
+                rows.lerp_(target2_64[r:r + n], -1.0)
+
             torch.cuda.synchronize()
-            ms_a64 = a.elapsed_time(b)
-            upd_a64 = 4 * cfg.nfreq * cfg.npoints
-            extra["fp64_adjoint_updates_per_s"] = upd_a64 / (ms_a64 * 1e-3)
-            extra["fp64_adjoint_sample"] = (f"4 upward rays from stride-1 checkpoints: "
-                                            f"{ms_a64:.1f} ms")
-            log(f"FP64 adjoint (4 rays) {ms_a64:.1f} ms")
-            del ck64
+            t64 = time.perf_counter()
+            inter64.run(k64, p64, e64, atm.i_bottom, atm.w2, jkq, it64, seed64, gk64, gp64,
+                        ge64, timer=lambda kind: Mark(kind, marks64))
+            with Mark("see", marks64):
+                porta.see_update(jkq, state["s_old"], atm.eps_c, atm.delta2, atm.w2, atm.planck,
+                                 hanle, bhat, kappa=k64, emis_out=e64_next, prec=porta.F64,
+                                 s_new=s64_new, rc=rc, workspace=ws_see)
+            torch.cuda.synchronize()
+            wall64 = time.perf_counter() - t64
+            m64 = split(marks64)
+            extra["fp64_step_ms"] = round(wall64 * 1e3, 2)
+            extra["fp64_step_updates_per_s"] = (fwd_updates + adj_updates) / wall64
+            extra["fp64_step_sweep_ms"] = round(m64["sweep"], 2)
+            extra["fp64_adjoint_ms"] = round(m64["adjoint"], 2)
+            extra["fp64_adjoint_updates_per_s"] = adj_updates / (m64["adjoint"] * 1e-3)
+            extra["fp32_over_fp64_step_rate"] = round(wall64 * 1e3 / step_ms, 3)
+            extra["fp64_step"] = ("one step of the same schedule in FP64: upward rays in "
+                                  "ranges of 4, stride-1 checkpoints, reversed at once; "
+                                  "downward rays; SEE")
+            log(f"FP64 step {wall64 * 1e3:.1f} ms (sweep {m64['sweep']:.1f}, adjoint "
+                f"{m64['adjoint']:.1f}, SEE {m64['see']:.2f})")
+            del inter64, target2_64
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the workload ...")
@@ -599,8 +638,10 @@ def main():
                                    ("unpolarized (intensity only)", nst == 1),
                                    ("parabolic control point", args.control == "parabolic"))
                                    if on),
-                   "updates_per_step": cfg.updates + adj_updates,
-                   "forward_updates": cfg.updates, "adjoint_updates": adj_updates,
+                   "updates_per_step": fwd_updates + adj_updates,
+                   "forward_updates": fwd_updates, "adjoint_updates": adj_updates,
+                   "update_count": "one per node, ray and frequency on the nz-1 planes "
+                                   "after each ray's boundary plane",
                    "ray_batch": nrb, "schedule": schedule,
                    "checkpoint_stride": 1 if schedule == "interleaved" else args.checkpoint_stride,
                    "adjoint_ray_batch": range_rays if schedule == "interleaved"

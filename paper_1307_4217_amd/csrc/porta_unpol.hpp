@@ -57,20 +57,36 @@ __global__ void __launch_bounds__(256) k_sweep_plane_i(const PlaneArgs<T> a) {
   const T* ip = a.iprev ? a.iprev + (size_t)rb * a.nfreq * fstride : nullptr;
   T* op = a.inext + (size_t)rb * a.nfreq * fstride + p;
   double jacc = 0.0, lacc = 0.0;
-  for (int f = 0; f < a.nfreq; ++f) {
-    T IM;
-    if (ip) {
-      const T* q = ip + (size_t)f * fstride;
-      IM = w00 * q[sM.i00] + w10 * q[sM.i10] + w01 * q[sM.i01] + w11 * q[sM.i11];
-    } else {
-      IM = a.ibound;
-    }
+  // one update (the scalar Eq. fsbez) at frequency f from the upwind intensity IM
+  auto update = [&](int f, T IM) __attribute__((always_inline)) {
     const Coefs<T> cf = coefficients(tau0 * s_phi[f]);
     const T x = cf.e * IM + cf.omM * SMt + cf.omO * SOt + cf.omC * cMt;
     op[(size_t)f * fstride] = x;
     const double W = s_wn[f];
     jacc += W * (double)x;
     lacc += W * (double)(cf.omO + lf * cf.omC);
+  };
+  if (!ip) {
+    // the upwind plane is the boundary
+    for (int f = 0; f < a.nfreq; ++f) update(f, a.ibound);
+  } else {
+    // the four corners of frequency f + 1 are loaded during the arithmetic of frequency f
+    auto load = [&](int f, T v[4]) __attribute__((always_inline)) {
+      const T* q = ip + (size_t)f * fstride;
+      v[0] = q[sM.i00];
+      v[1] = q[sM.i10];
+      v[2] = q[sM.i01];
+      v[3] = q[sM.i11];
+    };
+    T vA[4], vB[4];
+    load(0, vA);
+    for (int f = 0; f < a.nfreq; f += 2) {
+      if (f + 1 < a.nfreq) load(f + 1, vB);
+      update(f, w00 * vA[0] + w10 * vA[1] + w01 * vA[2] + w11 * vA[3]);
+      if (f + 1 >= a.nfreq) break;
+      if (f + 2 < a.nfreq) load(f + 2, vA);
+      update(f + 1, w00 * vB[0] + w10 * vB[1] + w01 * vB[2] + w11 * vB[3]);
+    }
   }
   if (a.jpart) {
     // the per-ray partial sums of J in the layout of the polarized sweep (Q, U, V zero)
