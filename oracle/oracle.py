@@ -32,7 +32,7 @@ class Problem(C.Structure):
                 ("nmu", C.c_int), ("nchi", C.c_int), ("nfreq", C.c_int),
                 ("mu", _dp), ("wmu", _dp), ("phi", _dp), ("wfreq", _dp),
                 ("i_bottom", C.c_double), ("w2", C.c_double), ("interp", C.c_int),
-                ("control", C.c_int)]
+                ("control", C.c_int), ("faces", C.c_int)]
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +59,8 @@ def lib():
                                              C.c_int]
             L.oracle_fs_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int, _ip,
                                             C.c_int, _ip, _dp, _dp, _dp, _dp, C.c_int]
+            L.oracle_lc_fine_sweep.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int, _ip,
+                                               C.c_int, _ip, C.c_int, _dp, C.c_int]
             L.oracle_lc_sweep.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int, _ip,
                                           C.c_int, _ip, _dp]
             L.oracle_jkq_accumulate.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, C.c_int,
@@ -98,7 +100,7 @@ class OracleProblem:
     """Holds the NumPy arrays behind a Problem struct."""
 
     def __init__(self, atm, quad, interp: int = 0, i_bottom: float | None = None,
-                 control: int = 0):
+                 control: int = 0, faces: int = 0):
         self.nx, self.ny, self.nz = atm.nx, atm.ny, atm.nz
         self.N = atm.nx * atm.ny * atm.nz
         self.z = _f64(atm.z)
@@ -116,7 +118,7 @@ class OracleProblem:
                               _d(self.z), len(self.mu), self.nchi, self.nfreq, _d(self.mu),
                               _d(self.wmu), _d(self.phi), _d(self.wfreq),
                               float(atm.i_bottom if i_bottom is None else i_bottom),
-                              float(atm.w2), int(interp), int(control))
+                              float(atm.w2), int(interp), int(control), int(faces))
 
     def with_fields(self, kappa=None, prop=None, emis=None):
         """Shallow copy with replaced material arrays."""
@@ -217,6 +219,21 @@ def lc_sweep(op: OracleProblem, rays, freqs):
                            freqs.ctypes.data_as(_ip), _d(out))
     if rc != 0:
         raise ValueError("oracle_lc_sweep rejected its inputs")
+    return out
+
+
+def lc_fine_sweep(op: OracleProblem, rays, freqs, nsub=1, nthreads: int = 0):
+    """Long characteristics through the trilinear medium, cut at every face crossing and
+    each piece in nsub parts: Stokes vectors at every point, [nr][nf][N][4]."""
+    L = lib()
+    rays = np.asarray(rays, np.int32)
+    freqs = np.asarray(freqs, np.int32)
+    out = np.zeros((len(rays), len(freqs), op.N, 4))
+    rc = L.oracle_lc_fine_sweep(C.byref(op.struct), _d(op.kappa), _d(op.prop), _d(op.emis),
+                                len(rays), rays.ctypes.data_as(_ip), len(freqs),
+                                freqs.ctypes.data_as(_ip), int(nsub), _d(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_lc_fine_sweep rejected its inputs")
     return out
 
 

@@ -17,7 +17,9 @@
  *   - one Jacobi update of the statistical equilibrium of a two-level
  *     J_l = 0 -> J_u = 1 atom with Hanle rotation (Sect. 2, Eq. nonlte;
  *     Sect. 5 for the Jacobi scheme and the convergence measure R_c);
- *   - long characteristics along the same rays (brute force check);
+ *   - long characteristics along the same rays (brute force check), and through
+ *     the trilinear medium cut at every face crossing (reference for the
+ *     vertical-face variant);
  *   - complex-step directional derivatives of the emergent Stokes vector;
  *   - the reverse-mode gradient of a loss on the emergent Stokes vector with
  *     respect to every transfer coefficient (recorded node updates, walked
@@ -47,6 +49,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -91,6 +94,10 @@ typedef struct {
   int interp;           /* 0 bilinear, 1 9-point monotonic Bezier */
   int control;          /* control point along the ray: 0 BESSER (Sect. 3.2, steps 1-9),
                            1 parabolic (steps 1, 3, 4 only: the DELOPAR choice) */
+  int faces;            /* where M and P lie: 0 on the neighbouring horizontal planes
+                           (reading A1); 1 on the first face of the grid the ray crosses,
+                           horizontal or vertical (Sect. 3.1), with bilinear interpolation
+                           on that face; needs interp = 0 */
 } oracle_problem;
 }
 
@@ -383,6 +390,78 @@ struct FieldsT {
   const T* emis;   // [6][N]
 };
 
+/* Sect. 3.1: the point where the short characteristic through node O = (i, j, k)
+ * first meets a face of the grid, going upwind (dir = -1, the point M) or downwind
+ * (dir = +1, the point P): the horizontal plane next to k, or a vertical plane x =
+ * const or y = const of the nodes next to O, whichever the ray reaches first (ties
+ * go to the horizontal plane).  On a horizontal plane the four nodes around the
+ * point are those of the bilinear interpolation in x and y; on a vertical plane they
+ * are the nodes of that plane around it, bilinear in y (or x) and z, two of them on
+ * plane k itself.  Returns false where the ray leaves the grid through its top or
+ * bottom plane without crossing a face (no point P on the last plane). */
+struct FacePoint {
+  size_t node[4];
+  double w[4];
+  double ds;   /* distance from O */
+};
+
+bool first_face(const oracle_problem& pb, const Ray& ray, int i, int j, int k, int dir,
+                FacePoint& fp) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny;
+  const double dx = pb.lx / nx, dy = pb.ly / ny;
+  const double ux = dir * ray.sx, uy = dir * ray.sy, uz = dir * ray.mu;   // direction of travel
+  const int kz = k + (uz > 0.0 ? 1 : -1);
+  if (kz < 0 || kz >= nz) return false;
+  const double sz = std::fabs(pb.z[kz] - pb.z[k]) / std::fabs(uz);
+  const double inf = std::numeric_limits<double>::infinity();
+  const double sx = ux != 0.0 ? dx / std::fabs(ux) : inf;
+  const double sy = uy != 0.0 ? dy / std::fabs(uy) : inf;
+  auto at = [&](int ii, int jj, int kk) {
+    return (size_t)kk * np + (size_t)wrap(jj, ny) * nx + (size_t)wrap(ii, nx);
+  };
+  if (sz <= sx && sz <= sy) {
+    fp.ds = sz;
+    const double fx = i + sz * ux / dx, fy = j + sz * uy / dy;
+    const double fi = std::floor(fx), fj = std::floor(fy);
+    const double tx = fx - fi, ty = fy - fj;
+    const int i0 = (int)fi, j0 = (int)fj;
+    fp.node[0] = at(i0, j0, kz);     fp.w[0] = (1.0 - tx) * (1.0 - ty);
+    fp.node[1] = at(i0 + 1, j0, kz); fp.w[1] = tx * (1.0 - ty);
+    fp.node[2] = at(i0, j0 + 1, kz); fp.w[2] = (1.0 - tx) * ty;
+    fp.node[3] = at(i0 + 1, j0 + 1, kz); fp.w[3] = tx * ty;
+    return true;
+  }
+  const bool xface = sx <= sy;
+  const double s = xface ? sx : sy;
+  fp.ds = s;
+  const double tz = s * std::fabs(uz) / std::fabs(pb.z[kz] - pb.z[k]);   // fraction from k to kz
+  if (xface) {
+    const int ic = i + (ux > 0.0 ? 1 : -1);
+    const double fy = j + s * uy / dy, fj = std::floor(fy), ty = fy - fj;
+    const int j0 = (int)fj;
+    fp.node[0] = at(ic, j0, k);      fp.w[0] = (1.0 - ty) * (1.0 - tz);
+    fp.node[1] = at(ic, j0 + 1, k);  fp.w[1] = ty * (1.0 - tz);
+    fp.node[2] = at(ic, j0, kz);     fp.w[2] = (1.0 - ty) * tz;
+    fp.node[3] = at(ic, j0 + 1, kz); fp.w[3] = ty * tz;
+  } else {
+    const int jc = j + (uy > 0.0 ? 1 : -1);
+    const double fx = i + s * ux / dx, fi = std::floor(fx), tx = fx - fi;
+    const int i0 = (int)fi;
+    fp.node[0] = at(i0, jc, k);      fp.w[0] = (1.0 - tx) * (1.0 - tz);
+    fp.node[1] = at(i0 + 1, jc, k);  fp.w[1] = tx * (1.0 - tz);
+    fp.node[2] = at(i0, jc, kz);     fp.w[2] = (1.0 - tx) * tz;
+    fp.node[3] = at(i0 + 1, jc, kz); fp.w[3] = tx * tz;
+  }
+  return true;
+}
+
+template <class T>
+T face_interp(const T* f, const FacePoint& fp) {
+  return fp.w[0] * f[fp.node[0]] + fp.w[1] * f[fp.node[1]] + fp.w[2] * f[fp.node[2]] +
+         fp.w[3] * f[fp.node[3]];
+}
+
 /* One step of the formal solution: the Stokes vector at node O = (i, j) of plane k
  * of the ray, from the upwind plane k - s already held in I ([4][N], one Stokes
  * component after the other).  Writes I_O into I and, if lam is given, Lambda* at O. */
@@ -395,17 +474,23 @@ void node_update(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray,
   const double dx = pb.lx / nx, dy = pb.ly / ny;
   const int s = ray.up ? 1 : -1;
   const int kup = k - s, kdn = k + s;
-  const bool hasP = (kdn >= 0 && kdn < nz);
-  const double dsM = (pb.z[k] - pb.z[kup]) / ray.mu;
-  const double dsP = hasP ? (pb.z[kdn] - pb.z[k]) / ray.mu : 0.0;
   const size_t pO = (size_t)k * np + (size_t)j * nx + i;
-  /* M on the upwind plane, P on the downwind plane (reading A1) */
+  /* M and P on the first face crossed (faces = 1, Sect. 3.1) */
+  FacePoint fpM{}, fpP{};
+  const bool faces = pb.faces != 0;
+  const bool hasP = faces ? first_face(pb, ray, i, j, k, +1, fpP) : (kdn >= 0 && kdn < nz);
+  if (faces) first_face(pb, ray, i, j, k, -1, fpM);
+  const double dsM = faces ? fpM.ds : (pb.z[k] - pb.z[kup]) / ray.mu;
+  const double dsP = faces ? (hasP ? fpP.ds : 0.0) : (hasP ? (pb.z[kdn] - pb.z[k]) / ray.mu : 0.0);
+  /* or M on the upwind plane, P on the downwind plane (reading A1) */
   const double fxM = i - dsM * ray.sx / dx, fyM = j - dsM * ray.sy / dy;
   const double fxP = i + dsP * ray.sx / dx, fyP = j + dsP * ray.sy / dy;
   auto atM = [&](const T* arr) {
+    if (faces) return face_interp(arr, fpM);
     return interp_plane(arr + (size_t)kup * np, nx, ny, fxM, fyM, pb.interp);
   };
   auto atP = [&](const T* arr) {
+    if (faces) return face_interp(arr, fpP);
     return interp_plane(arr + (size_t)kdn * np, nx, ny, fxP, fyP, pb.interp);
   };
   /* absorption and emission at M, O, P (reading A3) */
@@ -487,6 +572,52 @@ void boundary_plane(const oracle_problem& pb, const Ray& ray, T* I, double* lam)
   }
 }
 
+/* The sweep when M may lie on a vertical face (faces = 1): a node then depends on
+ * nodes of its own plane, and with x and y periodic these dependencies close around
+ * the box.  Each plane (in upwind order) is therefore the fixed point of its node
+ * equations, reached by passes over the plane in the ray's horizontal upwind order
+ * (each pass carries the intensity once around the box) until a pass changes no
+ * Stokes value by more than 1e-15 of the largest; the plane starts from zero.  A plane
+ * that does not converge in kMaxPasses passes is set to NaN. */
+constexpr int kMaxPasses = 200000;
+
+template <class T>
+void sweep_faces(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray,
+                 const Cx<double> t[4][9], double phi, T* I, double* lam) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny, N = np * nz;
+  const int s = ray.up ? 1 : -1;
+  const int kb = ray.up ? 0 : nz - 1;
+  const bool xup = ray.sx >= 0.0, yup = ray.sy >= 0.0;   // upwind neighbours at lower index
+  for (int step = 1; step < nz; ++step) {
+    const int k = kb + s * step;
+    for (size_t q = 0; q < np; ++q)
+      for (int st = 0; st < 4; ++st) I[st * N + (size_t)k * np + q] = T(0.0);
+    bool done = false;
+    for (int pass = 0; pass < kMaxPasses && !done; ++pass) {
+      double change = 0.0, scale = 0.0;
+      for (int jj = 0; jj < ny; ++jj)
+        for (int ii = 0; ii < nx; ++ii) {
+          const int i = xup ? ii : nx - 1 - ii, j = yup ? jj : ny - 1 - jj;
+          const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+          double old[4];
+          for (int st = 0; st < 4; ++st) old[st] = rp(I[st * N + pO]);
+          node_update(pb, f, ray, t, phi, k, i, j, I, lam);
+          for (int st = 0; st < 4; ++st) {
+            const double v = rp(I[st * N + pO]);
+            change = std::max(change, std::fabs(v - old[st]));
+            scale = std::max(scale, std::fabs(v));
+          }
+        }
+      done = pass > 0 && change <= 1e-15 * scale;
+    }
+    if (!done)
+      for (size_t q = 0; q < np; ++q)
+        for (int st = 0; st < 4; ++st)
+          I[st * N + (size_t)k * np + q] = T(std::numeric_limits<double>::quiet_NaN());
+  }
+}
+
 /* Formal solution for one ray and one frequency over the whole grid.
  * Writes I ([4][N], one Stokes component after the other) and Lambda* (N). */
 template <class T>
@@ -497,6 +628,10 @@ void sweep_one(const oracle_problem& pb, const FieldsT<T>& f, const Ray& ray, in
   const int s = ray.up ? 1 : -1;
   const int kb = ray.up ? 0 : pb.nz - 1;   // boundary plane
   boundary_plane(pb, ray, I, lam);
+  if (pb.faces) {
+    sweep_faces(pb, f, ray, t, pb.phi[jf], I, lam);
+    return;
+  }
   for (int step = 1; step < pb.nz; ++step) {
     const int k = kb + s * step;
     for (int j = 0; j < pb.ny; ++j)
@@ -612,7 +747,8 @@ void accumulate_j(const Ray& ray, double Wj, const double* I,
 bool valid_problem(const oracle_problem* pb) {
   if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 2 || pb->nmu < 1 || pb->nchi < 1 ||
       pb->nfreq < 1 || !pb->z || !pb->mu || !pb->wmu || !pb->phi || !pb->wfreq ||
-      (pb->interp != 0 && pb->interp != 1) || (pb->control != 0 && pb->control != 1))
+      (pb->interp != 0 && pb->interp != 1) || (pb->control != 0 && pb->control != 1) ||
+      (pb->faces != 0 && pb->faces != 1) || (pb->faces == 1 && pb->interp != 0))
     return false;
   for (int k = 1; k < pb->nz; ++k)
     if (!(pb->z[k] > pb->z[k - 1])) return false;
@@ -708,6 +844,134 @@ void lc_one(const oracle_problem& pb, const FieldsT<double>& f, const Ray& ray, 
       }
 }
 
+/* Trilinear interpolation of a node field at a point in cell units (fx, fy; x and y
+ * periodic) and height z (inside [z_0, z_{nz-1}]). */
+double trilinear(const oracle_problem& pb, const double* f, double fx, double fy, double z) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny;
+  int kk = 0;
+  while (kk < nz - 2 && pb.z[kk + 1] <= z) ++kk;
+  const double tz = std::min(1.0, std::max(0.0, (z - pb.z[kk]) / (pb.z[kk + 1] - pb.z[kk])));
+  const double fi = std::floor(fx), fj = std::floor(fy);
+  const double tx = fx - fi, ty = fy - fj;
+  const int i0 = wrap((long)fi, nx), i1 = wrap((long)fi + 1, nx);
+  const int j0 = wrap((long)fj, ny), j1 = wrap((long)fj + 1, ny);
+  double v = 0.0;
+  for (int dk = 0; dk < 2; ++dk) {
+    const double* g = f + (size_t)(kk + dk) * np;
+    const double pl = (1.0 - tx) * (1.0 - ty) * g[j0 * nx + i0] + tx * (1.0 - ty) * g[j0 * nx + i1] +
+                      (1.0 - tx) * ty * g[j1 * nx + i0] + tx * ty * g[j1 * nx + i1];
+    v += (dk ? tz : 1.0 - tz) * pl;
+  }
+  return v;
+}
+
+/* Long characteristics through the trilinear medium: the straight ray from the
+ * boundary to node O is cut at every face of the grid it crosses (x, y and z planes;
+ * beyond O, at the first face crossed downwind, the point P of the last step), each
+ * piece is split into nsub equal parts, the transfer coefficients at the cuts are the
+ * trilinear interpolation of the node values, and Eq. fsbez with BESSER control
+ * points is applied piece by piece.  As nsub grows this tends to the exact solution
+ * of the transfer equation in that medium. */
+void lc_fine_one(const oracle_problem& pb, const FieldsT<double>& f, const Ray& ray, int jf,
+                 int nsub, double* Iout) {
+  const int nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  const size_t np = (size_t)nx * ny, N = np * nz;
+  const double dx = pb.lx / nx, dy = pb.ly / ny;
+  const double phi = pb.phi[jf];
+  Cx<double> t[4][9];
+  tkq(ray.mu, ray.chi, t);
+  const int kb = ray.up ? 0 : nz - 1;
+  const double amu = std::fabs(ray.mu);
+  std::vector<double> cuts, pts;
+  struct Pt {
+    double kap, eta[6], eps[6];
+  };
+  std::vector<Pt> path;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t pO = (size_t)k * np + (size_t)j * nx + i;
+        if (k == kb) {
+          Iout[4 * pO] = ray.up ? pb.i_bottom : 0.0;
+          Iout[4 * pO + 1] = Iout[4 * pO + 2] = Iout[4 * pO + 3] = 0.0;
+          continue;
+        }
+        /* distances upwind from O (positive) of the face crossings, O at 0 */
+        const double send = std::fabs(pb.z[k] - pb.z[kb]) / amu;
+        cuts.assign(1, 0.0);
+        for (int kk = k; kk != kb;) {
+          kk += ray.up ? -1 : 1;
+          cuts.push_back(std::fabs(pb.z[k] - pb.z[kk]) / amu);
+        }
+        if (ray.sx != 0.0)
+          for (int m = 1; m * dx / std::fabs(ray.sx) < send; ++m) cuts.push_back(m * dx / std::fabs(ray.sx));
+        if (ray.sy != 0.0)
+          for (int m = 1; m * dy / std::fabs(ray.sy) < send; ++m) cuts.push_back(m * dy / std::fabs(ray.sy));
+        std::sort(cuts.begin(), cuts.end());
+        std::vector<double> u;
+        for (double c : cuts)
+          if (u.empty() || c - u.back() > 1e-12 * send) u.push_back(c);
+        u.back() = send;
+        /* the downwind piece: first face crossed beyond O, if inside the grid */
+        FacePoint fpP;
+        const bool hasP = first_face(pb, ray, i, j, k, +1, fpP);
+        pts.clear();
+        for (size_t a = u.size() - 1; a >= 1; --a)
+          for (int q = 0; q < nsub; ++q) pts.push_back(u[a] - (u[a] - u[a - 1]) * q / nsub);
+        pts.push_back(0.0);
+        if (hasP) pts.push_back(-fpP.ds / nsub);
+        path.resize(pts.size());
+        for (size_t a = 0; a < pts.size(); ++a) {
+          const double sd = pts[a];
+          const double fx = i - sd * ray.sx / dx, fy = j - sd * ray.sy / dy;
+          const double z = pb.z[k] - sd * ray.mu;
+          Pt& pt = path[a];
+          pt.kap = trilinear(pb, f.kappa, fx, fy, z);
+          for (int c = 0; c < 6; ++c) {
+            pt.eta[c] = trilinear(pb, f.prop + c * N, fx, fy, z);
+            pt.eps[c] = trilinear(pb, f.emis + c * N, fx, fy, z);
+          }
+        }
+        const size_t nO = pts.size() - (hasP ? 2 : 1);   // index of O
+        double Ic[4] = {ray.up ? pb.i_bottom : 0.0, 0.0, 0.0, 0.0};
+        for (size_t m = 1; m <= nO; ++m) {
+          const Pt &nM = path[m - 1], &nO_ = path[m];
+          const bool hp = m + 1 < path.size();
+          const Pt* nP = hp ? &path[m + 1] : nullptr;
+          const double dsM = pts[m - 1] - pts[m], dsP = hp ? pts[m] - pts[m + 1] : 0.0;
+          const double tauMO = 0.5 * (nM.kap + nO_.kap) * phi * dsM;
+          const double tauOP = hp ? 0.5 * (nO_.kap + nP->kap) * phi * dsP : 0.0;
+          double SM[4], SO[4], SP[4], cM[4], eM[6], eO[6], eP[6], hM[6], hO[6];
+          for (int c = 0; c < 6; ++c) {
+            eM[c] = nM.eps[c] * phi; eO[c] = nO_.eps[c] * phi; eP[c] = hp ? nP->eps[c] * phi : 0.0;
+            hM[c] = nM.eta[c] * phi; hO[c] = nO_.eta[c] * phi;
+          }
+          for (int st = 0; st < 4; ++st) {
+            SM[st] = emission(t, st, eM, pb.w2) / (nM.kap * phi);
+            SO[st] = emission(t, st, eO, pb.w2) / (nO_.kap * phi);
+            SP[st] = hp ? emission(t, st, eP, pb.w2) / (nP->kap * phi) : 0.0;
+            cM[st] = hp ? control_point(pb.control, SM[st], SO[st], SP[st], tauMO, tauOP)
+                        : 0.5 * (SM[st] + SO[st]);
+          }
+          double KM[4][4], KO[4][4];
+          kprime(hM, nM.kap * phi, KM);
+          kprime(hO, nO_.kap * phi, KO);
+          const Coef<double> cf = coefficients(tauMO);
+          double b[4], A[4][4], x[4];
+          for (int a = 0; a < 4; ++a) {
+            double acc = cf.e * Ic[a];
+            for (int c = 0; c < 4; ++c) acc -= cf.psiM * KM[a][c] * Ic[c];
+            b[a] = acc + cf.omM * SM[a] + cf.omO * SO[a] + cf.omC * cM[a];
+            for (int c = 0; c < 4; ++c) A[a][c] = (a == c ? 1.0 : 0.0) + cf.psiO * KO[a][c];
+          }
+          gauss_solve<double, 4>(A, b, x);
+          for (int st = 0; st < 4; ++st) Ic[st] = x[st];
+        }
+        for (int st = 0; st < 4; ++st) Iout[4 * pO + st] = Ic[st];
+      }
+}
+
 }  // namespace
 
 extern "C" {
@@ -776,7 +1040,9 @@ int oracle_fs_sweep_cs(const oracle_problem* pb, const double* kappa, const doub
                        const double* demis, double h, int nray_sel, const int* rays,
                        int nfreq_sel, const int* freqs, double* itop_re, double* itop_im,
                        int nthreads) {
-  if (!valid_problem(pb) || !kappa || !prop || !emis || !dkappa || !dprop || !demis) return -1;
+  if (!valid_problem(pb) || pb->faces || !kappa || !prop || !emis || !dkappa || !dprop ||
+      !demis)
+    return -1;
   const size_t np = (size_t)pb->nx * pb->ny, N = np * pb->nz;
   std::vector<cd> ck(N), cp(6 * N), ce(6 * N);
   for (size_t p = 0; p < N; ++p) ck[p] = cd(kappa[p], h * dkappa[p]);
@@ -827,8 +1093,8 @@ int oracle_fs_adjoint(const oracle_problem* pb, const double* kappa, const doubl
                       const double* emis, int nray_sel, const int* rays, int nfreq_sel,
                       const int* freqs, const double* seed, double* g_kappa, double* g_prop,
                       double* g_emis, int nthreads) {
-  if (!valid_problem(pb) || !kappa || !prop || !emis || !seed || !g_kappa || !g_prop ||
-      !g_emis || nray_sel < 0 || nfreq_sel < 0)
+  if (!valid_problem(pb) || pb->faces || !kappa || !prop || !emis || !seed || !g_kappa ||
+      !g_prop || !g_emis || nray_sel < 0 || nfreq_sel < 0)
     return -1;
   const int nrays = 2 * pb->nmu * pb->nchi;
   for (int r = 0; r < nray_sel; ++r)
@@ -937,12 +1203,29 @@ int oracle_fs_adjoint(const oracle_problem* pb, const double* kappa, const doubl
 int oracle_lc_sweep(const oracle_problem* pb, const double* kappa, const double* prop,
                     const double* emis, int nray_sel, const int* rays, int nfreq_sel,
                     const int* freqs, double* ifull) {
-  if (!valid_problem(pb) || !ifull) return -1;
+  if (!valid_problem(pb) || pb->faces || !ifull) return -1;
   const size_t N = (size_t)pb->nx * pb->ny * pb->nz;
   const FieldsT<double> f{kappa, prop, emis};
   for (int r = 0; r < nray_sel; ++r)
     for (int q = 0; q < nfreq_sel; ++q)
       lc_one(*pb, f, make_ray(*pb, rays[r]), freqs[q], ifull + ((size_t)r * nfreq_sel + q) * N * 4);
+  return 0;
+}
+
+/* Long characteristics through the trilinear medium (lc_fine_one) at every point,
+ * [nray_sel][nfreq_sel][N][4]; nsub >= 1 parts per piece between face crossings. */
+int oracle_lc_fine_sweep(const oracle_problem* pb, const double* kappa, const double* prop,
+                         const double* emis, int nray_sel, const int* rays, int nfreq_sel,
+                         const int* freqs, int nsub, double* ifull, int nthreads) {
+  if (!valid_problem(pb) || !ifull || nsub < 1) return -1;
+  const size_t N = (size_t)pb->nx * pb->ny * pb->nz;
+  const FieldsT<double> f{kappa, prop, emis};
+  const long npairs = (long)nray_sel * nfreq_sel;
+  const int nt = nthreads_of(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (long pair = 0; pair < npairs; ++pair)
+    lc_fine_one(*pb, f, make_ray(*pb, rays[pair / nfreq_sel]), freqs[pair % nfreq_sel], nsub,
+                ifull + (size_t)pair * N * 4);
   return 0;
 }
 
