@@ -233,3 +233,43 @@ def test_nested_multigrid_starts_closer_than_a_vcycle(mg):
     r_n = np.abs(levels[0].residual(S, f))
     assert r_n.max() < 0.5 * r_v.max()
     assert r_n[0].max() < 0.1 * r_v[0].max()
+
+
+def test_random_propagation_matrix_leaves_isolated_slow_points(mg):
+    """Why the V-cycle barely helps on the configured atmosphere (16x16x33, random
+    eta_X, rho_X up to 5% of eta_I with no matching emission, magnetic field): in the
+    optically thick lower planes each cell's own dichroism raises J above S by
+    delta = [(1 + K')^-1]_II - 1, comparable to eps_c, which leaves a local equation with
+    a destruction probability eps_c - delta close to zero.  The error that survives the
+    cycles sits on a few isolated points of that kind, which no coarser grid represents,
+    so a V(2,4) cycle gains about what its own smoothing gains."""
+    from oracle import multigrid as mgm
+    cfg = inputs.Config("mg", 16, 16, 33, 2, 4, 5, True)
+    atm = inputs.make_atmosphere(cfg, seed=0, magnetic=True)
+    q = inputs.make_quadrature(cfg)
+    levels = mgm.make_levels(atm, q, 3)
+    f = levels[0].planck_rhs()
+    S = atm.source.copy()
+    hist = []
+    for _ in range(6):
+        new = mgm.vcycle(levels, S.copy(), f)
+        hist.append(mgm.relative_change(new, S))
+        prev, S = S, new
+    factor = (hist[-1] / hist[-3]) ** 0.5
+    # slow: about 0.4 per cycle, against 0.86 per Jacobi sweep (0.86^6 = 0.41 for the
+    # cycle's six smoothing sweeps)
+    assert factor > 0.3, hist
+    d = np.abs(S[0] - prev[0]) / np.abs(S[0])
+    slow = d > d.max() / 10
+    np_ = cfg.nx * cfg.ny
+    assert slow.mean() < 0.02                      # a few points carry the change
+    sm = slow.reshape(cfg.nz, np_)
+    assert sm[6:].sum() == 0                       # all in the optically thick planes
+    S3 = S[0].reshape(cfg.nz, np_)
+    ratio = np.concatenate([S3[k][sm[k]] / np.median(S3[k]) for k in range(cfg.nz) if sm[k].any()])
+    assert np.median(ratio) > 1.3                  # where S00 rose above its plane
+    eta = atm.propmat / atm.kappa
+    a2, r2 = (eta[:3] ** 2).sum(0), (eta[3:] ** 2).sum(0)
+    ar = (eta[:3] * eta[3:]).sum(0)
+    delta = (1 + r2) / (1 + r2 - a2 - ar ** 2) - 1
+    assert np.median(delta[slow]) > 1.3 * np.median(delta)   # with the larger dichroism
