@@ -15,6 +15,14 @@ Methods (constant opacity, Delta z = Delta tau, unpolarised):
   cbezier    as bezier, with c_M clipped to the range of y_M, y_O
 The last node has no downwind point; it takes the chord midpoint as control point and
 is left out of E.
+
+Other readings of the Bezier solvers (solve_ray_reading), each on the nodes of
+[-12, 12] with the analytic source at ghost nodes beyond both ends, so that every
+interval takes its full rule and E covers every node:
+  bezier_o   tangent at O from the Fritsch-Butland derivative (as bezier above)
+  bezier_m   tangent at M: c = y_M + h y'_M / 2, y'_M from the triple around M
+  bezier_mo  the mean of those two control points
+and each with the clip of c_M to the range of y_M, y_O (prefix c).
 """
 from __future__ import annotations
 
@@ -97,3 +105,24 @@ def error_table(node_counts=(9, 13, 17, 25, 33, 49, 97, 193, 385)):
     """{method: [(Delta tau, E), ...]}."""
     return {m: [((Z_MAX - Z_MIN) / (n - 1), max_true_error(n, m)) for n in node_counts]
             for m in METHODS}
+
+
+def solve_ray_reading(nodes, reading):
+    """E for `nodes` uniform points on [-12, 12] with one of the readings above."""
+    z = np.linspace(Z_MIN, Z_MAX, nodes)
+    h = z[1] - z[0]
+    S = source(np.r_[z[0] - 2 * h, z[0] - h, z, z[-1] + h])   # S[k + 2] is the source at z[k]
+    ia = intensity(z)
+    out = np.empty(nodes)
+    out[0] = ia[0]
+    base = reading.lstrip("c")
+    for k in range(1, nodes):
+        yMM, yM, yO, yP = S[k], S[k + 1], S[k + 2], S[k + 3]
+        e, psi_m, psi_o, om_m, om_o, om_c = orc.coefficients(h)
+        cO = yO - 0.5 * h * fritsch_butland(yM, yO, yP, h, h)
+        cM = yM + 0.5 * h * fritsch_butland(yMM, yM, yO, h, h)
+        c = {"bezier_o": cO, "bezier_m": cM, "bezier_mo": 0.5 * (cO + cM)}[base]
+        if reading.startswith("c"):
+            c = min(max(c, min(yM, yO)), max(yM, yO))
+        out[k] = e * out[k - 1] + om_m * yM + om_o * yO + om_c * c
+    return float(np.max(np.abs((out - ia) / ia)))
