@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--control", default="besser", choices=["besser", "parabolic"],
                     help="control point of the Bezier step: BESSER or the parabolic "
                          "(DELOPAR) rule (sweep only, with --no-adjoint)")
+    ap.add_argument("--faces", action="store_true",
+                    help="M and P on the first face of the grid each ray crosses, vertical "
+                         "ones included (sweep only, with --no-adjoint)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1,
                     help="row tiles per XCD per round (-1: the library default)")
@@ -109,6 +112,7 @@ KERNEL_SYMBOLS = {
     "k_adjoint_gather<float>": "_ZN5porta16k_adjoint_gatherIfEEvNS_10GatherArgsIT_EE",
     "k_sweep_plane<float, 1>": "_ZN5porta13k_sweep_planeIfLi1EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_i<float>": "_ZN5porta15k_sweep_plane_iIfEEvNS_9PlaneArgsIT_EE",
+    "k_sweep_plane_faces<float>": "_ZN5porta19k_sweep_plane_facesIfEEvNS_9FacesArgsIT_EE",
 }
 
 
@@ -268,14 +272,16 @@ def main():
                                                           device=dev)
     hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
-    variant = (args.interp != "bilinear" or args.stokes != 4 or args.control != "besser")
+    variant = (args.interp != "bilinear" or args.stokes != 4 or args.control != "besser"
+               or args.faces)
     if variant and not args.no_adjoint:
-        sys.exit("--interp, --stokes and --control time the sweep alone: add --no-adjoint")
+        sys.exit("--interp, --stokes, --control and --faces time the sweep alone: add "
+                 "--no-adjoint")
     interp = porta.BEZIER2D if args.interp == "bezier2d" else porta.BILINEAR
     control = porta.CONTROL_PARABOLIC if args.control == "parabolic" else porta.CONTROL_BESSER
     nst = args.stokes
     opts = porta.options(ray_batch=args.ray_batch, block=args.block, xcd_remap=args.xcd_remap,
-                         control=control, stokes=nst)
+                         control=control, stokes=nst, faces=int(args.faces))
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
     adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block,
                              xcd_remap=args.xcd_remap)
@@ -466,6 +472,7 @@ def main():
     achieved = lbytes / (launch_ms * 1e-3) / 1e9
     tname = "float" if elem == 4 else "double"
     kname = (f"k_sweep_plane_i<{tname}>" if nst == 1 else
+             f"k_sweep_plane_faces<{tname}>" if args.faces else
              f"k_sweep_plane<{tname}, {1 if interp == porta.BEZIER2D else 0}>")
     workload = counter_workload(cfg, args.prec, schedule, nrb,
                                 inter.range_rays if inter else 0)
@@ -560,6 +567,7 @@ def main():
         b64 = (cfg.nz - 1) * sum(sweep_launch_bytes(cfg, n, 8, nst)[0] for n in shapes64) / n64
         a64 = b64 / (ms64 / n64 * 1e-3) / 1e9
         k64name = ("k_sweep_plane_i<double>" if nst == 1 else
+                   "k_sweep_plane_faces<double>" if args.faces else
                    f"k_sweep_plane<double, {1 if interp == porta.BEZIER2D else 0}>")
         c64 = (measured_counters(k64name, counter_workload(cfg, "f64", "shared", nrb, 0))
                if args.block in (0, 256) and args.xcd_remap == -1 else None)
@@ -636,7 +644,8 @@ def main():
                                + "".join(f", {v}" for v, on in (
                                    ("9-point Bezier interpolation", interp == porta.BEZIER2D),
                                    ("unpolarized (intensity only)", nst == 1),
-                                   ("parabolic control point", args.control == "parabolic"))
+                                   ("parabolic control point", args.control == "parabolic"),
+                                   ("M and P on the first face crossed", args.faces))
                                    if on),
                    "updates_per_step": fwd_updates + adj_updates,
                    "forward_updates": fwd_updates, "adjoint_updates": adj_updates,

@@ -153,6 +153,17 @@ typedef struct {
                                if not.  The check reads the fields once and waits on the
                                stream for its result (so it cannot be captured in a HIP
                                graph); 0 (default): no check, no wait */
+  int32_t faces;            /* where the points M and P of a short characteristic lie
+                               (Sect. 3.1): 0 (default) on the neighbouring horizontal
+                               planes, however far the ray travels sideways in between;
+                               1 on the first face of the grid the ray crosses, horizontal
+                               or vertical, interpolated bilinearly on that face.  A
+                               vertical face makes the nodes of a plane depend on each
+                               other around the periodic box; each plane is then solved to
+                               its fixed point (to the rounding of the sweep precision).
+                               With 1: Stokes vector, PORTA_INTERP_BILINEAR, no
+                               checkpoints, nx and ny <= 512; porta_fs_adjoint returns
+                               PORTA_EUNSUPPORTED */
 } porta_options;
 
 typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;

@@ -12,6 +12,7 @@
 
 #include "../../include/porta.h"
 #include "porta_adjoint.hpp"
+#include "porta_faces.hpp"
 #include "porta_host.hpp"
 #include "porta_kernels.hpp"
 #include "porta_unpol.hpp"
@@ -134,7 +135,30 @@ int validate_options(const porta_options* o) {
     return fail(PORTA_EINVAL, "ray_first and ray_count must be >= 0");
   if (o->check_inputs != 0 && o->check_inputs != 1)
     return fail(PORTA_EINVAL, "check_inputs must be 0 or 1");
+  if (o->faces != 0 && o->faces != 1) return fail(PORTA_EINVAL, "faces must be 0 or 1");
   return PORTA_OK;
+}
+
+bool faces_of(const porta_options* o) { return o && o->faces == 1; }
+
+// Lanes of a block of the first-face kernel (the columns of a plane in either frame)
+// and the frequencies it holds: as many as its LDS (kFacesLds) has room for, at most
+// faces_chunk, spread evenly over the chunks; 0 if even one does not fit.
+void faces_shape(const porta_grid* g, const porta_quad* q, int prec, int& lanes, int& fchunk) {
+  const int n = std::max(g->nx, g->ny);
+  lanes = (n + 63) / 64 * 64;
+  const bool f32 = prec == PORTA_F32;
+  const size_t base = f32 ? faces_lds_bytes<float>(q->nfreq, 0, lanes)
+                          : faces_lds_bytes<double>(q->nfreq, 0, lanes);
+  const size_t per = (f32 ? faces_lds_bytes<float>(q->nfreq, 1, lanes)
+                          : faces_lds_bytes<double>(q->nfreq, 1, lanes)) - base;
+  const size_t cap = f32 ? faces_chunk<float>() : faces_chunk<double>();
+  const size_t fit = kFacesLds > base ? (kFacesLds - base) / per : 0;
+  fchunk = (int)std::min<size_t>({cap, fit, (size_t)q->nfreq});
+  if (fchunk > 0) {
+    const int nchunk = (q->nfreq + fchunk - 1) / fchunk;
+    fchunk = (q->nfreq + nchunk - 1) / nchunk;
+  }
 }
 
 int validate_rays(const porta_quad* q, const porta_options* o) {
@@ -181,6 +205,7 @@ struct Layout {
   size_t jpart;
   // adjoint: checkpoints, recompute slots, Lambda ping-pong, per-ray partials, gradient
   size_t ck, slots, lamA, lamB, go, gm, gp, grad;
+  size_t tf;               // first-face sweep: transposed transfer coefficients
   size_t plane;            // bytes of one plane state of a ray batch
   int nck, nslot;
   size_t total;
@@ -216,6 +241,17 @@ Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const po
   off = align_up(off + state);
   L.jpart = off;
   off = align_up(off + 2 * nrb * 5 * np * sizeof(double));   // double-buffered partial sums
+  if (faces_of(o)) {
+    // per-chunk partial sums of the first-face kernel
+    int lanes, fchunk;
+    faces_shape(g, q, prec, lanes, fchunk);
+    const size_t nchunk = fchunk > 0 ? (q->nfreq + fchunk - 1) / fchunk : 1;
+    L.ck = off;
+    off = align_up(off + nrb * nchunk * 5 * np * sizeof(double));
+    // the transfer coefficients with x and y exchanged in every plane
+    L.tf = off;
+    off = align_up(off + 13 * np * g->nz * elem(prec));
+  }
   L.total = off;
   return L;
 }
@@ -325,6 +361,107 @@ int check_inputs(const porta_grid* g, const porta_fields* f, char* ws, const Lay
 }
 
 // ---------------------------------------------------------------------------
+// Forward sweep with M and P on the first face crossed (options.faces = 1)
+// ---------------------------------------------------------------------------
+template <class T>
+int sweep_faces_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
+                     const porta_options* o, double* jkq, T* itop, char* ws, const Layout& L,
+                     const RayConsts* rays, const T* phiT, const double* wn, T* state[2],
+                     hipStream_t st) {
+  int rc;
+  const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
+  const size_t N = (size_t)np * nz;
+  const int nh = q->nmu * q->nchi;
+  const int nrb_max = ray_batch(q, o);
+  int lanes, fchunk;
+  faces_shape(g, q, sizeof(T) == 4 ? PORTA_F32 : PORTA_F64, lanes, fchunk);
+  const int nchunk = (q->nfreq + fchunk - 1) / fchunk;
+  double* jpart = reinterpret_cast<double*>(ws + L.jpart);
+  double* jchunk = reinterpret_cast<double*>(ws + L.ck);
+  const size_t lds = faces_lds_bytes<T>(q->nfreq, fchunk, lanes);
+  const dim3 rblk(256), rgrid((np + 255) / 256);
+  // rays that meet an x face first read the fields with x and y exchanged
+  T* tf = reinterpret_cast<T*>(ws + L.tf);
+  {
+    const T* src[3] = {static_cast<const T*>(f->kappa), static_cast<const T*>(f->propmat),
+                       static_cast<const T*>(f->emis)};
+    const size_t nfield[3] = {1, 6, 6}, dst[3] = {0, N, 7 * N};
+    for (int c = 0; c < 3; ++c) {
+      const size_t n = nfield[c] * N;
+      hipLaunchKernelGGL(k_transpose_planes<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                         st, src[c], tf + dst[c], nx, ny, nfield[c] * nz);
+      if ((rc = check_launch("transpose_planes"))) return rc;
+    }
+  }
+  for (int hemi = 0; hemi < 2; ++hemi) {
+    const bool up = (hemi == 0);
+    const int kb = up ? 0 : nz - 1, s = up ? 1 : -1;
+    const T ibound = up ? (T)f->i_bottom : T(0);
+    int lo, hi;
+    hemi_range(q, o, hemi, lo, hi);
+    for (int r0 = lo; r0 < hi; r0 += nrb_max) {
+      const int nrb = std::min(nrb_max, hi - r0);
+      const int ray0 = hemi * nh + r0;
+      if (jkq) {
+        // the boundary plane
+        hipLaunchKernelGGL(k_jreduce, rgrid, rblk, 0, st, jkq, (const double*)nullptr, rays,
+                           ray0, nrb, np, N, (size_t)kb * np, 1, (double)ibound);
+        if ((rc = check_launch("jreduce (boundary)"))) return rc;
+      }
+      const T* prev = nullptr;
+      for (int step = 1; step < nz; ++step) {
+        const int k = kb + s * step;
+        const bool last = (step == nz - 1);
+        FacesArgs<T> a;
+        a.kappa = static_cast<const T*>(f->kappa);
+        a.prop = static_cast<const T*>(f->propmat);
+        a.emis = static_cast<const T*>(f->emis);
+        a.kappa_t = tf;
+        a.prop_t = tf + N;
+        a.emis_t = tf + 7 * N;
+        a.rays = rays;
+        a.phi = phiT;
+        a.wn = wn;
+        a.iprev = prev;
+        a.top = last && up && itop;
+        a.inext = a.top ? itop + (size_t)r0 * q->nfreq * np * 4 : state[step & 1];
+        a.jchunk = jkq ? jchunk : nullptr;
+        a.N = N;
+        a.nx = nx;
+        a.ny = ny;
+        a.np = np;
+        a.nfreq = q->nfreq;
+        a.fchunk = fchunk;
+        a.nchunk = nchunk;
+        a.kO = k;
+        a.kM = k - s;
+        a.kP = last ? -1 : k + s;
+        a.dzM = std::fabs(g->z[k] - g->z[k - s]);
+        a.dzP = last ? 0.0 : std::fabs(g->z[k + s] - g->z[k]);
+        a.inv_dx = nx / g->lx;
+        a.inv_dy = ny / g->ly;
+        a.ray0 = ray0;
+        a.parabolic = parabolic_of(o);
+        a.tol = sizeof(T) == 4 ? 1e-9 : 1e-18;
+        a.ibound = ibound;
+        hipLaunchKernelGGL(k_sweep_plane_faces<T>, dim3(nchunk, nrb), dim3(lanes), lds, st, a);
+        if ((rc = check_launch("sweep_plane_faces"))) return rc;
+        if (jkq) {
+          hipLaunchKernelGGL(k_sum_chunks, dim3((np + 255) / 256, nrb), dim3(256), 0, st, jpart,
+                             (const double*)jchunk, nrb, nchunk, np);
+          if ((rc = check_launch("sum_chunks"))) return rc;
+          hipLaunchKernelGGL(k_jreduce, rgrid, rblk, 0, st, jkq, (const double*)jpart, rays,
+                             ray0, nrb, np, N, (size_t)k * np, 0, 0.0);
+          if ((rc = check_launch("jreduce"))) return rc;
+        }
+        prev = a.inext;
+      }
+    }
+  }
+  return PORTA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Forward sweep
 // ---------------------------------------------------------------------------
 template <class T>
@@ -347,6 +484,8 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
   const T* phiT = reinterpret_cast<const T*>(ws + L.phiT);
   const double* wn = reinterpret_cast<const double*>(ws + L.wn);
   T* state[2] = {reinterpret_cast<T*>(ws + L.stateA), reinterpret_cast<T*>(ws + L.stateB)};
+  if (faces_of(o))
+    return sweep_faces_impl<T>(g, q, f, o, jkq, itop, ws, L, rays, phiT, wn, state, st);
   double* jpart[2] = {nullptr, nullptr};
   if (jkq) {
     jpart[0] = reinterpret_cast<double*>(ws + L.jpart);
@@ -644,6 +783,18 @@ int sweep_entry(const porta_grid* grid, const porta_quad* quad, const porta_fiel
   if (checkpoints && interp != PORTA_INTERP_BILINEAR)
     return fail(PORTA_EUNSUPPORTED,
                 "checkpoints are for the adjoint, which differentiates the bilinear sweep");
+  if (faces_of(opts)) {
+    if (nstokes(opts) == 1 || interp != PORTA_INTERP_BILINEAR || checkpoints)
+      return fail(PORTA_EUNSUPPORTED,
+                  "faces = 1 is for the bilinear Stokes-vector sweep without checkpoints");
+    if (std::max(grid->nx, grid->ny) > kFacesMaxLanes)
+      return fail(PORTA_EUNSUPPORTED, "faces = 1 needs nx, ny <= %d", kFacesMaxLanes);
+    int lanes, fchunk;
+    faces_shape(grid, quad, prec, lanes, fchunk);
+    if (fchunk < 1)
+      return fail(PORTA_EUNSUPPORTED, "faces = 1: %d frequencies leave no room in LDS",
+                  quad->nfreq);
+  }
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");
   if (checkpoints) {
@@ -814,6 +965,8 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
   if ((rc = validate_options(opts)) || (rc = validate_rays(quad, opts))) return rc;
   if (nstokes(opts) == 1)
     return fail(PORTA_EUNSUPPORTED, "the adjoint is for the Stokes-vector sweep");
+  if (faces_of(opts))
+    return fail(PORTA_EUNSUPPORTED, "the adjoint differentiates the plane-hop sweep (faces = 0)");
   if (checkpoints) {
     const size_t need = checkpoint_bytes(grid, quad, prec, checkpoint_stride, opts);
     if (ck_bytes < need)

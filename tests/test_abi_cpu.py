@@ -337,3 +337,32 @@ def test_checkpoints_rejected_with_the_bezier_mode():
                             None, None, 0, None, dummy.ctypes.data, 1 << 40, 4,
                             dummy.ctypes.data, 1 << 40, None) == porta.EUNSUPPORTED
     assert "bilinear" in L.porta_last_error().decode()
+
+
+def test_faces_option_checks():
+    """options.faces = 1 (M and P on the first face crossed): bilinear Stokes-vector sweep
+    only, no checkpoints, no adjoint, nx and ny up to 512; other values rejected."""
+    L = porta.lib()
+    hg = small_hg()
+    dummy = np.zeros(8)
+    f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
+
+    def sweep(opts, interp=porta.BILINEAR, ck=False, g=hg):
+        return L.porta_fs_sweep(C.byref(g.grid), C.byref(g.quad), C.byref(f), 0, interp,
+                                C.byref(opts), None, 0, None, dummy.ctypes.data if ck else None,
+                                1 << 40, 4, dummy.ctypes.data, 1 << 40, None)
+
+    assert sweep(porta.options(faces=2)) == porta.EINVAL
+    assert sweep(porta.options(faces=1), interp=porta.BEZIER2D) == porta.EUNSUPPORTED
+    assert sweep(porta.options(faces=1, stokes=1)) == porta.EUNSUPPORTED
+    assert sweep(porta.options(faces=1), ck=True) == porta.EUNSUPPORTED
+    assert sweep(porta.options(faces=1), g=small_hg(nx=520)) == porta.EUNSUPPORTED
+    assert "512" in L.porta_last_error().decode()
+    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0,
+                              porta.BILINEAR, C.byref(porta.options(faces=1)),
+                              dummy.ctypes.data, None, 0, 4, dummy.ctypes.data,
+                              dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1 << 40,
+                              None) == porta.EUNSUPPORTED
+    # the per-chunk partial sums of J enlarge the workspace
+    assert (porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, porta.options(faces=1))
+            > porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, porta.options()))
