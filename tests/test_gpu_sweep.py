@@ -52,6 +52,26 @@ def test_sweep_ragged_grid_batches_and_blocks(orc, prec, ray_batch, block):
     compare_jkq(jkq, ref["jkq"], tol_i, "jkq")
 
 
+@pytest.mark.parametrize("ray_batch, block", [(0, 256), (5, 64), (3, 192)])
+def test_sweep_rows_of_whole_wavefronts(orc, ray_batch, block):
+    """nx a multiple of 64 (128x3 planes, lx != ly, unequal z steps): the FP32 kernel
+    takes the x + 1 corners of the upwind stencil from the next lane, the last lane's
+    from a wavefront-uniform load; the wrap of the stencil around x falls inside a
+    wavefront for the shifted rays, and blocks of 192 threads put row boundaries
+    between wavefronts of one block."""
+    cfg = inputs.Config("rows64", 128, 3, 7, 2, 4, 3, True)
+    atm = inputs.make_atmosphere(cfg, seed=12)
+    z = np.cumsum(np.r_[0.0, np.random.default_rng(13).uniform(30.0, 120.0, cfg.nz - 1)])
+    atm = rounded(dataclasses.replace(atm, lx=1700.0, ly=90.0, z=z), np.float32)
+    q = inputs.make_quadrature(cfg)
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q))
+    jkq, itop = Case(atm, q, porta.F32).sweep(opts=porta.options(ray_batch=ray_batch,
+                                                                  block=block))
+    ei, ep = compare_stokes(itop, up_rays(ref["itop"], q), 2e-5, 1e-7, "itop")
+    ej = compare_jkq(jkq, ref["jkq"], 2e-5, "jkq")
+    print(f"128x3 FP32 block {block}: I {ei:.2e}, Q/I.. {ep:.2e}, J {ej:.2e}")
+
+
 @pytest.mark.parametrize("prec", [porta.F64, porta.F32])
 @pytest.mark.parametrize("scale", [1e-7, 1e3])
 def test_extreme_optical_depths(orc, prec, scale):
