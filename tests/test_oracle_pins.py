@@ -487,6 +487,52 @@ def test_homogeneous_dichroic_slab_converges_to_matrix_exponential(orc):
     assert np.all(errs[:-1] / errs[1:] > 3.0)   # second order
 
 
+def _magneto_optical_column(orc, nz, r):
+    """A column, vertical ray, no emission, I = (1, 0, 0, 0) at the bottom: dichroism
+    (eta_Q, eta_U, eta_V) below z = 0.3 polarizes the beam, above it only the
+    magneto-optical entries rho = r kappa act.  Returns P/I at the first node above the
+    interval where the two mix and at the top, and the optical path between them."""
+    z = np.linspace(0.0, 1.0, nz)
+    kap = 3.0
+    low = z <= 0.3
+    prop = np.zeros((6, nz))
+    prop[0:3, low] = (np.array([0.5, 0.3, 0.2]) * kap)[:, None]
+    prop[3:6, ~low] = (np.asarray(r) * kap)[:, None]
+    atm = mk_atm(1, 1, nz, 1, 1, z, np.full(nz, kap), prop=prop, i_bottom=1.0)
+    full = orc.fs_sweep(orc.OracleProblem(atm, mk_quad([1.0], [1.0], 1)), rays=[0],
+                        want_full=True)["ifull"][0, 0]
+    ent = int(np.argmax(z > 0.3)) + 1
+    return full[ent, 1:] / full[ent, 0], full[-1, 1:] / full[-1, 0], kap * (z[-1] - z[ent])
+
+
+def test_magneto_optical_block_rotates_polarization_about_rho(orc):
+    """With only rho_Q, rho_U, rho_V (relative to eta_I) the transfer equation for
+    P = (Q, U, V) e^tau is a rotation about the vector r = rho / eta_I by the angle
+    |r| tau (right-handed for the layout of reading A15): P.r and |P|/I are conserved
+    and P/I at the top is the Rodrigues rotation of its value on entry.  The
+    discretization conserves P.r exactly and the rest converges at second order; the
+    opposite sense of rotation, or a rho entry in the wrong place of the matrix, misses
+    by far more."""
+    from scipy.spatial.transform import Rotation
+    r = np.array([0.6, -0.4, 0.9])
+    rh = r / np.linalg.norm(r)
+    errs = []
+    for nz in (201, 401):
+        pe, pt, tau = _magneto_optical_column(orc, nz, r)
+        assert np.linalg.norm(pe) > 0.4                     # the beam is polarized
+        assert abs(pt @ rh - pe @ rh) < 1e-12
+        want = Rotation.from_rotvec(r * tau).apply(pe)
+        errs.append(np.abs(pt - want).max())
+        assert abs(np.linalg.norm(pt) - np.linalg.norm(pe)) < 2 * errs[-1] + 1e-15
+        # rotated by more than 2 rad: the other sense lands far away
+        assert np.abs(pt - Rotation.from_rotvec(-r * tau).apply(pe)).max() > 0.1
+    assert errs[1] < 2e-5 and errs[0] / errs[1] > 3.5
+    # any single rho moved to another place breaks the conserved axis
+    for perm in ([1, 0, 2], [0, 2, 1], [2, 1, 0]):
+        pe, pt, _ = _magneto_optical_column(orc, 201, r[perm])
+        assert abs(pt @ rh - pe @ rh) > 1e-3
+
+
 def test_linear_source_eddington_barbier(orc):
     """S = a + b tau_z in a plane-parallel, horizontally homogeneous slab: I(mu) = a + b mu."""
     nz = 40
