@@ -45,8 +45,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--ray-batch", type=int, default=40,
-                    help="rays swept together in the forward sweep and in the adjoint")
+    ap.add_argument("--ray-batch", type=int, default=None,
+                    help="rays swept together in the forward sweep and in the adjoint "
+                         "(default 40; with --faces 0, every ray of a hemisphere)")
     ap.add_argument("--adjoint-ray-batch", type=int, default=0,
                     help="rays per batch in the adjoint (default: --ray-batch)")
     ap.add_argument("--checkpoint-stride", type=int, default=11,
@@ -72,6 +73,9 @@ def parse():
     ap.add_argument("--faces", action="store_true",
                     help="M and P on the first face of the grid each ray crosses, vertical "
                          "ones included (sweep only, with --no-adjoint)")
+    ap.add_argument("--faces-chunk", type=int, default=0,
+                    help="with --faces: frequencies per block of the first-face kernel "
+                         "(0: as many as its LDS holds)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1,
                     help="row tiles per XCD per round (-1: the library default)")
@@ -82,7 +86,12 @@ def parse():
                     help="copy 1 GiB device-to-device first (counter calibration for profiles)")
     ap.add_argument("--cpu-pairs", type=int, default=48,
                     help="(ray, frequency) pairs of the workload swept by the CPU oracle")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.ray_batch is None:
+        # the first-face kernel's blocks are (ray, frequency chunk) pairs over a whole
+        # plane: a hemisphere's rays in one launch fill the chip
+        args.ray_batch = 0 if args.faces else 40
+    return args
 
 
 def sweep_launch_bytes(cfg, nrb, elem, nst=4):
@@ -281,7 +290,8 @@ def main():
     control = porta.CONTROL_PARABOLIC if args.control == "parabolic" else porta.CONTROL_BESSER
     nst = args.stokes
     opts = porta.options(ray_batch=args.ray_batch, block=args.block, xcd_remap=args.xcd_remap,
-                         control=control, stokes=nst, faces=int(args.faces))
+                         control=control, stokes=nst, faces=int(args.faces),
+                         faces_chunk=args.faces_chunk)
     nrb = min(args.ray_batch, cfg.nmu * cfg.nchi) if args.ray_batch > 0 else cfg.nmu * cfg.nchi
     adj_opts = porta.options(ray_batch=args.adjoint_ray_batch or args.ray_batch, block=args.block,
                              xcd_remap=args.xcd_remap)
@@ -477,7 +487,7 @@ def main():
     workload = counter_workload(cfg, args.prec, schedule, nrb,
                                 inter.range_rays if inter else 0)
     counters = (measured_counters(kname, workload) if args.block in (0, 256)
-                and args.xcd_remap == -1 else None)
+                and args.xcd_remap == -1 and args.faces_chunk == 0 else None)
     traffic = None if counters is None else counters["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -570,7 +580,8 @@ def main():
                    "k_sweep_plane_faces<double>" if args.faces else
                    f"k_sweep_plane<double, {1 if interp == porta.BEZIER2D else 0}>")
         c64 = (measured_counters(k64name, counter_workload(cfg, "f64", "shared", nrb, 0))
-               if args.block in (0, 256) and args.xcd_remap == -1 else None)
+               if args.block in (0, 256) and args.xcd_remap == -1 and args.faces_chunk == 0
+               else None)
         extra["fp64_roofline"] = {
             "bound": "hbm", "kernel": k64name, "achieved": round(a64, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(a64 / HBM_PEAK_GBS, 4),

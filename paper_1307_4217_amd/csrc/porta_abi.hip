@@ -136,15 +136,18 @@ int validate_options(const porta_options* o) {
   if (o->check_inputs != 0 && o->check_inputs != 1)
     return fail(PORTA_EINVAL, "check_inputs must be 0 or 1");
   if (o->faces != 0 && o->faces != 1) return fail(PORTA_EINVAL, "faces must be 0 or 1");
+  if (o->faces_chunk < 0) return fail(PORTA_EINVAL, "faces_chunk must be >= 0");
   return PORTA_OK;
 }
 
 bool faces_of(const porta_options* o) { return o && o->faces == 1; }
 
 // Lanes of a block of the first-face kernel (the columns of a plane in either frame)
-// and the frequencies it holds: as many as its LDS (kFacesLds) has room for, at most
-// faces_chunk, spread evenly over the chunks; 0 if even one does not fit.
-void faces_shape(const porta_grid* g, const porta_quad* q, int prec, int& lanes, int& fchunk) {
+// and the frequencies it holds: the options' faces_chunk if it fits, else as many as
+// its LDS (kFacesLds) has room for, at most faces_chunk<T>(), spread evenly over the
+// chunks; 0 if they do not fit.
+void faces_shape(const porta_grid* g, const porta_quad* q, int prec, const porta_options* o,
+                 int& lanes, int& fchunk) {
   const int n = std::max(g->nx, g->ny);
   lanes = (n + 63) / 64 * 64;
   const bool f32 = prec == PORTA_F32;
@@ -154,6 +157,11 @@ void faces_shape(const porta_grid* g, const porta_quad* q, int prec, int& lanes,
                           : faces_lds_bytes<double>(q->nfreq, 1, lanes)) - base;
   const size_t cap = f32 ? faces_chunk<float>() : faces_chunk<double>();
   const size_t fit = kFacesLds > base ? (kFacesLds - base) / per : 0;
+  if (o && o->faces_chunk > 0) {
+    const int want = std::min(o->faces_chunk, q->nfreq);
+    fchunk = (size_t)want <= fit ? want : 0;
+    return;
+  }
   fchunk = (int)std::min<size_t>({cap, fit, (size_t)q->nfreq});
   if (fchunk > 0) {
     const int nchunk = (q->nfreq + fchunk - 1) / fchunk;
@@ -206,6 +214,7 @@ struct Layout {
   // adjoint: checkpoints, recompute slots, Lambda ping-pong, per-ray partials, gradient
   size_t ck, slots, lamA, lamB, go, gm, gp, grad;
   size_t tf;               // first-face sweep: transposed transfer coefficients
+  size_t fcache;           // first-face sweep: set-up of the nodes of a plane
   size_t plane;            // bytes of one plane state of a ray batch
   int nck, nslot;
   size_t total;
@@ -244,13 +253,16 @@ Layout sweep_layout(const porta_grid* g, const porta_quad* q, int prec, const po
   if (faces_of(o)) {
     // per-chunk partial sums of the first-face kernel
     int lanes, fchunk;
-    faces_shape(g, q, prec, lanes, fchunk);
+    faces_shape(g, q, prec, o, lanes, fchunk);
     const size_t nchunk = fchunk > 0 ? (q->nfreq + fchunk - 1) / fchunk : 1;
     L.ck = off;
     off = align_up(off + nrb * nchunk * 5 * np * sizeof(double));
     // the transfer coefficients with x and y exchanged in every plane
     L.tf = off;
     off = align_up(off + 13 * np * g->nz * elem(prec));
+    // the set-up of every node and ray of one plane
+    L.fcache = off;
+    off = align_up(off + nrb * kFacesCache * np * elem(prec));
   }
   L.total = off;
   return L;
@@ -374,7 +386,7 @@ int sweep_faces_impl(const porta_grid* g, const porta_quad* q, const porta_field
   const int nh = q->nmu * q->nchi;
   const int nrb_max = ray_batch(q, o);
   int lanes, fchunk;
-  faces_shape(g, q, sizeof(T) == 4 ? PORTA_F32 : PORTA_F64, lanes, fchunk);
+  faces_shape(g, q, sizeof(T) == 4 ? PORTA_F32 : PORTA_F64, o, lanes, fchunk);
   const int nchunk = (q->nfreq + fchunk - 1) / fchunk;
   double* jpart = reinterpret_cast<double*>(ws + L.jpart);
   double* jchunk = reinterpret_cast<double*>(ws + L.ck);
@@ -444,6 +456,9 @@ int sweep_faces_impl(const porta_grid* g, const porta_quad* q, const porta_field
         a.parabolic = parabolic_of(o);
         a.tol = sizeof(T) == 4 ? 1e-9 : 1e-18;
         a.ibound = ibound;
+        a.cache = reinterpret_cast<T*>(ws + L.fcache);
+        hipLaunchKernelGGL(k_faces_setup<T>, dim3((np + 255) / 256, nrb), dim3(256), 0, st, a);
+        if ((rc = check_launch("faces_setup"))) return rc;
         hipLaunchKernelGGL(k_sweep_plane_faces<T>, dim3(nchunk, nrb), dim3(lanes), lds, st, a);
         if ((rc = check_launch("sweep_plane_faces"))) return rc;
         if (jkq) {
@@ -790,10 +805,10 @@ int sweep_entry(const porta_grid* grid, const porta_quad* quad, const porta_fiel
     if (std::max(grid->nx, grid->ny) > kFacesMaxLanes)
       return fail(PORTA_EUNSUPPORTED, "faces = 1 needs nx, ny <= %d", kFacesMaxLanes);
     int lanes, fchunk;
-    faces_shape(grid, quad, prec, lanes, fchunk);
+    faces_shape(grid, quad, prec, opts, lanes, fchunk);
     if (fchunk < 1)
-      return fail(PORTA_EUNSUPPORTED, "faces = 1: %d frequencies leave no room in LDS",
-                  quad->nfreq);
+      return fail(PORTA_EUNSUPPORTED, "faces = 1: the LDS of a block has no room for %s",
+                  opts->faces_chunk > 0 ? "faces_chunk frequencies" : "one frequency");
   }
   if (checkpoints && (checkpoint_stride < 1 || checkpoint_stride > grid->nz - 1))
     return fail(PORTA_EINVAL, "checkpoint_stride must be in 1..nz-1");

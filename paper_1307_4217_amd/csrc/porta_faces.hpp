@@ -14,13 +14,15 @@
 // consecutive addresses) from the previous row (kept in LDS) and the upwind plane.  A
 // ray that reaches an x = const face before a y = const one is solved on a transposed
 // copy of the transfer coefficients (its own plane states transposed too), so that its
-// in-plane dependencies also run from row to row.  The march starts m rows early: the part of I_M taken from plane k carries the weight 1 - t_z per
+// in-plane dependencies also run from row to row.  The march starts m rows early: the
+// part of I_M taken from plane k carries the weight 1 - t_z per
 // step (t_z the fraction of the layer the ray descends while crossing a cell), and the
 // rest of the update is a contraction, so after m >= ln(tol)/ln(1 - t_z) steps the
-// starting guess no longer shows at the working precision and the remaining columns
-// are the fixed point.  Frequency-independent work (interpolation of the transfer
-// coefficients on the faces, S, K', control points) is done once per node, ray and
-// frequency chunk.
+// starting guess no longer shows at the working precision and the remaining rows are
+// the fixed point.  The frequency-independent work (interpolation of the transfer
+// coefficients on the faces, S, K', control points, in FP64) is done once per node and
+// ray by a parallel kernel before the march, which reads its results in the sweep
+// precision as rows of a plane-sized table.
 #pragma once
 
 #include "porta_kernels.hpp"
@@ -148,6 +150,7 @@ struct FacesArgs {
   int top;           // inext is I_top: nodes in the stored frame
   double* jchunk;    // [ray][chunk][5][node] (stored frame): per frequency chunk,
                      // sum_j W_j I_i and sum_j W_j Lambda*
+  T* cache;          // [ray][kFacesCache][node] (working frame): the set-up of each node
   size_t N;
   int nx, ny, np, nfreq, fchunk, nchunk;
   int kO, kM, kP;    // plane of O, upwind plane, downwind plane (-1: none)
@@ -159,10 +162,21 @@ struct FacesArgs {
   T ibound;
 };
 
-// frequencies per block, at most (LDS sets the actual number)
+// Values of the set-up of a node and ray that the march reads, in the sweep precision:
+// K'_M / eta_I entries (eta 3, rho 3), K'_O (3, 3), S_M (4), S_O (4), c_M (4), the
+// optical depth tau_MO at line centre and the Lambda* factor of omega_C.
+enum FacesCacheSlot {
+  kCeM = 0, kCrM = 3, kCeO = 6, kCrO = 9, kCSM = 12, kCSO = 16, kCcM = 20, kCtau = 24,
+  kClf = 25, kFacesCache = 26
+};
+
+// frequencies per block, at most (LDS may set fewer).  Small chunks give more blocks
+// (the launch is nchunk x rays of them, of unequal lengths) and more blocks per CU; the
+// set-up table is read once per chunk.  At 256x256x128, 80 rays and 101 frequencies in
+// FP32, chunks of 4, 6, 8, 11 and 15 took 14.3, 13.5, 14.2, 16.1 and 17.1 ms per launch.
 template <class T>
 __host__ __device__ constexpr int faces_chunk() {
-  return sizeof(T) == 4 ? 32 : 16;
+  return sizeof(T) == 4 ? 6 : 7;
 }
 constexpr int kFacesMaxLanes = 512;  // columns of a plane held by one block
 constexpr size_t kFacesLds = 65536;  // LDS of one block, at most
@@ -246,6 +260,45 @@ __device__ inline void setup_point_faces(const T* __restrict__ kappa, const T* _
   }
 }
 
+// The frequency-independent set-up of every node of plane kO (working frame) for every
+// ray of the batch (blockIdx.y), in FP64, stored in the sweep precision.
+template <class T>
+__global__ void __launch_bounds__(256) k_faces_setup(const FacesArgs<T> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, rb = blockIdx.y;
+  if (p >= a.np) return;
+  const RayConsts& rc = a.rays[a.ray0 + rb];
+  const Frame fr = ray_frame(rc, a.nx, a.ny, a.inv_dx, a.inv_dy);
+  const T* kappa = fr.tr ? a.kappa_t : a.kappa;
+  const T* prop = fr.tr ? a.prop_t : a.prop;
+  const T* emis = fr.tr ? a.emis_t : a.emis;
+  const FaceGeom gM = face_geom(rc.mu, fr, -1, a.dzM);
+  const bool hasP = a.kP >= 0;
+  const FaceGeom gP = hasP ? face_geom(rc.mu, fr, +1, a.dzP) : gM;
+  const int i = p % fr.nx, j = p / fr.nx;
+  const FaceStencil sM = face_stencil(gM, i, j, fr.nx, fr.ny);
+  const FaceStencil sP = hasP ? face_stencil(gP, i, j, fr.nx, fr.ny) : sM;
+  PointSetup ps;
+  setup_point_faces(kappa, prop, emis, a, rc, gM, sM, gP, sP, hasP, p, ps);
+  const double lamfac = hasP ? control_cm(0.0, 1.0, 0.0, ps.ratio, a.parabolic != 0) : 0.5;
+  const size_t np = (size_t)a.np;
+  T* c = a.cache + (size_t)rb * kFacesCache * np + p;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c[(kCeM + k) * np] = (T)(ps.etaM[k] * ps.ikM);
+    c[(kCrM + k) * np] = (T)(ps.etaM[3 + k] * ps.ikM);
+    c[(kCeO + k) * np] = (T)(ps.etaO[k] * ps.ikO);
+    c[(kCrO + k) * np] = (T)(ps.etaO[3 + k] * ps.ikO);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    c[(kCSM + s) * np] = (T)ps.SM[s];
+    c[(kCSO + s) * np] = (T)ps.SO[s];
+    c[(kCcM + s) * np] = (T)ps.cM[s];
+  }
+  c[kCtau * np] = (T)ps.tau0M;
+  c[kClf * np] = (T)lamfac;
+}
+
 // One plane for one ray (blockIdx.y) and one chunk of frequencies (blockIdx.x).  Lanes
 // are the columns of the working frame; the block walks its rows.  Each lane keeps its
 // own column's Stokes vectors of the previous row in LDS and reads the neighbouring
@@ -272,13 +325,10 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
   const int nf = min(a.fchunk, a.nfreq - f0);
   const RayConsts& rc = a.rays[a.ray0 + rb];
   const Frame fr = ray_frame(rc, a.nx, a.ny, a.inv_dx, a.inv_dy);
-  const T* kappa = fr.tr ? a.kappa_t : a.kappa;
-  const T* prop = fr.tr ? a.prop_t : a.prop;
-  const T* emis = fr.tr ? a.emis_t : a.emis;
   const FaceGeom gM = face_geom(rc.mu, fr, -1, a.dzM);
-  const bool hasP = a.kP >= 0;
-  const FaceGeom gP = hasP ? face_geom(rc.mu, fr, +1, a.dzP) : gM;
   const bool chain = gM.kind != 0;   // same for the whole block
+  const size_t np = (size_t)a.np;
+  const T* cache = a.cache + (size_t)rb * kFacesCache * np;
   const int lane = threadIdx.x, wave = lane >> 6;
   const bool active = lane < fr.nx;
   const int nstep = fr.ny;
@@ -343,27 +393,20 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
       const int p = j * fr.nx + i;                         // working frame
       const int po = fr.tr ? i * a.nx + j : p;            // stored frame
       const FaceStencil sM = face_stencil(gM, i, j, fr.nx, fr.ny);
-      const FaceStencil sP = hasP ? face_stencil(gP, i, j, fr.nx, fr.ny) : sM;
-      PointSetup ps;
-      setup_point_faces(kappa, prop, emis, a, rc, gM, sM, gP, sP, hasP, p, ps);
-      const double lamfac = hasP ? control_cm(0.0, 1.0, 0.0, ps.ratio, a.parabolic != 0) : 0.5;
-      const T eMv[3] = {(T)(ps.etaM[0] * ps.ikM), (T)(ps.etaM[1] * ps.ikM),
-                        (T)(ps.etaM[2] * ps.ikM)};
-      const T rMv[3] = {(T)(ps.etaM[3] * ps.ikM), (T)(ps.etaM[4] * ps.ikM),
-                        (T)(ps.etaM[5] * ps.ikM)};
-      const T eOv[3] = {(T)(ps.etaO[0] * ps.ikO), (T)(ps.etaO[1] * ps.ikO),
-                        (T)(ps.etaO[2] * ps.ikO)};
-      const T rOv[3] = {(T)(ps.etaO[3] * ps.ikO), (T)(ps.etaO[4] * ps.ikO),
-                        (T)(ps.etaO[5] * ps.ikO)};
+      const T* cp = cache + p;
+      const T eMv[3] = {cp[(kCeM + 0) * np], cp[(kCeM + 1) * np], cp[(kCeM + 2) * np]};
+      const T rMv[3] = {cp[(kCrM + 0) * np], cp[(kCrM + 1) * np], cp[(kCrM + 2) * np]};
+      const T eOv[3] = {cp[(kCeO + 0) * np], cp[(kCeO + 1) * np], cp[(kCeO + 2) * np]};
+      const T rOv[3] = {cp[(kCrO + 0) * np], cp[(kCrO + 1) * np], cp[(kCrO + 2) * np]};
       const StokesOp<T> KO = stokes_op(eOv, rOv);
       T SMt[4], SOt[4], cMt[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        SMt[s] = (T)ps.SM[s];
-        SOt[s] = (T)ps.SO[s];
-        cMt[s] = (T)ps.cM[s];
+        SMt[s] = cp[(kCSM + s) * np];
+        SOt[s] = cp[(kCSO + s) * np];
+        cMt[s] = cp[(kCcM + s) * np];
       }
-      const T tau0 = (T)ps.tau0M, lf = (T)lamfac;
+      const T tau0 = cp[kCtau * np], lf = cp[kClf * np];
       const T w0 = (T)sM.w[0], w1 = (T)sM.w[1], w2 = (T)sM.w[2], w3 = (T)sM.w[3];
       const T* r0 = (c_bnd[0] ? s_bnd + rd : s_row) + c_off[0];
       const T* r1 = (c_bnd[1] ? s_bnd + rd : s_row) + c_off[1];

@@ -47,7 +47,7 @@ class Options(C.Structure):
     _fields_ = [("ray_batch", C.c_int32), ("block", C.c_int32), ("xcd_remap", C.c_int32),
                 ("control", C.c_int32), ("stokes", C.c_int32), ("ray_first", C.c_int32),
                 ("ray_count", C.c_int32), ("check_inputs", C.c_int32),
-                ("faces", C.c_int32)]
+                ("faces", C.c_int32), ("faces_chunk", C.c_int32)]
 
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ENONFINITE = 0, -1, -2, -3, -4, -5
@@ -174,15 +174,17 @@ class HostGrid:
 
 
 def options(ray_batch=0, block=0, xcd_remap=-1, control=0, stokes=4, ray_first=0,
-            ray_count=0, check_inputs=False, faces=0):
+            ray_count=0, check_inputs=False, faces=0, faces_chunk=0):
     """porta_options; control = CONTROL_BESSER or CONTROL_PARABOLIC; stokes = 4 (Stokes
     vector) or 1 (intensity only, the unpolarized problem); rays [ray_first,
     ray_first + ray_count) of the enumeration (ray_count 0: every ray); check_inputs: the
     sweep and the adjoint first check that the coefficients are finite and eta_I > 0
     (waits on the stream; PORTA_ENONFINITE otherwise); faces = 1: M and P on the first
-    face of the grid the ray crosses (0: on the neighbouring horizontal planes)."""
+    face of the grid the ray crosses (0: on the neighbouring horizontal planes), with
+    faces_chunk frequencies per block of its kernel (0: chosen from the LDS)."""
     return Options(int(ray_batch), int(block), int(xcd_remap), int(control), int(stokes),
-                   int(ray_first), int(ray_count), int(bool(check_inputs)), int(faces))
+                   int(ray_first), int(ray_count), int(bool(check_inputs)), int(faces),
+                   int(faces_chunk))
 
 
 def workspace_size(hg: HostGrid, prec, kind, checkpoint_stride=1, opts=None) -> int:

@@ -347,10 +347,10 @@ def test_faces_option_checks():
     dummy = np.zeros(8)
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
 
-    def sweep(opts, interp=porta.BILINEAR, ck=False, g=hg):
+    def sweep(opts, interp=porta.BILINEAR, ck=False, g=hg, ws_bytes=1 << 40):
         return L.porta_fs_sweep(C.byref(g.grid), C.byref(g.quad), C.byref(f), 0, interp,
                                 C.byref(opts), None, 0, None, dummy.ctypes.data if ck else None,
-                                1 << 40, 4, dummy.ctypes.data, 1 << 40, None)
+                                1 << 40, 4, dummy.ctypes.data, ws_bytes, None)
 
     assert sweep(porta.options(faces=2)) == porta.EINVAL
     assert sweep(porta.options(faces=1), interp=porta.BEZIER2D) == porta.EUNSUPPORTED
@@ -363,6 +363,16 @@ def test_faces_option_checks():
                               dummy.ctypes.data, None, 0, 4, dummy.ctypes.data,
                               dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1 << 40,
                               None) == porta.EUNSUPPORTED
-    # the per-chunk partial sums of J enlarge the workspace
-    assert (porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, porta.options(faces=1))
-            > porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, porta.options()))
+    # the per-chunk partial sums of J enlarge the workspace, the more the smaller the chunk
+    ws = lambda o: porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, o)
+    assert ws(porta.options(faces=1)) > ws(porta.options())
+    assert ws(porta.options(faces=1, faces_chunk=1)) > ws(porta.options(faces=1))
+    # frequencies per block: >= 0, and they must fit in the LDS of a block (FP64, 512
+    # lanes: 17 KiB per frequency)
+    assert sweep(porta.options(faces=1, faces_chunk=-1)) == porta.EINVAL
+    assert sweep(porta.options(faces=1, faces_chunk=10), g=small_hg(nx=500)) == \
+        porta.EUNSUPPORTED
+    assert "faces_chunk" in L.porta_last_error().decode()
+    # three fit: the call gets past the option checks to the workspace check
+    assert sweep(porta.options(faces=1, faces_chunk=3), g=small_hg(nx=500), ws_bytes=16) == \
+        porta.ENOMEM
