@@ -122,6 +122,7 @@ KERNEL_SYMBOLS = {
     "k_sweep_plane<float, 1>": "_ZN5porta13k_sweep_planeIfLi1EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_i<float>": "_ZN5porta15k_sweep_plane_iIfEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_faces<float>": "_ZN5porta19k_sweep_plane_facesIfEEvNS_9FacesArgsIT_EE",
+    "k_faces_setup<float>": "_ZN5porta13k_faces_setupIfEEvNS_9FacesArgsIT_EE",
 }
 
 

@@ -462,8 +462,10 @@ int sweep_faces_impl(const porta_grid* g, const porta_quad* q, const porta_field
         hipLaunchKernelGGL(k_sweep_plane_faces<T>, dim3(nchunk, nrb), dim3(lanes), lds, st, a);
         if ((rc = check_launch("sweep_plane_faces"))) return rc;
         if (jkq) {
-          hipLaunchKernelGGL(k_sum_chunks, dim3((np + 255) / 256, nrb), dim3(256), 0, st, jpart,
-                             (const double*)jchunk, nrb, nchunk, np);
+          const unsigned tiles = (unsigned)((std::max(nx, ny) + kSumTile - 1) / kSumTile);
+          hipLaunchKernelGGL(k_sum_chunks, dim3(tiles, tiles, nrb), dim3(256), 0, st, jpart,
+                             (const double*)jchunk, rays, ray0, nchunk, nx, ny, nx / g->lx,
+                             ny / g->ly);
           if ((rc = check_launch("sum_chunks"))) return rc;
           hipLaunchKernelGGL(k_jreduce, rgrid, rblk, 0, st, jkq, (const double*)jpart, rays,
                              ray0, nrb, np, N, (size_t)k * np, 0, 0.0);

@@ -148,7 +148,7 @@ struct FacesArgs {
                      // working frame), or nullptr: the boundary
   T* inext;          // states of plane k, same layout
   int top;           // inext is I_top: nodes in the stored frame
-  double* jchunk;    // [ray][chunk][5][node] (stored frame): per frequency chunk,
+  double* jchunk;    // [ray][chunk][5][node] (working frame): per frequency chunk,
                      // sum_j W_j I_i and sum_j W_j Lambda*
   T* cache;          // [ray][kFacesCache][node] (working frame): the set-up of each node
   size_t N;
@@ -472,8 +472,8 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
       }
       if (store && jc) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) jc[(size_t)s * a.np + po] = jacc[s];
-        jc[4 * (size_t)a.np + po] = lacc;
+        for (int s = 0; s < 4; ++s) jc[(size_t)s * a.np + p] = jacc[s];
+        jc[4 * (size_t)a.np + p] = lacc;
       }
     }
     // the row is complete (and its copies for the other waves) before the next reads it
@@ -495,18 +495,48 @@ __global__ void __launch_bounds__(256)
 }
 
 // Sum the frequency-chunk partials of every ray into the per-ray layout of the J
-// reduction: jpart[ray][5][node] = sum_chunk jchunk[ray][chunk][5][node].
+// reduction, from the ray's working frame to the grid's own: jpart[ray][5][node] =
+// sum_chunk jchunk[ray][chunk][5][working node].  A block takes a 32 x 32 tile of the
+// working frame (blockIdx.x, blockIdx.y over a square of the larger side) for one ray
+// (blockIdx.z) and writes it through LDS, so that both the reads and, for a ray
+// solved with x and y exchanged, the transposed writes are coalesced.
+constexpr int kSumTile = 32;
+
 __global__ void __launch_bounds__(256)
-    k_sum_chunks(double* __restrict__ jpart, const double* __restrict__ jchunk, int nrb,
-                 int nchunk, int np) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int rb = blockIdx.y;
-  if (p >= np) return;
+    k_sum_chunks(double* __restrict__ jpart, const double* __restrict__ jchunk,
+                 const RayConsts* __restrict__ rays, int ray0, int nchunk, int nx, int ny,
+                 double inv_dx, double inv_dy) {
+  __shared__ double tile[kSumTile][kSumTile + 1];
+  const int rb = blockIdx.z;
+  const Frame fr = ray_frame(rays[ray0 + rb], nx, ny, inv_dx, inv_dy);
+  const int x0 = blockIdx.x * kSumTile, y0 = blockIdx.y * kSumTile;
+  if (x0 >= fr.nx || y0 >= fr.ny) return;   // the same for the whole block
+  const size_t np = (size_t)nx * ny;
+  const int tx = threadIdx.x % kSumTile, ty = threadIdx.x / kSumTile;   // 32 x 8
   for (int c = 0; c < 5; ++c) {
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k)
-      s += jchunk[(((size_t)rb * nchunk + k) * 5 + c) * np + p];
-    jpart[((size_t)rb * 5 + c) * np + p] = s;
+    for (int r = ty; r < kSumTile; r += 8) {
+      const int xw = x0 + tx, yw = y0 + r;
+      double sum = 0.0;
+      if (xw < fr.nx && yw < fr.ny) {
+        const size_t pw = (size_t)yw * fr.nx + xw;
+        for (int k = 0; k < nchunk; ++k)
+          sum += jchunk[(((size_t)rb * nchunk + k) * 5 + c) * np + pw];
+      }
+      tile[r][tx] = sum;
+    }
+    __syncthreads();
+    double* out = jpart + ((size_t)rb * 5 + c) * np;
+    for (int r = ty; r < kSumTile; r += 8) {
+      if (!fr.tr) {
+        const int xw = x0 + tx, yw = y0 + r;
+        if (xw < fr.nx && yw < fr.ny) out[(size_t)yw * nx + xw] = tile[r][tx];
+      } else {
+        // stored (x, y) = working (y, x): consecutive lanes take consecutive stored x
+        const int yw = y0 + tx, xw = x0 + r;
+        if (xw < fr.nx && yw < fr.ny) out[(size_t)xw * nx + yw] = tile[tx][r];
+      }
+    }
+    __syncthreads();
   }
 }
 
