@@ -96,6 +96,8 @@ __device__ inline FaceGeom face_geom(double mu, const Frame& fr, int dir, double
 struct FaceStencil {
   int n[4];
   double w[4];
+  double a, b;    // the same as two linear steps: a between nodes 0, 1 (and 2, 3), b from
+                  // the pair 0, 1 to the pair 2, 3
   bool inplane;   // nodes 0 and 1 lie on plane k itself
 };
 
@@ -105,6 +107,10 @@ __device__ inline FaceStencil face_stencil(const FaceGeom& g, int i, int j, int 
     const Stencil b = make_stencil(i, j, nx, ny, g.u, g.v);
     s.n[0] = b.i00; s.n[1] = b.i10; s.n[2] = b.i01; s.n[3] = b.i11;
     s.w[0] = b.w00; s.w[1] = b.w10; s.w[2] = b.w01; s.w[3] = b.w11;
+    // the fractions of the cell, reduced as make_stencil reduces them
+    const double u = g.u - nx * floor(g.u / nx), v = g.v - ny * floor(g.v / ny);
+    s.a = u - floor(u);
+    s.b = v - floor(v);
     s.inplane = false;
     return s;
   }
@@ -121,6 +127,8 @@ __device__ inline FaceStencil face_stencil(const FaceGeom& g, int i, int j, int 
   s.w[1] = f * (1.0 - g.tz);
   s.w[2] = (1.0 - f) * g.tz;
   s.w[3] = f * g.tz;
+  s.a = f;
+  s.b = g.tz;
   return s;
 }
 
@@ -407,7 +415,10 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
         cMt[s] = cp[(kCcM + s) * np];
       }
       const T tau0 = cp[kCtau * np], lf = cp[kClf * np];
-      const T w0 = (T)sM.w[0], w1 = (T)sM.w[1], w2 = (T)sM.w[2], w3 = (T)sM.w[3];
+      // I_M as two linear steps (x, then z or y): a field constant over the stencil is
+      // returned exactly, so the rounding of the four weights, the same for every node
+      // of a ray, adds no bias that the many cell steps of an inclined ray would pile up
+      const T fa = (T)sM.a, fb = (T)sM.b;
       const T* r0 = (c_bnd[0] ? s_bnd + rd : s_row) + c_off[0];
       const T* r1 = (c_bnd[1] ? s_bnd + rd : s_row) + c_off[1];
       T* own = s_row + 4 * (size_t)lane;
@@ -431,8 +442,11 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
           load4(r0 + (size_t)f * c_str[0], c0);
           load4(r1 + (size_t)f * c_str[1], c1);
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            IM[s] = w0 * c0[s] + w1 * c1[s] + w2 * up[0][s] + w3 * up[1][s];
+          for (int s = 0; s < 4; ++s) {
+            const T A = c0[s] + fa * (c1[s] - c0[s]);
+            const T B = up[0][s] + fa * (up[1][s] - up[0][s]);
+            IM[s] = A + fb * (B - A);
+          }
         } else {
           T v0[4], v1[4];
           if (ip) {
@@ -444,17 +458,26 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
             for (int s = 0; s < 4; ++s) v0[s] = v1[s] = up[0][s];
           }
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            IM[s] = w0 * v0[s] + w1 * v1[s] + w2 * up[0][s] + w3 * up[1][s];
+          for (int s = 0; s < 4; ++s) {
+            const T A = v0[s] + fa * (v1[s] - v0[s]);
+            const T B = up[0][s] + fa * (up[1][s] - up[0][s]);
+            IM[s] = A + fb * (B - A);
+          }
         }
         const T tau = tau0 * s_phi[fg];
-        const Coefs<T> cf = coefficients(tau);
+        const Coefs<T> cf = coefficients<true>(tau);
         T KI[4], b[4], res[4];
         kprime_apply(eMv, rMv, IM, KI);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          b[s] = cf.e * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] +
-                 cf.omC * cMt[s];
+        for (int s = 0; s < 4; ++s) {
+          // e I_M as I_M - (1 - e) I_M (see Coefs::em1), and the change of a step summed
+          // before it is added to I_M: on thin steps each term alone can fall below half
+          // a unit in the last place of I_M, and dropping the source terms while keeping
+          // the attenuation would bias a long chain of steps
+          const T d = -cf.em1 * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] +
+                      cf.omC * cMt[s];
+          b[s] = IM[s] + d;
+        }
         stokes_solve<1>(KO, stokes_freq(KO, cf.psiO), b, res);
         if (chain) {
           store4(own + (size_t)f * lanes * 4, res);

@@ -46,6 +46,10 @@ __host__ __device__ inline double recip(double x) { return 1.0 / x; }
 template <class T>
 struct Coefs {
   T e, psiM, psiO, omM, omO, omC;
+  T em1;             // 1 - e to the relative precision of T, formed on request (EM1 of
+                     // coefficients), for an update written as I_M - em1 I_M: e itself,
+                     // rounded next to 1 in FP32, is off by up to 3e-8 for thin steps, a
+                     // bias that a chain of thousands of steps would add up
   T pmt, omt, oct;   // psi'_M / tau, omega_M / tau, omega_C / tau (for the tau-derivatives)
 };
 
@@ -66,6 +70,7 @@ __host__ __device__ inline T series(T tau, const T (&c)[NT]) {
 // (from 1/(n!(n+2)) = 1/(n+1)! - 1/(n+2)!, 1/(n!(n+3)) = 1/(n+1)! - 2/(n+2)! + 2/(n+3)!
 // and 2/(n!(n+2)(n+3)) = 2/(n+2)! - 4/(n+3)!), so ten terms of E_3 and the downward
 // recurrence (stable for t < 1.2) give every coefficient within 1e-6 relative.
+template <bool EM1 = false>
 __host__ __device__ inline Coefs<float> coefficients(float tau) {
   Coefs<float> c;
   if (tau < 1.2f) {
@@ -78,6 +83,7 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
     const float E2 = 0.5f - tau * E3;
     const float E1 = 1.0f - tau * E2;
     c.e = 1.0f - tau * E1;
+    if constexpr (EM1) c.em1 = tau * E1;
     c.pmt = E1 - E2;
     c.omt = E1 + 2.0f * (E3 - E2);
     c.oct = 2.0f * E2 - 4.0f * E3;
@@ -88,6 +94,7 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
     c.omC = tau * c.oct;
   } else {
     c.e = exp_neg(tau);
+    if constexpr (EM1) c.em1 = 1.0f - c.e;
     const float it = recip(tau), it2 = it * it;
     const float g = c.e + tau - 1.0f;               // e + tau - 1
     c.psiO = g * it;
@@ -102,6 +109,7 @@ __host__ __device__ inline Coefs<float> coefficients(float tau) {
   return c;
 }
 
+template <bool EM1 = false>
 __host__ __device__ inline Coefs<double> coefficients(double tau) {
   // eight terms, identical to the rows of Table 1 for the omegas
   const double kPM[8] = {1.0 / 2, -1.0 / 3, 1.0 / 8, -1.0 / 30, 1.0 / 144, -1.0 / 840,
@@ -116,6 +124,7 @@ __host__ __device__ inline Coefs<double> coefficients(double tau) {
                          1.0 / 25920, -1.0 / 226800};
   Coefs<double> c;
   c.e = exp_neg(tau);
+  if constexpr (EM1) c.em1 = 1.0 - c.e;   // FP64: the same bias is 1e-16 per step
   const double it = 1.0 / tau, it2 = it * it;
   if (tau < 0.1) {
     c.psiM = series(tau, kPM);

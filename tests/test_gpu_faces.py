@@ -121,3 +121,34 @@ def test_first_face_sweep_equals_plane_hops_where_every_face_is_horizontal():
     torch.cuda.synchronize()
     np.testing.assert_allclose(it1, it0, rtol=1e-13, atol=1e-15 * np.abs(it0).max())
     np.testing.assert_allclose(j1, j0, rtol=1e-13, atol=1e-15 * np.abs(j0).max())
+
+
+def test_first_face_sweep_full_size_sampled(orc):
+    """256x256x128, 160 rays, 101 frequencies, in the launch configuration the benchmark
+    times (a hemisphere of rays per launch, the default frequency chunks): I_top over the
+    whole top surface for 8 upward rays (the most inclined ones meeting x faces and y
+    faces, intermediate ones, steep ones whose first face is the plane below) at line
+    centre and in the wing, FP32 and FP64 sweeps of the same FP32-rounded inputs against
+    the oracle's first-face mode on those pairs."""
+    torch = require_gpu()
+    cfg = inputs.CONFIGS["C3"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    rays, freqs = [0, 4, 17, 21, 38, 55, 64, 75], [50, 10]
+    kinds = _face_kinds(atm, q)[rays]
+    assert {0, 1, 2} <= set(kinds.tolist())
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, faces=1), rays=rays, freqs=freqs,
+                       want_j=False)["itop"]
+    print("  oracle done", flush=True)
+    for prec, tol_i, tol_p in ((porta.F32, 2e-5, 1e-7), (porta.F64, 1e-10, 1e-12)):
+        case = Case(atm, q, prec)
+        _, itop = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                                 atm.w2, prec=prec, want_jkq=False,
+                                 opts=porta.options(faces=1))
+        got = itop[rays][:, freqs].cpu().numpy().astype(np.float64)
+        name = "FP32" if prec == porta.F32 else "FP64"
+        ei, ep = compare_stokes(got, ref, tol_i, tol_p, f"faces C3 {name}")
+        print(f"first-face sweep C3 {name}, {len(rays)} rays x {len(freqs)} frequencies x "
+              f"{cfg.nx * cfg.ny} top points: I {ei:.2e}, Q/I.. {ep:.2e}", flush=True)
+        del case, itop
+        torch.cuda.empty_cache()
