@@ -117,8 +117,8 @@ def adjoint_launch_bytes(cfg, nrb, elem):
 KERNEL_SYMBOLS = {
     "k_sweep_plane<float, 0>": "_ZN5porta13k_sweep_planeIfLi0EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane<double, 0>": "_ZN5porta13k_sweep_planeIdLi0EEEvNS_9PlaneArgsIT_EE",
-    "k_adjoint_plane<float>": "_ZN5porta15k_adjoint_planeIfEEvNS_7AdjArgsIT_EE",
-    "k_adjoint_gather<float>": "_ZN5porta16k_adjoint_gatherIfEEvNS_10GatherArgsIT_EE",
+    "k_adjoint_plane<float, 0>": "_ZN5porta15k_adjoint_planeIfLi0EEEvNS_7AdjArgsIT_EE",
+    "k_adjoint_gather<float, 0>": "_ZN5porta16k_adjoint_gatherIfLi0EEEvNS_10GatherArgsIT_EE",
     "k_sweep_plane<float, 1>": "_ZN5porta13k_sweep_planeIfLi1EEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_i<float>": "_ZN5porta15k_sweep_plane_iIfEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_faces<float>": "_ZN5porta19k_sweep_plane_facesIfEEvNS_9FacesArgsIT_EE",
@@ -515,7 +515,7 @@ def main():
         abytes = (cfg.nz - 1) * sum(adjoint_launch_bytes(cfg, n, elem)[0]
                                     for n in ashapes) / alaunches
         alaunch_ms = adj_ms / alaunches
-        aname = f"k_adjoint_plane<{'float' if elem == 4 else 'double'}>"
+        aname = f"k_adjoint_plane<{'float' if elem == 4 else 'double'}, 0>"
         acounters = (measured_counters(aname, workload) if args.block in (0, 256)
                      and args.xcd_remap == -1 else None)
         # The adjoint kernel is bound by its vector ALU: its rate is the VALU instructions

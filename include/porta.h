@@ -199,9 +199,10 @@ size_t porta_checkpoint_size(const porta_grid* grid, const porta_quad* quad, int
  *   checkpoints   : device, porta_checkpoint_size() bytes, or NULL; filled with
  *                   the upward rays' states every checkpoint_stride planes for a
  *                   later porta_fs_adjoint of the same fields (no extra traffic:
- *                   those planes are written there instead of the workspace).
- *                   Only with PORTA_INTERP_BILINEAR (the interpolation the adjoint
- *                   differentiates); PORTA_EUNSUPPORTED otherwise
+ *                   those planes are written there instead of the workspace),
+ *                   with the same interp (the states of a 9-point sweep are not
+ *                   those of a bilinear one: the adjoint cannot tell which mode wrote
+ *                   them, so matching them is the caller's to ensure)
  *   checkpoint_bytes : size of that buffer; below porta_checkpoint_size() the
  *                   call returns PORTA_ENOMEM before any launch
  *   workspace     : device, >= porta_workspace_size(..., PORTA_WS_SWEEP, ...)
@@ -338,7 +339,8 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * Reverse-mode derivative of a scalar loss L(i_top) through the sweep of the
  * upward rays, i.e. of the formal solution of Sect. 3.3 (Eqs. fsbez and kappa, the
  * BESSER or parabolic control point of Sect. 3.2, Table 1 for small tau_MO, the
- * bilinear interpolation of Sect. 3.1): given dL/d i_top (same layout and precision
+ * interpolation at M and P of Sect. 3.1 that interp names): given dL/d i_top (same
+ * layout and precision
  * as i_top), adds
  * dL/dkappa, dL/dpropmat and dL/demis (each in the layout of its field, in
  * the sweep precision) to g_kappa [N], g_propmat [6][N], g_emis [6][N].
@@ -356,8 +358,11 @@ int porta_rel_change(int64_t npoints, const double* s_new, const double* s_old, 
  * frequencies in the sweep precision, taken through the node's set-up (interpolation,
  * S = eps/eta_I, K', control point) in FP64, stored between launches in the sweep
  * precision and gathered onto the coefficients in FP64.
- * Only interp = PORTA_INTERP_BILINEAR is differentiated; PORTA_INTERP_BEZIER2D
- * returns PORTA_EUNSUPPORTED.
+ * With PORTA_INTERP_BEZIER2D the derivatives of the 9-point monotonic Bezier follow
+ * the branches of its clamps at the interpolated values (they depend on the values
+ * around each point, so the adjoint of the Stokes vectors of a plane is gathered from
+ * the plane above through the transposed stencils in a launch of its own, reading the
+ * forward states of that plane; the coefficients likewise).
  */
 int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta_fields* fields,
                      int prec, int interp, const porta_options* opts, const void* dl_ditop,

@@ -36,6 +36,10 @@ float hm_bezier3_f32(float ym, float y0, float yp, float t) {
   return porta::bezier3(ym, y0, yp, t);
 }
 
+double hm_bezier3_grad_f64(double ym, double y0, double yp, double t, double* g3) {
+  return porta::bez_eval_grad(porta::bez_weights(t), ym, y0, yp, g3);
+}
+
 void hm_solve_stokes_f64(const double* e3, const double* r3, const double* b4, double* x4) {
   porta::solve_stokes(e3, r3, b4, x4);
 }

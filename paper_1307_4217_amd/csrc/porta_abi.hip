@@ -590,8 +590,8 @@ int sweep_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f, 
 // ---------------------------------------------------------------------------
 template <class T>
 int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* f,
-                  const porta_options* o, char* ws, const Layout& L, int k, const T* prev, T* next,
-                  int ray0, int nrb, int block, hipStream_t st) {
+                  const porta_options* o, int interp, char* ws, const Layout& L, int k,
+                  const T* prev, T* next, int ray0, int nrb, int block, hipStream_t st) {
   const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
   PlaneArgs<T> a;
   a.kappa = static_cast<const T*>(f->kappa);
@@ -623,15 +623,19 @@ int forward_plane(const porta_grid* g, const porta_quad* q, const porta_fields* 
   a.parabolic = parabolic_of(o);
   a.ibound = (T)f->i_bottom;
   const size_t lds = (size_t)q->nfreq * (sizeof(double) + sizeof(T));
-  hipLaunchKernelGGL((k_sweep_plane<T, 0>), dim3((np + block - 1) / block, nrb), dim3(block), lds,
-                     st, a);
+  if (interp == PORTA_INTERP_BEZIER2D)
+    hipLaunchKernelGGL((k_sweep_plane<T, 1>), dim3((np + block - 1) / block, nrb), dim3(block),
+                       lds, st, a);
+  else
+    hipLaunchKernelGGL((k_sweep_plane<T, 0>), dim3((np + block - 1) / block, nrb), dim3(block),
+                       lds, st, a);
   return check_launch("sweep_plane (adjoint recompute)");
 }
 
 template <class T>
 int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f,
-                 const porta_options* o, const T* seed, const T* ext_ck, int C, T* gk, T* gpm,
-                 T* ge, char* ws, const Layout& L, hipStream_t st) {
+                 const porta_options* o, int interp, const T* seed, const T* ext_ck, int C, T* gk,
+                 T* gpm, T* ge, char* ws, const Layout& L, hipStream_t st) {
   int rc;
   if ((rc = prepare_tables<T>(ws, L, q, f->w2, st))) return rc;
   const int nx = g->nx, ny = g->ny, nz = g->nz, np = nx * ny;
@@ -667,8 +671,8 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
     // segment
     if (!ext_ck)
       for (int k = 1; k <= C * checkpoint_count(nz, C); ++k)
-        if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
-                                   st)))
+        if ((rc = forward_plane<T>(g, q, f, o, interp, ws, L, k, plane(k - 1), plane(k), r0,
+                                   nrb, block, st)))
           return rc;
     // reverse pass, one segment between checkpoints at a time
     const T* lam_next = nullptr;
@@ -679,8 +683,8 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
       // plane of a segment needs no state
       for (int k = s0 + 1; k < khi; ++k)
         if (!is_checkpoint(k, nz, C))
-          if ((rc = forward_plane<T>(g, q, f, o, ws, L, k, plane(k - 1), plane(k), r0, nrb, block,
-                                     st)))
+          if ((rc = forward_plane<T>(g, q, f, o, interp, ws, L, k, plane(k - 1), plane(k), r0,
+                                     nrb, block, st)))
             return rc;
       for (int k = khi; k > s0; --k) {
         AdjArgs<T> a;
@@ -713,13 +717,44 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         a.xcd_remap = xcd_chunk(o);
         a.parabolic = parabolic_of(o);
         a.ibound = (T)f->i_bottom;
-        hipLaunchKernelGGL(k_adjoint_plane<T>, dim3((np + block - 1) / block, nrb), dim3(block),
-                           lds_adj, st, a);
+        const bool bez = interp == PORTA_INTERP_BEZIER2D;
+        if (bez && lam_next) {
+          // the adjoint of the Stokes vectors of plane k, gathered through the transposed
+          // 9-point stencils of plane k + 1, into the buffer the adjoint of plane k then
+          // reads as its seed and overwrites, node by node, with its own output
+          TGatherArgs<T> t;
+          t.icur = plane(k);
+          t.lam_next = lam_next;
+          t.out = lam[cur];
+          t.rays = a.rays;
+          t.nx = nx;
+          t.ny = ny;
+          t.np = np;
+          t.nfreq = q->nfreq;
+          t.dzN = a.dzN;
+          t.inv_dx = a.inv_dx;
+          t.inv_dy = a.inv_dy;
+          t.ray0 = r0;
+          hipLaunchKernelGGL(k_bez9_tgather<T>, dim3((np + 255) / 256, nrb), dim3(256), 0, st, t);
+          if ((rc = check_launch("bez9_tgather"))) return rc;
+          a.lam_next = nullptr;
+          a.seed = lam[cur];
+          a.lam_cur = (k - 1 >= 1) ? lam[cur] : nullptr;
+        }
+        if (bez)
+          hipLaunchKernelGGL((k_adjoint_plane<T, 1>), dim3((np + block - 1) / block, nrb),
+                             dim3(block), lds_adj, st, a);
+        else
+          hipLaunchKernelGGL((k_adjoint_plane<T, 0>), dim3((np + block - 1) / block, nrb),
+                             dim3(block), lds_adj, st, a);
         if ((rc = check_launch("adjoint_plane"))) return rc;
         GatherArgs<T> b;
         b.g_o = a.g_o;
         b.g_m = a.g_m;
         b.g_p = a.g_p;
+        b.kappa = a.kappa;
+        b.prop = a.prop;
+        b.emis = a.emis;
         b.rays = a.rays;
         b.grad = grad;
         b.N = N;
@@ -735,7 +770,12 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
         b.inv_dy = a.inv_dy;
         b.ray0 = r0;
         b.nrb = nrb;
-        hipLaunchKernelGGL(k_adjoint_gather<T>, dim3((np + 255) / 256, 4), dim3(256), 0, st, b);
+        if (bez)
+          hipLaunchKernelGGL((k_adjoint_gather<T, 1>), dim3((np + 255) / 256, 4), dim3(256), 0, st,
+                             b);
+        else
+          hipLaunchKernelGGL((k_adjoint_gather<T, 0>), dim3((np + 255) / 256, 4), dim3(256), 0, st,
+                             b);
         if ((rc = check_launch("adjoint_gather"))) return rc;
         lam_next = a.lam_cur;
         cur ^= 1;
@@ -797,9 +837,6 @@ int sweep_entry(const porta_grid* grid, const porta_quad* quad, const porta_fiel
     return fail(PORTA_EUNSUPPORTED, "the intensity-only sweep interpolates bilinearly only");
   if (nstokes(opts) == 1 && checkpoints)
     return fail(PORTA_EUNSUPPORTED, "checkpoints are for the Stokes-vector sweep");
-  if (checkpoints && interp != PORTA_INTERP_BILINEAR)
-    return fail(PORTA_EUNSUPPORTED,
-                "checkpoints are for the adjoint, which differentiates the bilinear sweep");
   if (faces_of(opts)) {
     if (nstokes(opts) == 1 || interp != PORTA_INTERP_BILINEAR || checkpoints)
       return fail(PORTA_EUNSUPPORTED,
@@ -990,8 +1027,6 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
       return fail(PORTA_ENOMEM, "checkpoint buffer of %zu bytes is smaller than the %zu required",
                   ck_bytes, need);
   }
-  if (interp != PORTA_INTERP_BILINEAR)
-    return fail(PORTA_EUNSUPPORTED, "this interpolation mode is not available in the adjoint");
   if (!workspace) return fail(PORTA_EINVAL, "workspace is NULL");
   const Layout L = adjoint_layout(grid, quad, prec, checkpoint_stride, opts, !checkpoints);
   if (ws_bytes < L.total)
@@ -1004,11 +1039,13 @@ int porta_fs_adjoint(const porta_grid* grid, const porta_quad* quad, const porta
                                 : check_inputs<float>(grid, fields, ws, L, st)))
     return rc;
   if (prec == PORTA_F64)
-    return adjoint_impl<double>(grid, quad, fields, opts, static_cast<const double*>(dl_ditop),
+    return adjoint_impl<double>(grid, quad, fields, opts, interp,
+                                static_cast<const double*>(dl_ditop),
                                 static_cast<const double*>(checkpoints), checkpoint_stride,
                                 static_cast<double*>(g_kappa), static_cast<double*>(g_propmat),
                                 static_cast<double*>(g_emis), ws, L, st);
-  return adjoint_impl<float>(grid, quad, fields, opts, static_cast<const float*>(dl_ditop),
+  return adjoint_impl<float>(grid, quad, fields, opts, interp,
+                             static_cast<const float*>(dl_ditop),
                              static_cast<const float*>(checkpoints), checkpoint_stride,
                              static_cast<float*>(g_kappa), static_cast<float*>(g_propmat),
                              static_cast<float*>(g_emis), ws, L, st);

@@ -73,11 +73,129 @@ __device__ inline void kprime_outer(T psi, const T l[4], const T x[4], T g[6]) {
   for (int c = 0; c < 6; ++c) g[c] -= psi * q[c];
 }
 
+// Where the 9-point stencil of a displacement (u, v) in cells sits, as make_stencil9
+// places it: the centre is the node (fu, fv) away, the point at (tx, ty) from it.
+struct Bez9Geom {
+  int fu, fv;
+  double tx, ty;
+};
+
+__device__ inline Bez9Geom bez9_geom(double u, double v, int nx, int ny) {
+  u -= nx * floor(u / nx);
+  v -= ny * floor(v / ny);
+  Bez9Geom g;
+  const double fu = floor(u + 0.5), fv = floor(v + 0.5);
+  g.fu = (int)fu;
+  g.fv = (int)fv;
+  g.tx = u - fu;
+  g.ty = v - fv;
+  return g;
+}
+
+// Adjoint of the 9-point monotonic Bezier interpolation (x pass over three rows, then
+// y), gathered at a node q: out += sum_p dB_p / df(q) adj(p) over the nine nodes p
+// whose stencil holds q.  The stencil of p is centred (fu, fv) from p, so those p are
+// q - (fu, fv) + (cc, rc), cc, rc in {-1, 0, 1}, with their centre at (cc, rc) from q.
+// val(r, c, v) loads the K components of the interpolated field at q + (c, r), |c|,
+// |r| <= 2; adj(rc, cc, g) loads the adjoint of the interpolated value at that p.  The
+// partials follow the branches of the forward evaluation (bez_eval_grad); a node that
+// the periodic wrap puts at several places of a stencil gets the sum of its partials,
+// one per place.
+template <class T, int K, class Val, class Adj>
+__device__ inline void bez9_adjoint_gather(const BezW<T>& wx, const BezW<T>& wy, Val val,
+                                           Adj adj, T out[K]) {
+  T R[5][3][K];   // x pass of rows -2..2 (index + 2) about column centres -1, 0, 1
+  T gx[3][K];     // d R[row 0][cc] / d f(q)
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    T v[5][K];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) val(r - 2, c - 2, v[c]);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (r == 2) {
+          T g[3];
+          R[r][cc][k] = bez_eval_grad(wx, v[cc][k], v[cc + 1][k], v[cc + 2][k], g);
+          gx[cc][k] = g[2 - cc];   // q is column 0: place 2 - cc of the triple
+        } else {
+          R[r][cc][k] = bez_eval(wx, v[cc][k], v[cc + 1][k], v[cc + 2][k]);
+        }
+      }
+  }
+#pragma unroll
+  for (int rc = 0; rc < 3; ++rc)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      T ga[K];
+      adj(rc - 1, cc - 1, ga);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T g[3];
+        bez_eval_grad(wy, R[rc][cc][k], R[rc + 1][cc][k], R[rc + 2][cc][k], g);
+        out[k] += g[2 - rc] * gx[cc][k] * ga[k];   // q is row 0: place 2 - rc
+      }
+    }
+}
+
+// Adjoint of the Stokes vectors of plane kO in the 9-point mode: gathered from the
+// adjoint of I_M at the nodes of plane kO + 1 (whose M points interpolate plane kO)
+// through the transposed Bezier stencil, at every frequency.  Thread = (node, ray).
+template <class T>
+struct TGatherArgs {
+  const T* icur;       // forward state of plane kO ([ray][freq][node][4])
+  const T* lam_next;   // adjoint of I_M at the nodes of plane kO + 1, same layout
+  T* out;              // adjoint of I at the nodes of plane kO, same layout
+  const RayConsts* rays;
+  int nx, ny, np, nfreq;
+  double dzN, inv_dx, inv_dy;   // dzN = |z_{kO+1} - z_kO|
+  int ray0;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_bez9_tgather(const TGatherArgs<T> a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x, rb = blockIdx.y;
+  if (q >= a.np) return;
+  const RayConsts& rc = a.rays[a.ray0 + rb];
+  const double dsN = a.dzN / fabs(rc.mu);
+  const Bez9Geom gm = bez9_geom(-dsN * rc.sx * a.inv_dx, -dsN * rc.sy * a.inv_dy, a.nx, a.ny);
+  const BezW<T> wx = bez_weights((T)gm.tx), wy = bez_weights((T)gm.ty);
+  const int qi = q % a.nx, qj = q / a.nx;
+  int rowb[5], coli[5], prow[3], pcol[3];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    rowb[d] = wrapi(qj + d - 2, a.ny) * a.nx;
+    coli[d] = wrapi(qi + d - 2, a.nx);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    prow[d] = wrapi(qj - gm.fv + d - 1, a.ny) * a.nx;
+    pcol[d] = wrapi(qi - gm.fu + d - 1, a.nx);
+  }
+  const size_t fstride = (size_t)a.np * 4;
+  const size_t roff = (size_t)rb * a.nfreq * fstride;
+  for (int f = 0; f < a.nfreq; ++f) {
+    const T* ic = a.icur + roff + (size_t)f * fstride;
+    const T* ln = a.lam_next + roff + (size_t)f * fstride;
+    T out[4] = {T(0), T(0), T(0), T(0)};
+    bez9_adjoint_gather<T, 4>(
+        wx, wy,
+        [&](int r, int c, T v[4]) { load4(ic + 4 * (size_t)(rowb[r + 2] + coli[c + 2]), v); },
+        [&](int r, int c, T g[4]) { load4(ln + 4 * (size_t)(prow[r + 1] + pcol[c + 1]), g); },
+        out);
+    store4(a.out + roff + (size_t)f * fstride + 4 * (size_t)q, out);
+  }
+}
+
 // FP32: two waves per SIMD (256 VGPRs), which leaves room for the loads of the next
 // frequency to be in flight during the current one's arithmetic, with no spill in
 // the frequency loop; three waves without that prefetch were 13% slower, three with
 // it spill inside the loop.
-template <class T>
+// MODE 1 (9-point Bezier): the set-up and I_M as the 9-point sweep forms them; the
+// adjoint of the Stokes vectors at O comes gathered (k_bez9_tgather) in `seed`, with
+// lam_next null.
+template <class T, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 k_adjoint_plane(const AdjArgs<T> a) {
   extern __shared__ double s_tab[];
@@ -90,9 +208,11 @@ k_adjoint_plane(const AdjArgs<T> a) {
   if (p >= a.np) return;
   const RayConsts& rc = a.rays[a.ray0 + rb];
   PointSetup ps;
-  Stencil9 unused9;
-  setup_point<0>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
-                 a.dzP, a.inv_dx, a.inv_dy, rc, p, a.parabolic != 0, ps, unused9);
+  Stencil9 sM9;
+  setup_point<MODE>(a.kappa, a.prop, a.emis, a.N, a.nx, a.ny, a.np, a.kO, a.kM, a.kP, a.dzM,
+                    a.dzP, a.inv_dx, a.inv_dy, rc, p, a.parabolic != 0, ps, sM9);
+  const BezW<T> bwx = bez_weights(MODE == 1 ? (T)sM9.tx : T(0));
+  const BezW<T> bwy = bez_weights(MODE == 1 ? (T)sM9.ty : T(0));
   const int i = p % a.nx, j = p / a.nx;
   const double inv_mu = 1.0 / fabs(rc.mu);
   // nodes of the plane above whose upwind stencil contains p
@@ -149,7 +269,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
       } else {
         load4(sp + fo, c.l[0]);
       }
-      if constexpr (HI) {
+      if constexpr (HI && MODE == 0) {
         load4(ip + fo + 4 * (size_t)ps.sM.i00, c.m[0]);
         load4(ip + fo + 4 * (size_t)ps.sM.i10, c.m[1]);
         load4(ip + fo + 4 * (size_t)ps.sM.i01, c.m[2]);
@@ -168,7 +288,9 @@ k_adjoint_plane(const AdjArgs<T> a) {
         for (int s = 0; s < 4; ++s) lam[s] = c.l[0][s];
       }
       T IM[4];
-      if constexpr (HI) {
+      if constexpr (HI && MODE == 1) {
+        upwind_bez9(ip + fo, sM9, bwx, bwy, IM);
+      } else if constexpr (HI) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           IM[s] = w00 * c.m[0][s] + w10 * c.m[1][s] + w01 * c.m[2][s] + w11 * c.m[3][s];
@@ -356,11 +478,14 @@ struct GatherArgs {
   int kO, kM, kP;
   double dzM, dzP, inv_dx, inv_dy;
   int ray0, nrb;
+  const T* kappa;     // the coefficients (MODE 1: the Bezier partials depend on them)
+  const T* prop;
+  const T* emis;
 };
 
 // blockIdx.y: component group (0: the 13 at O; 1, 2: the 13 at M in two halves; 3: the
 // 7 at P), so that four threads share a node and each stencil is built once per group.
-template <class T>
+template <class T, int MODE>
 __global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs<T> a) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
@@ -388,14 +513,54 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(const GatherArgs<T> a) {
     const double inv_mu = 1.0 / fabs(rc.mu);
     const double ds = (atM ? a.dzM : a.dzP) * inv_mu;
     const double sds = atM ? -ds : ds;   // M upwind, P downwind, as in the sweep
-    const Stencil t = make_tstencil(i, j, a.nx, a.ny, sds * rc.sx * a.inv_dx,
-                                    sds * rc.sy * a.inv_dy);
     const T* gb = atM ? a.g_m + ((size_t)rb * 13 + c0) * np : a.g_p + (size_t)rb * 7 * np;
+    if constexpr (MODE == 0) {
+      const Stencil t = make_tstencil(i, j, a.nx, a.ny, sds * rc.sx * a.inv_dx,
+                                      sds * rc.sy * a.inv_dy);
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      if (c < nc) {
+      for (int c = 0; c < 7; ++c) {
+        if (c < nc) {
+          const T* g = gb + c * np;
+          acc[c] += t.w00 * g[t.i00] + t.w10 * g[t.i10] + t.w01 * g[t.i01] + t.w11 * g[t.i11];
+        }
+      }
+    } else {
+      // the transposed 9-point Bezier of each coefficient, whose clamps depend on the
+      // coefficient's values around q
+      const Bez9Geom gm = bez9_geom(sds * rc.sx * a.inv_dx, sds * rc.sy * a.inv_dy, a.nx, a.ny);
+      const BezW<double> wx = bez_weights(gm.tx), wy = bez_weights(gm.ty);
+      int rowb[5], coli[5], prow[3], pcol[3];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        rowb[d] = wrapi(j + d - 2, a.ny) * a.nx;
+        coli[d] = wrapi(i + d - 2, a.nx);
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        prow[d] = wrapi(j - gm.fv + d - 1, a.ny) * a.nx;
+        pcol[d] = wrapi(i - gm.fu + d - 1, a.nx);
+      }
+      const size_t kb = (size_t)(atM ? a.kM : a.kP) * np;
+#pragma unroll 1
+      for (int c = 0; c < nc; ++c) {
+        // coefficient c of the group: M, first half kappa and propmat; M, second half
+        // emis; P: kappa and emis
+        const int cg = c0 + c;
+        const T* fld = (!atM) ? (c == 0 ? a.kappa : a.emis + (size_t)(c - 1) * a.N)
+                              : (cg == 0 ? a.kappa
+                                         : (cg < 7 ? a.prop + (size_t)(cg - 1) * a.N
+                                                   : a.emis + (size_t)(cg - 7) * a.N));
+        const T* fb = fld + kb;
         const T* g = gb + c * np;
-        acc[c] += t.w00 * g[t.i00] + t.w10 * g[t.i10] + t.w01 * g[t.i01] + t.w11 * g[t.i11];
+        double out[1] = {0.0};
+        bez9_adjoint_gather<double, 1>(
+            wx, wy,
+            [&](int r, int cc, double v[1]) { v[0] = (double)fb[rowb[r + 2] + coli[cc + 2]]; },
+            [&](int r, int cc, double w[1]) { w[0] = (double)g[prow[r + 1] + pcol[cc + 1]]; },
+            out);
+#pragma unroll
+        for (int cc = 0; cc < 7; ++cc)   // (a register array takes no run-time index)
+          if (cc == c) acc[cc] += out[0];
       }
     }
   }

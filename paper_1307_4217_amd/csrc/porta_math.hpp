@@ -247,6 +247,33 @@ __host__ __device__ inline T bez_eval(const BezW<T>& w, T ym, T y0, T yp) {
   return w.a * ym + w.b * y0 + w.c * yp + w.e * q;
 }
 
+// bez_eval with its partial derivatives g = d/d(ym, y0, yp), on the branches the value
+// takes: q = c - y0 is the clamped offset of the control point, which is 0 (with no
+// dependence) where the two differences do not share a strict sign (the extremum rule
+// of the control point), else d1, d2 or (d1 + d2)/4, whichever is smallest in size.
+template <class T>
+__host__ __device__ inline T bez_eval_grad(const BezW<T>& w, T ym, T y0, T yp, T g[3]) {
+  const T d1 = y0 - ym, d2 = yp - y0;
+  T q = T(0), q1 = T(0), q2 = T(0);   // q and its partials in d1, d2
+  if (d1 * d2 > T(0)) {
+    const T a1 = fabs(d1), a2 = fabs(d2), a3 = T(0.25) * fabs(d1 + d2);
+    if (a1 <= a2 && a1 <= a3) {
+      q = d1;
+      q1 = T(1);
+    } else if (a2 <= a3) {
+      q = d2;
+      q2 = T(1);
+    } else {
+      q = T(0.25) * (d1 + d2);
+      q1 = q2 = T(0.25);
+    }
+  }
+  g[0] = w.a - w.e * q1;
+  g[1] = w.b + w.e * (q1 - q2);
+  g[2] = w.c + w.e * q2;
+  return w.a * ym + w.b * y0 + w.c * yp + w.e * q;
+}
+
 template <class T>
 __host__ __device__ inline T bezier3(T ym, T y0, T yp, T t) {
   return bez_eval(bez_weights(t), ym, y0, yp);

@@ -127,15 +127,22 @@ def test_other_entry_points_validate():
     assert porta.lib().porta_strerror(-3) == b"workspace too small"
 
 
-def test_adjoint_rejects_bezier_mode():
+def test_adjoint_accepts_both_interpolation_modes():
+    """Both modes pass the option checks of the adjoint and reach the workspace check
+    (a workspace of 16 bytes: PORTA_ENOMEM before any launch); an unknown mode does not."""
     L = porta.lib()
     hg = small_hg()
     dummy = np.zeros(8)
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
-    assert L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0,
-                              porta.BEZIER2D, None, dummy.ctypes.data, None, 0, 4,
-                              dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data,
-                              dummy.ctypes.data, 1 << 40, None) == -2
+
+    def adj(interp):
+        return L.porta_fs_adjoint(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, interp,
+                                  None, dummy.ctypes.data, None, 0, 4, dummy.ctypes.data,
+                                  dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 16,
+                                  None)
+    assert adj(porta.BILINEAR) == porta.ENOMEM
+    assert adj(porta.BEZIER2D) == porta.ENOMEM
+    assert adj(7) == porta.EINVAL
 
 
 def test_multigrid_entry_points_validate():
@@ -169,7 +176,7 @@ def test_kernel_code_digest_found_in_built_library():
     """The benchmark keys its committed HBM counters to the machine code of the kernel."""
     import re
     import bench
-    for k in ("k_sweep_plane<float, 0>", "k_adjoint_plane<float>"):
+    for k in ("k_sweep_plane<float, 0>", "k_adjoint_plane<float, 0>"):
         d = bench.kernel_code_sha256(k)
         assert d is not None and re.fullmatch(r"[0-9a-f]{64}", d)
     assert bench.kernel_code_sha256("no such kernel") is None
@@ -325,18 +332,17 @@ def test_noalloc_sweep_validates_before_touching_the_device():
                                     None, 0, None, None) == porta.EINVAL
 
 
-def test_checkpoints_rejected_with_the_bezier_mode():
-    """The adjoint differentiates the bilinear sweep only, so a sweep in the 9-point mode
-    may not leave checkpoints for it (they would hold the states of another forward
-    model)."""
+def test_checkpoints_accepted_with_the_bezier_mode():
+    """The adjoint differentiates either mode, so a 9-point sweep may leave checkpoints
+    (for an adjoint called with the same mode): the call gets past the option checks to
+    the workspace check."""
     L = porta.lib()
     hg = small_hg()
     dummy = np.zeros(8)
     f = porta.Fields(dummy.ctypes.data, dummy.ctypes.data, dummy.ctypes.data, 1.0, 1.0)
     assert L.porta_fs_sweep(C.byref(hg.grid), C.byref(hg.quad), C.byref(f), 0, porta.BEZIER2D,
                             None, None, 0, None, dummy.ctypes.data, 1 << 40, 4,
-                            dummy.ctypes.data, 1 << 40, None) == porta.EUNSUPPORTED
-    assert "bilinear" in L.porta_last_error().decode()
+                            dummy.ctypes.data, 16, None) == porta.ENOMEM
 
 
 def test_faces_option_checks():

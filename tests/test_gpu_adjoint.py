@@ -288,11 +288,36 @@ def test_autograd_function_uses_the_adjoint(orc):
     assert got == pytest.approx(oracle_directional(orc, atm, q, w, *v), rel=1e-10)
 
 
+def test_autograd_function_in_the_bezier_mode():
+    """emergent_stokes(interp=BEZIER2D): the forward is the 9-point sweep and the backward
+    its adjoint, bitwise, with and without checkpoints kept by the forward."""
+    torch = require_gpu()
+    from paper_1307_4217_amd.autograd import emergent_stokes
+    atm, q = tiny_case(porta.F64, seed=23, nx=5, ny=4, nz=6)
+    case = Case(atm, q, porta.F64)
+    target = torch.zeros((case.hg.nray_up, case.hg.nfreq, atm.ny, atm.nx, 4),
+                         dtype=torch.float64, device="cuda")
+    _, ref_t = case.sweep(interp=porta.BEZIER2D, want_jkq=False)
+    for keep in (False, True):
+        k, pm, e = (x.clone().requires_grad_(True) for x in (case.kappa, case.prop, case.emis))
+        itop = emergent_stokes(case.hg, k, pm, e, atm.i_bottom, atm.w2, prec=porta.F64,
+                               checkpoint_stride=2, keep_checkpoints=keep,
+                               interp=porta.BEZIER2D)
+        ((itop - target) ** 2).sum().backward()
+        g = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom,
+                             (2 * (itop - target)).detach(), atm.w2, prec=porta.F64,
+                             interp=porta.BEZIER2D, checkpoint_stride=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(itop.detach().cpu().numpy(), ref_t)
+        assert torch.equal(k.grad, g[0]) and torch.equal(pm.grad, g[1]) and torch.equal(e.grad, g[2])
+
+
+@pytest.mark.parametrize("interp", [porta.BILINEAR, porta.BEZIER2D])
 @pytest.mark.parametrize("prec", [porta.F64, porta.F32])
 @pytest.mark.parametrize("stride, rb_fwd, rb_adj", [(2, 0, 3), (3, 5, 0), (1, 2, 7), (6, 0, 0)])
-def test_adjoint_with_checkpoints_from_the_sweep(prec, stride, rb_fwd, rb_adj):
+def test_adjoint_with_checkpoints_from_the_sweep(prec, stride, rb_fwd, rb_adj, interp):
     """Checkpoints written by porta_fs_sweep (any ray batch) give the same gradient, bitwise,
-    as the adjoint making its own."""
+    as the adjoint making its own, in either interpolation mode."""
     torch = require_gpu()
     atm, q = tiny_case(prec, seed=31, nx=5, ny=4, nz=7)
     case = Case(atm, q, prec)
@@ -300,18 +325,18 @@ def test_adjoint_with_checkpoints_from_the_sweep(prec, stride, rb_fwd, rb_adj):
     n = porta.checkpoint_size(case.hg, prec, stride)
     ck = torch.full((max(n, 256),), 255, dtype=torch.uint8, device="cuda")
     jkq, itop = porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
-                               prec=prec, checkpoints=ck, checkpoint_stride=stride,
-                               opts=porta.options(ray_batch=rb_fwd))
-    ref_j, ref_t = case.sweep()
+                               prec=prec, interp=interp, checkpoints=ck,
+                               checkpoint_stride=stride, opts=porta.options(ray_batch=rb_fwd))
+    ref_j, ref_t = case.sweep(interp=interp)
     torch.cuda.synchronize()
     # I_top is independent of the ray batching; J only up to its summation order
     assert np.array_equal(itop.cpu().numpy(), ref_t)
     np.testing.assert_allclose(jkq.cpu().numpy(), ref_j, rtol=1e-13, atol=1e-15)
     own = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
-                           prec=prec, checkpoint_stride=stride,
+                           prec=prec, interp=interp, checkpoint_stride=stride,
                            opts=porta.options(ray_batch=rb_adj))
     ext = porta.fs_adjoint(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, w, atm.w2,
-                           prec=prec, checkpoint_stride=stride, checkpoints=ck,
+                           prec=prec, interp=interp, checkpoint_stride=stride, checkpoints=ck,
                            opts=porta.options(ray_batch=rb_adj))
     torch.cuda.synchronize()
     for a, b in zip(own, ext):

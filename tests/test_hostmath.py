@@ -30,6 +30,8 @@ def hm():
     L.hm_bezier3_f64.restype = C.c_double
     L.hm_bezier3_f32.argtypes = [C.c_float] * 4
     L.hm_bezier3_f32.restype = C.c_float
+    L.hm_bezier3_grad_f64.argtypes = [C.c_double] * 4 + [C.POINTER(C.c_double)]
+    L.hm_bezier3_grad_f64.restype = C.c_double
     L.hm_solve_stokes_f64.argtypes = [_dp] * 4
     L.hm_solve_stokes_f32.argtypes = [_fp] * 4
     L.hm_kprime_apply.argtypes = [_dp] * 4
@@ -254,6 +256,42 @@ def test_bezier3_closed_form_equals_branchy_besser(hm, orc):
         assert hm.hm_bezier3_f64(ym, y0, yp, t) == pytest.approx(ref, abs=4e-16 * scale)
         f = hm.hm_bezier3_f32(ym, y0, yp, t)
         assert f == pytest.approx(ref, abs=3e-6 * scale)
+
+
+def test_bezier3_gradient_against_differences_and_oracle_branches(hm, orc):
+    """The partials of the equidistant Bezier (the adjoint of the 9-point mode) against
+    central differences of the oracle's BESSER-based evaluation, on random triples away
+    from the branch switches, in both halves of the interval; the value is the
+    interpolant itself; at an extremum or a zero difference the control point is y0 and
+    only the weights of the quadratic remain."""
+    rng = np.random.default_rng(12)
+    g = (C.c_double * 3)()
+    checked = 0
+    for _ in range(3000):
+        ym, y0, yp = rng.standard_normal(3)
+        t = rng.uniform(-0.5, 0.5)
+        d1, d2 = y0 - ym, yp - y0
+        a = sorted([abs(d1), abs(d2), 0.25 * abs(d1 + d2)])
+        if d1 * d2 > 0 and a[1] - a[0] < 1e-3:
+            continue                              # next to a switch of the clamp
+        if abs(d1) < 1e-3 or abs(d2) < 1e-3:
+            continue
+        v = hm.hm_bezier3_grad_f64(ym, y0, yp, t, g)
+        assert v == pytest.approx(hm.hm_bezier3_f64(ym, y0, yp, t), abs=1e-15)
+        h = 1e-6
+        y = [ym, y0, yp]
+        for k in range(3):
+            yp_, ym_ = list(y), list(y)
+            yp_[k] += h
+            ym_[k] -= h
+            fd = (orc.bezier1d(*yp_, t) - orc.bezier1d(*ym_, t)) / (2 * h)
+            assert g[k] == pytest.approx(fd, abs=1e-8), (y, t, k)
+        checked += 1
+    assert checked > 1500
+    for ym, y0, yp, t in [(0.0, 1.0, 0.0, 0.3), (1.0, 1.0, 2.0, -0.2), (2.0, 2.0, 2.0, 0.4)]:
+        hm.hm_bezier3_grad_f64(ym, y0, yp, t, g)
+        w = (t * t if t < 0 else 0.0, 1 - t * t, t * t if t >= 0 else 0.0)
+        assert list(g) == pytest.approx(w, abs=1e-15)
 
 
 def test_parabolic_control_point_matches_oracle_and_its_gradient(hm, orc):
