@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--interp", default="bilinear", choices=["bilinear", "bezier2d"],
                     help="upwind/downwind interpolation (bezier2d: the 9-point monotonic "
-                         "Bezier; sweep only, with --no-adjoint)")
+                         "Bezier, forward and adjoint)")
     ap.add_argument("--stokes", type=int, default=4, choices=[4, 1],
                     help="4: Stokes-vector transfer; 1: the unpolarized (intensity-only) "
                          "problem (sweep only, with --no-adjoint)")
@@ -282,11 +282,9 @@ def main():
                                                           device=dev)
     hanle = t(atm.hanle, torch.float64) if atm.hanle is not None else None
     bhat = t(atm.bhat, torch.float64) if atm.bhat is not None else None
-    variant = (args.interp != "bilinear" or args.stokes != 4 or args.control != "besser"
-               or args.faces)
+    variant = args.stokes != 4 or args.control != "besser" or args.faces
     if variant and not args.no_adjoint:
-        sys.exit("--interp, --stokes, --control and --faces time the sweep alone: add "
-                 "--no-adjoint")
+        sys.exit("--stokes, --control and --faces time the sweep alone: add --no-adjoint")
     interp = porta.BEZIER2D if args.interp == "bezier2d" else porta.BILINEAR
     control = porta.CONTROL_PARABOLIC if args.control == "parabolic" else porta.CONTROL_BESSER
     nst = args.stokes
@@ -319,7 +317,7 @@ def main():
         # one workspace for every sweep and adjoint call, checkpoints for one range
         inter = schedule_mod.InterleavedSweep(hg, prec, range_rays, ray_batch=args.ray_batch,
                                               block=args.block, xcd_remap=args.xcd_remap,
-                                              device=dev)
+                                              device=dev, interp=interp)
     elif not args.no_adjoint:
         # the sweep and the adjoint run one after the other and share one workspace
         ws_bytes = max(ws_bytes, porta.workspace_size(hg, prec, porta.WS_ADJOINT_CKPT,
@@ -340,8 +338,8 @@ def main():
         # swept with the launches of one step, so that a profile of the whole run holds
         # the step's mix of launch shapes
         for o in (inter.range_opts + [inter.down_opts] if inter else [opts]):
-            porta.fs_sweep(hg, tk, tp, te, atm.i_bottom, atm.w2, prec=prec, want_jkq=False,
-                           i_top=target, opts=o, workspace=ws)
+            porta.fs_sweep(hg, tk, tp, te, atm.i_bottom, atm.w2, prec=prec, interp=interp,
+                           want_jkq=False, i_top=target, opts=o, workspace=ws)
         del tatm, tk, tp, te
         # 2 x target, so that the seed 2 (I_top - target) = lerp(I_top, 2 target, -1) is
         # one pass over I_top
@@ -426,7 +424,7 @@ def main():
             e[3].record()
             g_k.zero_(), g_p.zero_(), g_e.zero_()
             porta.fs_adjoint(hg, kappa, prop, emis_cur, atm.i_bottom, seed, atm.w2, prec=prec,
-                             checkpoint_stride=args.checkpoint_stride, g_kappa=g_k,
+                             interp=interp, checkpoint_stride=args.checkpoint_stride, g_kappa=g_k,
                              g_propmat=g_p, g_emis=g_e, opts=adj_opts, workspace=ws_adj,
                              checkpoints=ckpt)
         else:
@@ -515,7 +513,8 @@ def main():
         abytes = (cfg.nz - 1) * sum(adjoint_launch_bytes(cfg, n, elem)[0]
                                     for n in ashapes) / alaunches
         alaunch_ms = adj_ms / alaunches
-        aname = f"k_adjoint_plane<{'float' if elem == 4 else 'double'}, 0>"
+        aname = (f"k_adjoint_plane<{'float' if elem == 4 else 'double'}, "
+                 f"{1 if interp == porta.BEZIER2D else 0}>")
         acounters = (measured_counters(aname, workload) if args.block in (0, 256)
                      and args.xcd_remap == -1 else None)
         # The adjoint kernel is bound by its vector ALU: its rate is the VALU instructions
@@ -598,7 +597,8 @@ def main():
             torch.cuda.empty_cache()
             inter64 = schedule_mod.InterleavedSweep(hg, porta.F64, 4, ray_batch=args.ray_batch,
                                                     block=args.block,
-                                                    xcd_remap=args.xcd_remap, device=dev)
+                                                    xcd_remap=args.xcd_remap, device=dev,
+                                                    interp=interp)
             target2_64 = target2.double()
             gk64, gp64, ge64 = (torch.zeros_like(k64), torch.zeros_like(p64),
                                 torch.zeros_like(e64))

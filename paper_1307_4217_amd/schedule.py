@@ -46,11 +46,11 @@ class InterleavedSweep:
     """
 
     def __init__(self, hg, prec, range_rays, ray_batch=40, block=0, xcd_remap=-1,
-                 device="cuda"):
+                 device="cuda", interp=porta.BILINEAR):
         import torch
         if range_rays < 1:
             raise ValueError("range_rays must be >= 1")
-        self.hg, self.prec = hg, prec
+        self.hg, self.prec, self.interp = hg, prec, interp
         nh = hg.nray_up
         self.range_rays = min(range_rays, nh)
         self.ranges = [(r, min(self.range_rays, nh - r)) for r in range(0, nh, self.range_rays)]
@@ -92,17 +92,19 @@ class InterleavedSweep:
         for i, (r, n) in enumerate(self.ranges):
             o = self.range_opts[i]
             with t("sweep"):
-                porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec, jkq=jkq,
-                               accumulate=i > 0, i_top=i_top, opts=o, workspace=self.workspace,
+                porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec,
+                               interp=self.interp, jkq=jkq, accumulate=i > 0, i_top=i_top,
+                               opts=o, workspace=self.workspace,
                                stream=stream, checkpoints=self.checkpoints, checkpoint_stride=1)
             with t("seed"):
                 seed(r, n, i_top[r:r + n])
             with t("adjoint"):
                 porta.fs_adjoint(hg, kappa, propmat, emis, i_bottom, i_top, w2, prec=prec,
-                                 checkpoint_stride=1, g_kappa=g_kappa, g_propmat=g_propmat,
+                                 interp=self.interp, checkpoint_stride=1, g_kappa=g_kappa, g_propmat=g_propmat,
                                  g_emis=g_emis, opts=o, workspace=self.workspace,
                                  stream=stream, checkpoints=self.checkpoints)
         with t("sweep"):
-            porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec, jkq=jkq,
-                           accumulate=True, want_itop=False, opts=self.down_opts,
+            porta.fs_sweep(hg, kappa, propmat, emis, i_bottom, w2, prec=prec,
+                           interp=self.interp, jkq=jkq, accumulate=True, want_itop=False,
+                           opts=self.down_opts,
                            workspace=self.workspace, stream=stream)

@@ -406,23 +406,25 @@ def test_adjoint_over_ray_ranges(prec):
             assert err <= tol, err
 
 
-@pytest.mark.parametrize("prec, range_rays", [(porta.F64, 3), (porta.F32, 5)])
-def test_interleaved_schedule_matches_separate_calls(prec, range_rays):
+@pytest.mark.parametrize("prec, range_rays, interp", [(porta.F64, 3, porta.BILINEAR),
+                                                      (porta.F32, 5, porta.BILINEAR),
+                                                      (porta.F64, 4, porta.BEZIER2D)])
+def test_interleaved_schedule_matches_separate_calls(prec, range_rays, interp):
     """schedule.InterleavedSweep (ranges of upward rays swept with every plane kept and
     reversed at once, downward rays last) against one sweep of all rays and one adjoint
     call: J, I_top before the seed, the seed rows handed to the callback, and the
-    gradients of L = sum (I_top - target)^2."""
+    gradients of L = sum (I_top - target)^2, in either interpolation mode."""
     torch = require_gpu()
     from paper_1307_4217_amd import schedule
     atm, q = tiny_case(prec, seed=33, nx=5, ny=4, nz=7)
     case = Case(atm, q, prec)
     hg = case.hg
-    ref_j, ref_t = case.sweep()
+    ref_j, ref_t = case.sweep(interp=interp)
     target = to_dev(ref_t * 0.9 + 0.01, case.dt)
     seed_ref = 2 * (to_dev(ref_t, case.dt) - target)
     g_ref = porta.fs_adjoint(hg, case.kappa, case.prop, case.emis, atm.i_bottom, seed_ref,
-                             atm.w2, prec=prec, checkpoint_stride=2)
-    inter = schedule.InterleavedSweep(hg, prec, range_rays, ray_batch=3)
+                             atm.w2, prec=prec, interp=interp, checkpoint_stride=2)
+    inter = schedule.InterleavedSweep(hg, prec, range_rays, ray_batch=3, interp=interp)
     jkq = torch.full((10, hg.N), float("nan"), dtype=torch.float64, device="cuda")
     itop = torch.full(ref_t.shape, float("nan"), dtype=case.dt, device="cuda")
     g = [torch.zeros_like(x) for x in g_ref]
