@@ -187,6 +187,7 @@ __host__ __device__ constexpr int faces_chunk() {
   return sizeof(T) == 4 ? 6 : 7;
 }
 constexpr int kFacesMaxLanes = 512;  // columns of a plane held by one block
+constexpr int kFacesMaxWarm = 65536; // warm-up rows of a march, at most
 constexpr size_t kFacesLds = 65536;  // LDS of one block, at most
 
 // LDS of the kernel: W_j and phi_j of every frequency; then (16-byte aligned) the row of
@@ -344,10 +345,12 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
   const int mdir = chain ? -gM.off : 1;
   int warm = 0;
   if (chain) {
-    // (1 - t_z)^warm <= tol, at most 64 times around the box (clamped before the cast)
+    // (1 - t_z)^warm <= tol (41 / t_z rows in FP64), however many times around the box
+    // that takes; at most kFacesMaxWarm rows (t_z >= 6.3e-4 in FP64), clamped before the
+    // cast
     const double q = log1p(-fmin(gM.tz, 1.0));
     const double w = q < 0.0 ? ceil(log(a.tol) / q) : 0.0;
-    warm = (int)fmin(fmax(w, 0.0), 64.0 * nstep);
+    warm = (int)fmin(fmax(w, 0.0), (double)kFacesMaxWarm);
   }
   const size_t fstride = (size_t)a.np * 4;
   const size_t rstride = (size_t)a.nfreq * fstride;

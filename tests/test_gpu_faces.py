@@ -100,6 +100,43 @@ def test_first_face_sweep_rows_span_several_wavefronts(orc, prec):
           f"Q/I.. {ep:.2e}, J {ej:.2e}")
 
 
+@pytest.mark.parametrize("prec", [porta.F64, porta.F32])
+def test_first_face_sweep_widest_rows(orc, prec):
+    """A 504x8 plane, the widest rows of the benchmark grids (blocks of 512 lanes, eight
+    wavefronts, the last one ragged; in the exchanged frame rows of 8 lanes and a march
+    of 504 rows), all three first faces."""
+    cfg = inputs.Config("wide504", 504, 8, 6, 2, 6, 3, True)
+    atm = inputs.make_atmosphere(cfg, seed=6)
+    atm = dataclasses.replace(atm, lx=504 * 100.0, ly=800.0, z=np.arange(cfg.nz) * 100.0)
+    if prec == porta.F32:
+        atm = rounded(atm, np.float32)
+    q = inputs.make_quadrature(cfg)
+    assert {0, 1, 2} <= set(_face_kinds(atm, q).tolist())
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, faces=1))
+    jkq, itop = Case(atm, q, prec).sweep(opts=porta.options(faces=1))
+    tol_i, tol_p = (1e-10, 1e-12) if prec == porta.F64 else (2e-5, 1e-7)
+    ei, ep = compare_stokes(itop, up_rays(ref["itop"], q), tol_i, tol_p, "faces 504x8")
+    ej = compare_jkq(jkq, ref["jkq"], tol_i if prec == porta.F64 else 2e-5, "faces 504x8")
+    print(f"first-face sweep 504x8 {'FP64' if prec == porta.F64 else 'FP32'}: I {ei:.2e}, "
+          f"Q/I.. {ep:.2e}, J {ej:.2e}")
+
+
+def test_first_face_march_goes_around_a_short_plane_many_times(orc):
+    """Rows of 16 nodes, 4 of them in the march direction, rays down to mu = 0.047: the
+    guess needs ~860 rows of warm-up (t_z = 0.047) to fall below the FP64 rounding, i.e.
+    more than 200 times around the box (FP64 bar)."""
+    cfg = inputs.Config("short", 16, 4, 6, 5, 8, 2, True)
+    atm = inputs.make_atmosphere(cfg, seed=7)
+    atm = dataclasses.replace(atm, lx=1600.0, ly=400.0, z=np.arange(cfg.nz) * 100.0)
+    q = inputs.make_quadrature(cfg)
+    assert q.mu.min() < 0.05 and 2 in set(_face_kinds(atm, q).tolist())
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, faces=1))
+    jkq, itop = Case(atm, q, porta.F64).sweep(opts=porta.options(faces=1))
+    ei, ep = compare_stokes(itop, up_rays(ref["itop"], q), 1e-10, 1e-12, "faces short")
+    compare_jkq(jkq, ref["jkq"], 1e-10, "faces short")
+    print(f"first-face sweep 16x4: I {ei:.2e}, Q/I.. {ep:.2e}")
+
+
 def test_first_face_sweep_equals_plane_hops_where_every_face_is_horizontal():
     """Rays that reach the plane below (and above) within one cell on every plane: the
     first face is that plane, so the two sweeps compute the same arithmetic up to
