@@ -137,6 +137,45 @@ def test_first_face_march_goes_around_a_short_plane_many_times(orc):
     print(f"first-face sweep 16x4: I {ei:.2e}, Q/I.. {ep:.2e}")
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 5), (1, 4, 5), (3, 1, 5), (4, 3, 2)])
+def test_first_face_sweep_degenerate_grids(orc, shape):
+    """A single column, a single row in either direction (the neighbouring row or column
+    of a face is the node's own), and one layer (nz = 2): FP64 against the oracle."""
+    nx, ny, nz = shape
+    cfg = inputs.Config("degenerate", nx, ny, nz, 3, 4, 2, True)
+    atm = inputs.make_atmosphere(cfg, seed=8)
+    atm = dataclasses.replace(atm, lx=nx * 100.0, ly=ny * 100.0, z=np.arange(nz) * 150.0)
+    q = inputs.make_quadrature(cfg)
+    assert {0, 1, 2} <= set(_face_kinds(atm, q).tolist())
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, faces=1))
+    jkq, itop = Case(atm, q, porta.F64).sweep(opts=porta.options(faces=1))
+    compare_stokes(itop, up_rays(ref["itop"], q), 1e-10, 1e-12, f"faces {shape}")
+    compare_jkq(jkq, ref["jkq"], 1e-10, f"faces {shape}")
+
+
+def test_first_face_sweep_over_ray_ranges_adds_up():
+    """Two calls over ray ranges (one straddling the hemispheres), J accumulated, give
+    the single call's I_top bitwise and its J to its summation order."""
+    torch = require_gpu()
+    cfg = inputs.Config("ranges", 9, 7, 6, 2, 5, 3, True)
+    atm = inputs.make_atmosphere(cfg, seed=9)
+    atm = dataclasses.replace(atm, lx=900.0, ly=700.0, z=np.arange(cfg.nz) * 120.0)
+    q = inputs.make_quadrature(cfg)
+    case = Case(atm, q, porta.F64)
+    j1, it1 = case.sweep(opts=porta.options(faces=1))
+    nray = 2 * len(q.mu) * q.nchi
+    jkq = torch.zeros((10, atm.npoints), dtype=torch.float64, device="cuda")
+    itop = torch.full(it1.shape, float("nan"), dtype=torch.float64, device="cuda")
+    for k, (first, count) in enumerate(((0, 7), (7, nray - 7))):
+        porta.fs_sweep(case.hg, case.kappa, case.prop, case.emis, atm.i_bottom, atm.w2,
+                       prec=porta.F64, jkq=jkq, accumulate=k > 0, i_top=itop,
+                       opts=porta.options(faces=1, ray_first=first, ray_count=count,
+                                          ray_batch=3))
+    torch.cuda.synchronize()
+    assert np.array_equal(itop.cpu().numpy(), it1)
+    np.testing.assert_allclose(jkq.cpu().numpy(), j1, rtol=1e-13, atol=1e-15 * np.abs(j1).max())
+
+
 def test_first_face_sweep_equals_plane_hops_where_every_face_is_horizontal():
     """Rays that reach the plane below (and above) within one cell on every plane: the
     first face is that plane, so the two sweeps compute the same arithmetic up to
