@@ -179,12 +179,14 @@ enum FacesCacheSlot {
 };
 
 // frequencies per block, at most (LDS may set fewer).  Small chunks give more blocks
-// (the launch is nchunk x rays of them, of unequal lengths) and more blocks per CU; the
-// set-up table is read once per chunk.  At 256x256x128, 80 rays and 101 frequencies in
-// FP32, chunks of 4, 6, 8, 11 and 15 took 14.3, 13.5, 14.2, 16.1 and 17.1 ms per launch.
+// (the launch is nchunk x rays of them, of unequal lengths: the most inclined rays
+// march 4x the rows of the steep ones) and more blocks per CU, and shorten the longest
+// block; the set-up table is read once per chunk.  At 256x256x128, 80 rays and 101
+// frequencies in FP32, chunks of 2, 3, 4 and 6 took 12.8, 10.8, 9.8 and 10.9 ms per
+// plane.
 template <class T>
 __host__ __device__ constexpr int faces_chunk() {
-  return sizeof(T) == 4 ? 6 : 7;
+  return sizeof(T) == 4 ? 4 : 7;
 }
 constexpr int kFacesMaxLanes = 512;  // columns of a plane held by one block
 constexpr int kFacesMaxWarm = 65536; // warm-up rows of a march, at most
