@@ -735,7 +735,10 @@ int adjoint_impl(const porta_grid* g, const porta_quad* q, const porta_fields* f
           t.inv_dx = a.inv_dx;
           t.inv_dy = a.inv_dy;
           t.ray0 = r0;
-          hipLaunchKernelGGL(k_bez9_tgather<T>, dim3((np + 255) / 256, nrb), dim3(256), 0, st, t);
+          constexpr int TX = TGTile<T>::X, TY = TGTile<T>::Y;
+          hipLaunchKernelGGL(k_bez9_tgather<T>,
+                             dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, nrb), dim3(TX * TY),
+                             0, st, t);
           if ((rc = check_launch("bez9_tgather"))) return rc;
           a.lam_next = nullptr;
           a.seed = lam[cur];

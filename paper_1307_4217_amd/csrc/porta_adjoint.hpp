@@ -141,7 +141,7 @@ __device__ inline void bez9_adjoint_gather(const BezW<T>& wx, const BezW<T>& wy,
 
 // Adjoint of the Stokes vectors of plane kO in the 9-point mode: gathered from the
 // adjoint of I_M at the nodes of plane kO + 1 (whose M points interpolate plane kO)
-// through the transposed Bezier stencil, at every frequency.  Thread = (node, ray).
+// through the transposed Bezier stencil, at every frequency.
 template <class T>
 struct TGatherArgs {
   const T* icur;       // forward state of plane kO ([ray][freq][node][4])
@@ -153,38 +153,141 @@ struct TGatherArgs {
   int ray0;
 };
 
+// A block takes a tile of TGX x TGY nodes q of one ray (blockIdx.z) and forms, per
+// frequency, the pieces of bez9_adjoint_gather that neighbouring nodes share once in
+// LDS: the x pass of every row triple (centre (x, y), rows of the tile +-2, columns +-1),
+// its partials on the tile's rows, and the partials of the y pass of every centre
+// (rows +-1).  Node q then sums, over the nine p whose stencil holds it, the product
+// of the y partial of p's centre (qx + cc, qy + rc) at q's row, the x partial of the
+// centre (qx + cc, qy) at q's column and the adjoint at p.  Positions, not nodes, are
+// staged, so a small periodic plane that puts a node at several places works as in
+// bez9_adjoint_gather.
+template <class T>
+struct TGTile {
+  static constexpr int X = sizeof(T) == 4 ? 64 : 32, Y = 4;
+};
+
 template <class T>
 __global__ void __launch_bounds__(256) k_bez9_tgather(const TGatherArgs<T> a) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x, rb = blockIdx.y;
-  if (q >= a.np) return;
+  constexpr int TX = TGTile<T>::X, TY = TGTile<T>::Y;
+  constexpr int FX = TX + 4, FY = TY + 4;   // staged forward states: columns -2..TX+1
+  constexpr int CX = TX + 2;                // centres: columns -1..TX
+  __shared__ T sF[FY][FX][4];               // rows -2..TY+1
+  __shared__ T sR[FY][CX][4];               // x pass at the centres, rows -2..TY+1
+  __shared__ T sGx[TY][CX][3][4];           // its partials on the tile's rows
+  __shared__ T sGy[TY + 2][CX][3][4];       // y-pass partials at centre rows -1..TY
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int rb = blockIdx.z;
+  const int qx0 = blockIdx.x * TX, qy0 = blockIdx.y * TY;
   const RayConsts& rc = a.rays[a.ray0 + rb];
   const double dsN = a.dzN / fabs(rc.mu);
   const Bez9Geom gm = bez9_geom(-dsN * rc.sx * a.inv_dx, -dsN * rc.sy * a.inv_dy, a.nx, a.ny);
   const BezW<T> wx = bez_weights((T)gm.tx), wy = bez_weights((T)gm.ty);
-  const int qi = q % a.nx, qj = q / a.nx;
-  int rowb[5], coli[5], prow[3], pcol[3];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    rowb[d] = wrapi(qj + d - 2, a.ny) * a.nx;
-    coli[d] = wrapi(qi + d - 2, a.nx);
-  }
+  const int lx = tid % TX, ly = tid / TX;     // this thread's node of the tile
+  const int qx = qx0 + lx, qy = qy0 + ly;
+  const bool active = ly < TY && qx < a.nx && qy < a.ny;
+  int prow[3], pcol[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    prow[d] = wrapi(qj - gm.fv + d - 1, a.ny) * a.nx;
-    pcol[d] = wrapi(qi - gm.fu + d - 1, a.nx);
+    prow[d] = wrapi(qy - gm.fv + d - 1, a.ny) * a.nx;
+    pcol[d] = wrapi(qx - gm.fu + d - 1, a.nx);
   }
   const size_t fstride = (size_t)a.np * 4;
   const size_t roff = (size_t)rb * a.nfreq * fstride;
-  for (int f = 0; f < a.nfreq; ++f) {
+  // The forward states of frequency f + 1 (this thread's share of the tile) and the
+  // nine adjoints at p are loaded while frequency f is being worked on, and the states
+  // go to LDS once the x passes of f have read it.
+  constexpr int NF = (FY * FX + TX * TY - 1) / (TX * TY);   // tile entries per thread
+  T fN[NF][4], lam[3][3][4], lamN[3][3][4];
+  auto load_tile = [&](int f) __attribute__((always_inline)) {
     const T* ic = a.icur + roff + (size_t)f * fstride;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int e = tid + i * nthr;
+      if (e < FY * FX) {
+        const int r = e / FX, c = e % FX;
+        const size_t n = (size_t)wrapi(qy0 + r - 2, a.ny) * a.nx + wrapi(qx0 + c - 2, a.nx);
+        load4(ic + 4 * n, fN[i]);
+      }
+    }
+  };
+  auto store_tile = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int e = tid + i * nthr;
+      if (e < FY * FX) {
+        const int r = e / FX, c = e % FX;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sF[r][c][k] = fN[i][k];
+      }
+    }
+  };
+  auto load_lam = [&](int f, T (&dst)[3][3][4]) __attribute__((always_inline)) {
     const T* ln = a.lam_next + roff + (size_t)f * fstride;
-    T out[4] = {T(0), T(0), T(0), T(0)};
-    bez9_adjoint_gather<T, 4>(
-        wx, wy,
-        [&](int r, int c, T v[4]) { load4(ic + 4 * (size_t)(rowb[r + 2] + coli[c + 2]), v); },
-        [&](int r, int c, T g[4]) { load4(ln + 4 * (size_t)(prow[r + 1] + pcol[c + 1]), g); },
-        out);
-    store4(a.out + roff + (size_t)f * fstride + 4 * (size_t)q, out);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) load4(ln + 4 * (size_t)(prow[r] + pcol[c]), dst[r][c]);
+  };
+  load_tile(0);
+  load_lam(0, lam);
+  store_tile();
+  __syncthreads();
+  for (int f = 0; f < a.nfreq; ++f) {
+    const bool more = f + 1 < a.nfreq;
+    if (more) {
+      load_tile(f + 1);
+      load_lam(f + 1, lamN);
+    }
+    for (int e = tid; e < FY * CX; e += nthr) {
+      const int r = e / CX, c = e % CX;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (r >= 2 && r < TY + 2) {
+          T g[3];
+          sR[r][c][k] = bez_eval_grad(wx, sF[r][c][k], sF[r][c + 1][k], sF[r][c + 2][k], g);
+          sGx[r - 2][c][0][k] = g[0];
+          sGx[r - 2][c][1][k] = g[1];
+          sGx[r - 2][c][2][k] = g[2];
+        } else {
+          sR[r][c][k] = bez_eval(wx, sF[r][c][k], sF[r][c + 1][k], sF[r][c + 2][k]);
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < (TY + 2) * CX; e += nthr) {
+      const int r = e / CX, c = e % CX;   // centre row qy0 - 1 + r: R rows r .. r + 2
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        T g[3];
+        bez_eval_grad(wy, sR[r][c][k], sR[r + 1][c][k], sR[r + 2][c][k], g);
+        sGy[r][c][0][k] = g[0];
+        sGy[r][c][1][k] = g[1];
+        sGy[r][c][2][k] = g[2];
+      }
+    }
+    if (more) store_tile();   // sF was last read before the barrier above
+    __syncthreads();
+    if (active) {
+      T out[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)        // rc = r - 1
+#pragma unroll
+        for (int c = 0; c < 3; ++c)      // cc = c - 1
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            out[k] += sGy[ly + r][lx + c][2 - r][k] * sGx[ly][lx + c][2 - c][k] * lam[r][c][k];
+      store4(a.out + roff + (size_t)f * fstride + 4 * ((size_t)qy * a.nx + qx), out);
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) lam[r][c][k] = lamN[r][c][k];
+    }
+    __syncthreads();   // sGx, sGy and sR are refilled for the next frequency
   }
 }
 
