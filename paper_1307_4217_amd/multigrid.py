@@ -221,7 +221,8 @@ def main(argv=None):
     ap.add_argument("--nfreq", type=int, default=41)
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--cycles", type=int, default=4)
-    ap.add_argument("--tol", type=float, default=0.0, help="stop once R_c falls below this")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="stop once R_c falls below this (the cycles and the Jacobi iterations)")
     ap.add_argument("--jacobi", type=int, default=0, help="also run this many Jacobi iterations")
     ap.add_argument("--ncoarse", type=int, default=20)
     ap.add_argument("--ray-batch", type=int, default=40)
@@ -266,12 +267,16 @@ def main(argv=None):
         from .jacobi import JacobiSolver
         js = JacobiSolver(atm, q, prec, opts=porta.options(ray_batch=args.ray_batch))
         t0 = time.perf_counter()
+        its = 0
         for it in range(args.jacobi):
             rcj = float(js.step().item())
-            if (it + 1) % 10 == 0:
-                print(json.dumps({"jacobi": it + 1, "R_c": rcj}), flush=True)
+            its = it + 1
+            if its % 10 == 0:
+                print(json.dumps({"jacobi": its, "R_c": rcj}), flush=True)
+            if rcj < args.tol:
+                break
         torch.cuda.synchronize()
-        out.update({"jacobi_iterations": args.jacobi, "jacobi_final_R_c": rcj,
+        out.update({"jacobi_iterations": its, "jacobi_final_R_c": rcj,
                     "jacobi_seconds": round(time.perf_counter() - t0, 3)})
     print(json.dumps(out), flush=True)
     return 0
