@@ -12,6 +12,10 @@ every plane and reversed at once, and the downward rays are swept after them;
 where those planes do not fit in device memory, one forward sweep keeps every
 C-th plane and the adjoint recomputes the rest.  Inputs are seeded synthetic
 fields already resident in HBM.  Prints one JSON line on stdout.
+
+After the timed steps (FP32 runs only, untimed): one FP32 and one FP64 sweep of the
+same FP32-rounded inputs, whose largest differences over every emergent Stokes vector
+and every point's J^K_Q go to `detail.precision`, then the FP64 sweep and step rates.
 """
 from __future__ import annotations
 
@@ -81,6 +85,9 @@ def parse():
                     help="row tiles per XCD per round (-1: the library default)")
     ap.add_argument("--no-fp64-rate", action="store_true",
                     help="skip the extra FP64 sweep used for the FP32-vs-FP64 rate")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32 sweep compared with the first FP64 sweep (profiles "
+                         "use it, so that the FP32 kernels' launches are those of the step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (counter calibration for profiles)")
@@ -201,6 +208,27 @@ def measured_counters(kernel, workload):
         if k is not None and k.get("code_sha256") == kernel_code_sha256(kernel):
             return k
     return None
+
+
+def precision_report(it32, it64, j32, j64, nst):
+    """Largest errors of an FP32 sweep against the FP64 sweep of the same FP32-rounded
+    inputs: relative on I and absolute on Q/I, U/I, V/I over every top point, upward ray
+    and frequency; J^K_Q (rows 0-8) relative to J^0_0 and Lambda-bar relative, at every
+    point.  Compared ray by ray, in FP64, on the device."""
+    ei = ep = 0.0
+    for r in range(it64.shape[0]):
+        a, b = it32[r].double(), it64[r]
+        ia, ib = (a[..., 0], b[..., 0]) if nst == 4 else (a, b)
+        ei = max(ei, ((ia - ib).abs() / ib.abs()).max().item())
+        if nst == 4:
+            ep = max(ep, (a[..., 1:] / ia[..., None] - b[..., 1:] / ib[..., None])
+                     .abs().max().item())
+    ej = ((j32[:9] - j64[:9]).abs() / j64[0].abs()).max().item()
+    el = ((j32[9] - j64[9]).abs() / j64[9].abs()).max().item()
+    return {"reference": "FP64 sweep of the same FP32-rounded inputs on the GPU",
+            "i_rel_max": ei, "pol_abs_max": ep if nst == 4 else None,
+            "jkq_rel_j00_max": ej, "lbar_rel_max": el,
+            "outputs": int(it64.numel() // (4 if nst == 4 else 1))}
 
 
 def host_cpus():
@@ -551,14 +579,32 @@ def main():
             del ws_adj, ckpt
         inter = None   # holds the workspace and checkpoints of the interleaved schedule
         torch.cuda.empty_cache()
-        k64, p64, e64 = t(atm.kappa, torch.float64), t(atm.propmat, torch.float64), t(
-            atm.emis, torch.float64)
+        # the FP32-rounded inputs, so that the first FP64 sweep is the reference of an
+        # FP32 sweep of the same inputs (untimed)
+        e32 = t(atm.emis, tdt)
+        k64, p64, e64 = kappa.double(), prop.double(), e32.double()
+        sshape = (hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx) + ((4,) if nst == 4 else ())
+        if not args.no_precision:
+            ws32 = torch.empty(porta.workspace_size(hg, porta.F32, porta.WS_SWEEP, 1, opts),
+                               dtype=torch.uint8, device=dev)
+            it32 = torch.empty(sshape, dtype=torch.float32, device=dev)
+            j32 = torch.empty_like(jkq)
+            porta.fs_sweep(hg, kappa, prop, e32, atm.i_bottom, atm.w2, prec=porta.F32,
+                           interp=interp, jkq=j32, i_top=it32, opts=opts, workspace=ws32)
+            del ws32
         ws64 = torch.empty(porta.workspace_size(hg, porta.F64, porta.WS_SWEEP, 1, opts),
                            dtype=torch.uint8, device=dev)
-        it64 = torch.empty((hg.nray_up, cfg.nfreq, cfg.ny, cfg.nx, 4), dtype=torch.float64,
-                           device=dev)
+        it64 = torch.empty(sshape, dtype=torch.float64, device=dev)
         porta.fs_sweep(hg, k64, p64, e64, atm.i_bottom, atm.w2, prec=porta.F64, interp=interp,
                        jkq=jkq, i_top=it64, opts=opts, workspace=ws64)
+        if not args.no_precision:
+            extra["precision"] = pr = precision_report(it32, it64, j32, jkq, nst)
+            log(f"FP32 vs FP64 over {pr['outputs']:.3e} emergent Stokes vectors: I rel "
+                f"{pr['i_rel_max']:.2e}, Q/I U/I V/I abs {pr['pol_abs_max'] or 0:.2e}; "
+                f"J^K_Q {pr['jkq_rel_j00_max']:.2e} of J00, Lbar {pr['lbar_rel_max']:.2e}")
+            del it32, j32
+        del e32
+        torch.cuda.empty_cache()
         torch.cuda.synchronize()
         a, b = ev(), ev()
         a.record()
