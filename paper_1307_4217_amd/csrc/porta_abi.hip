@@ -454,12 +454,14 @@ int sweep_faces_impl(const porta_grid* g, const porta_quad* q, const porta_field
         a.inv_dy = ny / g->ly;
         a.ray0 = ray0;
         a.parabolic = parabolic_of(o);
-        a.tol = sizeof(T) == 4 ? 1e-9 : 1e-18;
+        a.tol = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;   // the unit roundoff of the sweep precision
         a.ibound = ibound;
         a.cache = reinterpret_cast<T*>(ws + L.fcache);
+        a.nrb = nrb;
         hipLaunchKernelGGL(k_faces_setup<T>, dim3((np + 255) / 256, nrb), dim3(256), 0, st, a);
         if ((rc = check_launch("faces_setup"))) return rc;
-        hipLaunchKernelGGL(k_sweep_plane_faces<T>, dim3(nchunk, nrb), dim3(lanes), lds, st, a);
+        hipLaunchKernelGGL(k_sweep_plane_faces<T>, dim3(faces_grid(nrb, nchunk)), dim3(lanes),
+                           lds, st, a);
         if ((rc = check_launch("sweep_plane_faces"))) return rc;
         if (jkq) {
           const unsigned tiles = (unsigned)((std::max(nx, ny) + kSumTile - 1) / kSumTile);

@@ -166,9 +166,20 @@ struct FacesArgs {
   double inv_dx, inv_dy;
   int ray0;
   int parabolic;
-  double tol;        // the march's starting guess is damped below tol
+  double tol;        // the march's starting guess is damped below tol (the unit roundoff)
   T ibound;
+  int nrb;           // rays of the launch
 };
+
+// Workgroups of a launch go to the 8 XCDs in turn (workgroup w to XCD w % 8).  The march
+// takes a one-dimensional grid of 8 * ceil(nrb / 8) * nchunk workgroups and gives XCD x
+// the rays x, x + 8, x + 16, ... (every inclination alike on each XCD), each ray's
+// chunks one after another: they start together and walk the same rows, so the rows
+// of the set-up table that every chunk of the ray reads come from that XCD's L2.
+constexpr int kFacesXcds = 8;
+inline int faces_grid(int nrb, int nchunk) {
+  return kFacesXcds * ((nrb + kFacesXcds - 1) / kFacesXcds) * nchunk;
+}
 
 // Values of the set-up of a node and ray that the march reads, in the sweep precision:
 // K'_M / eta_I entries (eta 3, rho 3), K'_O (3, 3), S_M (4), S_O (4), c_M (4), the
@@ -181,12 +192,13 @@ enum FacesCacheSlot {
 // frequencies per block, at most (LDS may set fewer).  Small chunks give more blocks
 // (the launch is nchunk x rays of them, of unequal lengths: the most inclined rays
 // march 4x the rows of the steep ones) and more blocks per CU, and shorten the longest
-// block; the set-up table is read once per chunk.  At 256x256x128, 80 rays and 101
-// frequencies in FP32, chunks of 2, 3, 4 and 6 took 12.8, 10.8, 9.8 and 10.9 ms per
-// plane.
+// block; the set-up table is read once per chunk (from L2 for all but the first chunk
+// of a ray, with the order of faces_grid).  At 256x256x128, 80 rays and 101
+// frequencies, a sweep took 2.59, 2.39, 2.34 and 2.46 s with FP32 chunks of 3, 4, 5
+// and 6, and 6.51, 6.49 and 6.37 s with FP64 chunks of 5, 6 and 7.
 template <class T>
 __host__ __device__ constexpr int faces_chunk() {
-  return sizeof(T) == 4 ? 4 : 7;
+  return sizeof(T) == 4 ? 5 : 7;
 }
 constexpr int kFacesMaxLanes = 512;  // columns of a plane held by one block
 constexpr int kFacesMaxWarm = 65536; // warm-up rows of a march, at most
@@ -310,7 +322,7 @@ __global__ void __launch_bounds__(256) k_faces_setup(const FacesArgs<T> a) {
   c[kClf * np] = (T)lamfac;
 }
 
-// One plane for one ray (blockIdx.y) and one chunk of frequencies (blockIdx.x).  Lanes
+// One plane for one ray and one chunk of frequencies (order: faces_grid).  Lanes
 // are the columns of the working frame; the block walks its rows.  Each lane keeps its
 // own column's Stokes vectors of the previous row in LDS and reads the neighbouring
 // column's there too when that lane is in its wave (the lanes of a wave read before
@@ -320,6 +332,10 @@ __global__ void __launch_bounds__(256) k_faces_setup(const FacesArgs<T> a) {
 // dependency and takes no barrier.
 template <class T>
 __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const FacesArgs<T> a) {
+  // this workgroup's ray and chunk (faces_grid); the few past the last ray leave at once
+  const int wx = blockIdx.x % kFacesXcds, wk = blockIdx.x / kFacesXcds;
+  const int rb = wx + kFacesXcds * (wk / a.nchunk), chunk = wk % a.nchunk;
+  if (rb >= a.nrb) return;
   extern __shared__ double s_tab[];
   double* s_wn = s_tab;
   T* s_phi = reinterpret_cast<T*>(s_tab + a.nfreq);
@@ -331,7 +347,6 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
     s_wn[t] = a.wn[t];
     s_phi[t] = a.phi[t];
   }
-  const int rb = blockIdx.y, chunk = blockIdx.x;
   const int f0 = chunk * a.fchunk;
   const int nf = min(a.fchunk, a.nfreq - f0);
   const RayConsts& rc = a.rays[a.ray0 + rb];
@@ -347,9 +362,9 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
   const int mdir = chain ? -gM.off : 1;
   int warm = 0;
   if (chain) {
-    // (1 - t_z)^warm <= tol (41 / t_z rows in FP64), however many times around the box
-    // that takes; at most kFacesMaxWarm rows (t_z >= 6.3e-4 in FP64), clamped before the
-    // cast
+    // (1 - t_z)^warm <= tol (37 / t_z rows in FP64, 17 / t_z in FP32), however many
+    // times around the box that takes; at most kFacesMaxWarm rows (t_z >= 5.6e-4 in
+    // FP64), clamped before the cast
     const double q = log1p(-fmin(gM.tz, 1.0));
     const double w = q < 0.0 ? ceil(log(a.tol) / q) : 0.0;
     warm = (int)fmin(fmax(w, 0.0), (double)kFacesMaxWarm);

@@ -123,8 +123,8 @@ def test_first_face_sweep_widest_rows(orc, prec):
 
 def test_first_face_march_goes_around_a_short_plane_many_times(orc):
     """Rows of 16 nodes, 4 of them in the march direction, rays down to mu = 0.047: the
-    guess needs ~860 rows of warm-up (t_z = 0.047) to fall below the FP64 rounding, i.e.
-    more than 200 times around the box (FP64 bar)."""
+    guess needs ~760 rows of warm-up (t_z = 0.047) to fall below the FP64 unit roundoff,
+    i.e. more than 190 times around the box (FP64 bar)."""
     cfg = inputs.Config("short", 16, 4, 6, 5, 8, 2, True)
     atm = inputs.make_atmosphere(cfg, seed=7)
     atm = dataclasses.replace(atm, lx=1600.0, ly=400.0, z=np.arange(cfg.nz) * 100.0)
