@@ -422,3 +422,34 @@ def test_jacobi_save_and_resume_is_exact(tmp_path):
                                 hanle=None, bhat=None)
     with pytest.raises(ValueError):
         JacobiSolver(other, q, porta.F32).load(path)
+
+
+def test_jacobi_switches_sweep_precision(tmp_path):
+    """Three FP32 iterations, set_precision(F64) and three FP64 ones equal three FP32
+    iterations saved to disk, loaded by an FP64 solver and continued (the emissivities
+    formed from S^K_Q by porta_emissivity in both): S^K_Q, emissivities and R_c history
+    bitwise.  After the switch the iterate is the all-FP64 one up to the FP32 rounding
+    of the first iterations, which the contraction of the iteration damps."""
+    torch = require_gpu()
+    from paper_1307_4217_amd.jacobi import JacobiSolver
+    atm, q, _ = oracle_full("C1", 0, "f64")
+    a = JacobiSolver(atm, q, porta.F32)
+    a.solve(3, tol=0.0)
+    a.set_precision(porta.F64)
+    assert a.prec == porta.F64 and a.emis.dtype == torch.float64
+    a.solve(3, tol=0.0)
+    b = JacobiSolver(atm, q, porta.F32)
+    b.solve(3, tol=0.0)
+    path = str(tmp_path / "it32.npz")
+    b.save(path)
+    c = JacobiSolver(atm, q, porta.F64)
+    c.load(path)
+    c.solve(3, tol=0.0)
+    d = JacobiSolver(atm, q, porta.F64)
+    d.solve(6, tol=0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(a.source, c.source) and torch.equal(a.emis, c.emis)
+    assert a.history == c.history and c.iteration == 6
+    err = float(((a.source - d.source).abs().max() / d.source[0].abs().max()).item())
+    print(f"FP32 x 3 then FP64 x 3 vs FP64 x 6: max |dS| / max S00 = {err:.2e}")
+    assert err < 1e-4
