@@ -130,6 +130,9 @@ KERNEL_SYMBOLS = {
     "k_sweep_plane_i<float>": "_ZN5porta15k_sweep_plane_iIfEEvNS_9PlaneArgsIT_EE",
     "k_sweep_plane_faces<float>": "_ZN5porta19k_sweep_plane_facesIfEEvNS_9FacesArgsIT_EE",
     "k_faces_setup<float>": "_ZN5porta13k_faces_setupIfEEvNS_9FacesArgsIT_EE",
+    "k_adjoint_plane<float, 1>": "_ZN5porta15k_adjoint_planeIfLi1EEEvNS_7AdjArgsIT_EE",
+    "k_adjoint_gather<float, 1>": "_ZN5porta16k_adjoint_gatherIfLi1EEEvNS_10GatherArgsIT_EE",
+    "k_bez9_tgather<float>": "_ZN5porta14k_bez9_tgatherIfEEvNS_11TGatherArgsIT_EE",
 }
 
 
