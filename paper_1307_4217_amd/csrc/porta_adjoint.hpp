@@ -445,7 +445,7 @@ k_adjoint_plane(const AdjArgs<T> a) {
         T out[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) out[s] = cf.e * lb[s] - cf.psiM * KT[s];
-        store4(lo + fo, out);
+        store4_nt(lo + fo, out);
       }
     };
     if constexpr (sizeof(T) == 4) {

@@ -506,7 +506,10 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
           if (last_too) store4(b2 + 4, res);
         }
         if (store) {
-          store4(op + (size_t)fg * fstride + 4 * ostore, res);
+          // I_top of a ray in the exchanged frame goes to the grid's own indices, across
+          // rows: there the plain store, whose lines the cache merges, is the faster
+          if (a.top) store4(op + (size_t)fg * fstride + 4 * ostore, res);
+          else store4_nt(op + (size_t)fg * fstride + 4 * ostore, res);
           const double W = s_wn[fg];
 #pragma unroll
           for (int s = 0; s < 4; ++s) jacc[s] += W * (double)res[s];

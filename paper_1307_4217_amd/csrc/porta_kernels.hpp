@@ -106,6 +106,20 @@ __device__ inline void store4(double* p, const double v[4]) {
   *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
   *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
 }
+// The same with the non-temporal hint: a plane state that the next launch reads from
+// HBM anyway (the planes of a launch exceed the caches) need not take L2 lines from
+// the upwind rows and coefficients that neighbouring tiles read again.
+typedef float porta_f4 __attribute__((ext_vector_type(4)));
+typedef double porta_d2 __attribute__((ext_vector_type(2)));
+__device__ inline void store4_nt(float* p, const float v[4]) {
+  const porta_f4 q = {v[0], v[1], v[2], v[3]};
+  __builtin_nontemporal_store(q, reinterpret_cast<porta_f4*>(p));
+}
+__device__ inline void store4_nt(double* p, const double v[4]) {
+  const porta_d2 a = {v[0], v[1]}, b = {v[2], v[3]};
+  __builtin_nontemporal_store(a, reinterpret_cast<porta_d2*>(p));
+  __builtin_nontemporal_store(b, reinterpret_cast<porta_d2*>(p + 2));
+}
 
 __device__ inline int wrapi(int v, int n) {
   v %= n;
@@ -522,7 +536,7 @@ k_sweep_plane(const PlaneArgs<T> a) {
       b[s] = cf.e * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] + cf.omC * cMt[s];
     T x[4];
     stokes_solve<1>(KO, stokes_freq(KO, cf.psiO), b, x);
-    store4(op + (size_t)f * fstride, x);
+    store4_nt(op + (size_t)f * fstride, x);
     const double W = s_wn[f];
     jacc0 += W * (double)x[0];
     jacc1 += W * (double)x[1];

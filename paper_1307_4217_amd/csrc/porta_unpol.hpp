@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) k_sweep_plane_i(const PlaneArgs<T> a) {
   auto update = [&](int f, T IM) __attribute__((always_inline)) {
     const Coefs<T> cf = coefficients(tau0 * s_phi[f]);
     const T x = cf.e * IM + cf.omM * SMt + cf.omO * SOt + cf.omC * cMt;
-    op[(size_t)f * fstride] = x;
+    __builtin_nontemporal_store(x, op + (size_t)f * fstride);   // as store4_nt
     const double W = s_wn[f];
     jacc += W * (double)x;
     lacc += W * (double)(cf.omO + lf * cf.omC);

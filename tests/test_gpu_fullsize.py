@@ -309,8 +309,10 @@ def test_c5_fp32_against_fp64_first_iteration():
 def test_c3_variants_full_size_sampled_pairs(orc, prec):
     """The forward variants at 256x256x128 (160 rays, 101 frequencies) on sampled
     (ray, frequency) pairs over the whole top surface: the 9-point Bezier interpolation
-    (against the oracle's mode 1; in FP32 Stokes I only, Q/I.. reported: that mode misses
-    the 1e-7 bar in FP32, see test_bezier2d_mode_fp32_polarization_bar) and the
+    (against the oracle's mode 1; in FP32 Stokes I only on these two pairs, Q/I..
+    reported: that mode misses the 1e-7 bar in FP32, see
+    test_bezier2d_mode_fp32_polarization_bar, and over all rays the 2e-5 bar on I too,
+    see test_c3_bezier2d_fp32_stokes_i_every_upward_ray) and the
     intensity-only sweep (against the oracle with K' = 0 and the K = 2 emission zero)."""
     torch = require_gpu()
     torch.cuda.empty_cache()
@@ -350,3 +352,75 @@ def test_c3_variants_full_size_sampled_pairs(orc, prec):
     assert e1 <= tol
     del case
     torch.cuda.empty_cache()
+
+
+def _bezier2d_fp32_vs_fp64(torch):
+    """Largest relative difference of Stokes I between the FP32 and FP64 9-point sweeps of
+    the same FP32-rounded inputs, over every top point, upward ray and frequency, with
+    the (ray, frequency) where it occurs."""
+    cfg = inputs.CONFIGS["C3"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    hg = porta.HostGrid.from_inputs(atm, q)
+    its = []
+    for prec, dt in ((porta.F32, torch.float32), (porta.F64, torch.float64)):
+        _, it = porta.fs_sweep(hg, to_dev(atm.kappa, dt), to_dev(atm.propmat, dt),
+                               to_dev(atm.emis, dt), atm.i_bottom, atm.w2, prec=prec,
+                               interp=porta.BEZIER2D, want_jkq=False,
+                               opts=porta.options(ray_batch=40))
+        its.append(it)
+    worst, where = 0.0, None
+    for r in range(its[1].shape[0]):
+        e = ((its[0][r, ..., 0].double() - its[1][r, ..., 0]).abs() / its[1][r, ..., 0].abs())
+        m = e.reshape(e.shape[0], -1).max(dim=1).values
+        f = int(torch.argmax(m))
+        if float(m[f]) > worst:
+            worst, where = float(m[f]), (r, f)
+    del its
+    torch.cuda.empty_cache()
+    return worst, where
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "FP32 9-point Bezier mode misses the 2e-5 bar on Stokes I at 256x256x128 (up to 7.9e-3 "
+    "on mu = 0.5 rays): the clamped slope of each 1-D pass depends on the node values with "
+    "partials whose magnitudes add up to more than 1, so in this laterally rough model a "
+    "perturbation of a plane state grows by ~7% per plane, and the rounding of the FP32 "
+    "states with it over 127 planes; the FP64 sweep of the mode meets its bar"))
+def test_c3_bezier2d_fp32_stokes_i_every_upward_ray():
+    """The FP32 bar on Stokes I (2e-5 relative) for the 9-point Bezier sweep over every top
+    point, upward ray and frequency of the 256x256x128 instance, against the FP64 sweep
+    of the same FP32-rounded inputs (pinned to the oracle's mode 1 by
+    test_c3_bezier2d_fp64_where_fp32_drifts)."""
+    torch = require_gpu()
+    worst, where = _bezier2d_fp32_vs_fp64(torch)
+    print(f"C3 bezier2d FP32 vs FP64: Stokes I max rel diff {worst:.3e} at (ray, freq) {where}")
+    assert worst <= 2e-5
+
+
+def test_c3_bezier2d_fp64_where_fp32_drifts(orc):
+    """The FP64 9-point sweep against the oracle's mode 1 at 256x256x128 on the (ray,
+    frequency) pairs where the FP32 sweep drifts most (mu = 0.5, line wing) and on a
+    grazing and a steep ray, whole top surface: 1e-10 on I, and 1e-10 on Q/I, U/I, V/I
+    (the stated bar is 1e-7; the same growth over the planes that the FP32 rounding
+    shows takes the FP64 rounding to ~5e-12 here, above the 1e-12 of the other FP64
+    checks)."""
+    torch = require_gpu()
+    torch.cuda.empty_cache()
+    cfg = inputs.CONFIGS["C3"]
+    atm = rounded(inputs.make_atmosphere(cfg, seed=0), np.float32)
+    q = inputs.make_quadrature(cfg)
+    rays, freqs = [34, 45, 9, 66], [12, 14]
+    hg = porta.HostGrid.from_inputs(atm, q)
+    dt = torch.float64
+    _, it = porta.fs_sweep(hg, to_dev(atm.kappa, dt), to_dev(atm.propmat, dt),
+                           to_dev(atm.emis, dt), atm.i_bottom, atm.w2, prec=porta.F64,
+                           interp=porta.BEZIER2D, want_jkq=False,
+                           opts=porta.options(ray_batch=40))
+    got = it[rays][:, freqs].cpu().numpy()
+    del it
+    torch.cuda.empty_cache()
+    ref = orc.fs_sweep(orc.OracleProblem(atm, q, interp=1), rays=rays, freqs=freqs,
+                       want_j=False)["itop"]
+    ei, ep = compare_stokes(got, ref, 1e-10, 1e-10, "C3 bezier2d FP64")
+    print(f"C3 bezier2d FP64 vs oracle, rays {rays} x freqs {freqs}: I {ei:.2e}, Q/I.. {ep:.2e}")
