@@ -518,8 +518,8 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
       }
       if (store && jc) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) jc[(size_t)s * a.np + p] = jacc[s];
-        jc[4 * (size_t)a.np + p] = lacc;
+        for (int s = 0; s < 4; ++s) __builtin_nontemporal_store(jacc[s], jc + (size_t)s * a.np + p);
+        __builtin_nontemporal_store(lacc, jc + 4 * (size_t)a.np + p);
       }
     }
     // the row is complete (and its copies for the other waves) before the next reads it
