@@ -557,11 +557,16 @@ __host__ __device__ inline void hanle_system(double a, double h, double bx, doub
   A[4][4] = a;
 }
 
+// Gaussian elimination with partial pivoting.  Every index is a compile-time constant
+// (the pivot row is swapped in by selects over the candidate rows), so on the GPU the
+// matrix stays in registers rather than in per-lane scratch memory.
 template <int N>
 __host__ __device__ inline void solve_pivot(double A[N][N], double b[N]) {
+#pragma unroll
   for (int c = 0; c < N; ++c) {
     int piv = c;
     double best = fabs(A[c][c]);
+#pragma unroll
     for (int r = c + 1; r < N; ++r) {
       const double v = fabs(A[r][c]);
       if (v > best) {
@@ -569,25 +574,32 @@ __host__ __device__ inline void solve_pivot(double A[N][N], double b[N]) {
         piv = r;
       }
     }
-    if (piv != c) {
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      const bool sw = piv == r;
+#pragma unroll
       for (int k = 0; k < N; ++k) {
         const double t = A[c][k];
-        A[c][k] = A[piv][k];
-        A[piv][k] = t;
+        A[c][k] = sw ? A[r][k] : t;
+        A[r][k] = sw ? t : A[r][k];
       }
       const double t = b[c];
-      b[c] = b[piv];
-      b[piv] = t;
+      b[c] = sw ? b[r] : t;
+      b[r] = sw ? t : b[r];
     }
     const double inv = 1.0 / A[c][c];
+#pragma unroll
     for (int r = c + 1; r < N; ++r) {
       const double f = A[r][c] * inv;
+#pragma unroll
       for (int k = c; k < N; ++k) A[r][k] -= f * A[c][k];
       b[r] -= f * b[c];
     }
   }
+#pragma unroll
   for (int r = N - 1; r >= 0; --r) {
     double s = b[r];
+#pragma unroll
     for (int k = r + 1; k < N; ++k) s -= A[r][k] * b[k];
     b[r] = s / A[r][r];
   }
