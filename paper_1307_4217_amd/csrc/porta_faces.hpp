@@ -194,11 +194,12 @@ enum FacesCacheSlot {
 // march 4x the rows of the steep ones) and more blocks per CU, and shorten the longest
 // block; the set-up table is read once per chunk (from L2 for all but the first chunk
 // of a ray, with the order of faces_grid).  At 256x256x128, 80 rays and 101
-// frequencies, a sweep took 2.59, 2.39, 2.34 and 2.46 s with FP32 chunks of 3, 4, 5
-// and 6, and 6.51, 6.49 and 6.37 s with FP64 chunks of 5, 6 and 7.
+// frequencies, a sweep took 6.51, 6.49 and 6.37 s with FP64 chunks of 5, 6 and 7; in
+// FP32, with the previous row held in FP64 (36 KB of LDS per block at chunks of 4, four
+// blocks per CU), 2.53 and 2.59 s with chunks of 4 and 5.
 template <class T>
 __host__ __device__ constexpr int faces_chunk() {
-  return sizeof(T) == 4 ? 5 : 7;
+  return sizeof(T) == 4 ? 4 : 7;
 }
 constexpr int kFacesMaxLanes = 512;  // columns of a plane held by one block
 constexpr int kFacesMaxWarm = 65536; // warm-up rows of a march, at most
@@ -211,10 +212,12 @@ template <class T>
 __host__ __device__ inline size_t faces_col_offset(int nfreq) {
   return ((size_t)nfreq * (sizeof(double) + sizeof(T)) + 15) & ~(size_t)15;
 }
+// The previous row's Stokes vectors are kept in FP64 in either precision (see
+// k_sweep_plane_faces).
 template <class T>
 __host__ __device__ inline size_t faces_lds_bytes(int nfreq, int fchunk, int lanes) {
   const size_t waves = (size_t)(lanes + 63) / 64;
-  return faces_col_offset<T>(nfreq) + (size_t)fchunk * (lanes + 4 * waves) * 4 * sizeof(T);
+  return faces_col_offset<T>(nfreq) + (size_t)fchunk * (lanes + 4 * waves) * 4 * sizeof(double);
 }
 
 // Frequency-independent part of the update of node p (working frame): the PointSetup of
@@ -339,9 +342,14 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
   extern __shared__ double s_tab[];
   double* s_wn = s_tab;
   T* s_phi = reinterpret_cast<T*>(s_tab + a.nfreq);
-  T* s_row = reinterpret_cast<T*>(reinterpret_cast<char*>(s_tab) + faces_col_offset<T>(a.nfreq));
+  // the in-plane chain in FP64 (D): on the thin cell steps of an inclined ray in the line
+  // wings the change of I per step falls below half a unit in the last place of an FP32
+  // I, so an FP32 chain would drop it at every step; the FP32 arithmetic forms that
+  // change and the chain adds it in FP64 (the plane states stored are FP32)
+  using D = double;
+  D* s_row = reinterpret_cast<D*>(reinterpret_cast<char*>(s_tab) + faces_col_offset<T>(a.nfreq));
   const int lanes = blockDim.x, nwaves = (lanes + 63) >> 6;
-  T* s_bnd = s_row + (size_t)a.fchunk * lanes * 4;
+  D* s_bnd = s_row + (size_t)a.fchunk * lanes * 4;
   const size_t bpar = (size_t)a.fchunk * nwaves * 8;   // one parity of s_bnd
   for (int t = threadIdx.x; t < a.nfreq; t += blockDim.x) {
     s_wn[t] = a.wn[t];
@@ -403,11 +411,12 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
     for (int f = 0; f < nf && active; ++f) {
       T v[4] = {a.ibound, T(0), T(0), T(0)};
       if (ip) load4(ip + (size_t)(f0 + f) * fstride + 4 * (size_t)(cprev * fr.nx + lane), v);
-      store4(s_row + ((size_t)f * lanes + lane) * 4, v);
+      const D vd[4] = {(D)v[0], (D)v[1], (D)v[2], (D)v[3]};
+      store4(s_row + ((size_t)f * lanes + lane) * 4, vd);
       // the parity read at step 0 is that of step -1
-      T* b = s_bnd + bpar + ((size_t)f * nwaves + wave) * 8;
-      if (side >= 0) store4(b + 4 * side, v);
-      if (last_too) store4(b + 4, v);
+      D* b = s_bnd + bpar + ((size_t)f * nwaves + wave) * 8;
+      if (side >= 0) store4(b + 4 * side, vd);
+      if (last_too) store4(b + 4, vd);
     }
     __syncthreads();
   }
@@ -438,16 +447,16 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
       // I_M as two linear steps (x, then z or y): a field constant over the stencil is
       // returned exactly, so the rounding of the four weights, the same for every node
       // of a ray, adds no bias that the many cell steps of an inclined ray would pile up
-      const T fa = (T)sM.a, fb = (T)sM.b;
-      const T* r0 = (c_bnd[0] ? s_bnd + rd : s_row) + c_off[0];
-      const T* r1 = (c_bnd[1] ? s_bnd + rd : s_row) + c_off[1];
-      T* own = s_row + 4 * (size_t)lane;
-      T* bown = s_bnd + wr + 8 * (size_t)wave;
+      const D fa = sM.a, fb = sM.b;
+      const D* r0 = (c_bnd[0] ? s_bnd + rd : s_row) + c_off[0];
+      const D* r1 = (c_bnd[1] ? s_bnd + rd : s_row) + c_off[1];
+      D* own = s_row + 4 * (size_t)lane;
+      D* bown = s_bnd + wr + 8 * (size_t)wave;
       const size_t ostore = a.top ? (size_t)po : (size_t)p;
       double jacc[4] = {0, 0, 0, 0}, lacc = 0.0;
       for (int f = 0; f < nf; ++f) {
         const int fg = f0 + f;
-        T IM[4];
+        D IM[4];
         T up[2][4];   // the corners on the upwind plane (or the boundary)
         if (ip) {
           const T* q = ip + (size_t)fg * fstride;
@@ -458,13 +467,14 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
           up[0][1] = up[0][2] = up[0][3] = up[1][1] = up[1][2] = up[1][3] = T(0);
         }
         if (sM.inplane) {
-          T c0[4], c1[4];
+          D c0[4], c1[4];
           load4(r0 + (size_t)f * c_str[0], c0);
           load4(r1 + (size_t)f * c_str[1], c1);
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const T A = c0[s] + fa * (c1[s] - c0[s]);
-            const T B = up[0][s] + fa * (up[1][s] - up[0][s]);
+            const D A = c0[s] + fa * (c1[s] - c0[s]);
+            const D u0 = up[0][s], u1 = up[1][s];
+            const D B = u0 + fa * (u1 - u0);
             IM[s] = A + fb * (B - A);
           }
         } else {
@@ -479,40 +489,59 @@ __global__ void __launch_bounds__(kFacesMaxLanes) k_sweep_plane_faces(const Face
           }
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const T A = v0[s] + fa * (v1[s] - v0[s]);
-            const T B = up[0][s] + fa * (up[1][s] - up[0][s]);
+            const D w0 = v0[s], w1 = v1[s], u0 = up[0][s], u1 = up[1][s];
+            const D A = w0 + fa * (w1 - w0);
+            const D B = u0 + fa * (u1 - u0);
             IM[s] = A + fb * (B - A);
           }
         }
         const T tau = tau0 * s_phi[fg];
         const Coefs<T> cf = coefficients<true>(tau);
-        T KI[4], b[4], res[4];
-        kprime_apply(eMv, rMv, IM, KI);
+        const T IMt[4] = {(T)IM[0], (T)IM[1], (T)IM[2], (T)IM[3]};
+        T KI[4], dv[4];
+        kprime_apply(eMv, rMv, IMt, KI);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           // e I_M as I_M - (1 - e) I_M (see Coefs::em1), and the change of a step summed
           // before it is added to I_M: on thin steps each term alone can fall below half
           // a unit in the last place of I_M, and dropping the source terms while keeping
           // the attenuation would bias a long chain of steps
-          const T d = -cf.em1 * IM[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] +
-                      cf.omC * cMt[s];
-          b[s] = IM[s] + d;
+          dv[s] = -cf.em1 * IMt[s] - cf.psiM * KI[s] + cf.omM * SMt[s] + cf.omO * SOt[s] +
+                  cf.omC * cMt[s];
         }
-        stokes_solve<1>(KO, stokes_freq(KO, cf.psiO), b, res);
+        const StokesFreq<T> F = stokes_freq(KO, cf.psiO);
+        D res[4];
+        if constexpr (sizeof(T) == 4) {
+          // (1 + psi'_O K'_O) I_O = I_M + d, so I_O = I_M + x with
+          // (1 + psi'_O K'_O) x = d - psi'_O K'_O I_M: x in FP32, I_M + x in FP64
+          T KOI[4], rhs[4], x[4];
+          kprime_apply(eOv, rOv, IMt, KOI);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) rhs[s] = dv[s] - cf.psiO * KOI[s];
+          stokes_solve<1>(KO, F, rhs, x);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) res[s] = IM[s] + (D)x[s];
+        } else {
+          T b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[s] = IM[s] + dv[s];
+          stokes_solve<1>(KO, F, b, res);
+        }
+        const T rest[4] = {(T)res[0], (T)res[1], (T)res[2], (T)res[3]};
         if (chain) {
           store4(own + (size_t)f * lanes * 4, res);
-          T* b2 = bown + (size_t)f * nwaves * 8;
+          D* b2 = bown + (size_t)f * nwaves * 8;
           if (side >= 0) store4(b2 + 4 * side, res);
           if (last_too) store4(b2 + 4, res);
         }
         if (store) {
           // I_top of a ray in the exchanged frame goes to the grid's own indices, across
           // rows: there the plain store, whose lines the cache merges, is the faster
-          if (a.top) store4(op + (size_t)fg * fstride + 4 * ostore, res);
-          else store4_nt(op + (size_t)fg * fstride + 4 * ostore, res);
+          if (a.top) store4(op + (size_t)fg * fstride + 4 * ostore, rest);
+          else store4_nt(op + (size_t)fg * fstride + 4 * ostore, rest);
           const double W = s_wn[fg];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) jacc[s] += W * (double)res[s];
+          for (int s = 0; s < 4; ++s) jacc[s] += W * res[s];
           lacc += W * (double)(cf.omO + lf * cf.omC);
         }
       }
