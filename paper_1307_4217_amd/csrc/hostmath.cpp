@@ -99,6 +99,17 @@ void hm_hanle_solve(double a, double h, double bx, double by, double bz, const d
   for (int i = 0; i < 5; ++i) x5[i] = b[i];
 }
 
+// The pivoted 5x5 elimination of the SEE on a general system: A row-major, b in, x out.
+void hm_solve_pivot5(const double* A25, const double* b5, double* x5) {
+  double A[5][5], b[5];
+  for (int i = 0; i < 5; ++i) {
+    for (int k = 0; k < 5; ++k) A[i][k] = A25[5 * i + k];
+    b[i] = b5[i];
+  }
+  porta::solve_pivot<5>(A, b);
+  for (int i = 0; i < 5; ++i) x5[i] = b[i];
+}
+
 double hm_besser_cm_grad(double yM, double yO, double yP, double ratio, double* d4) {
   return porta::besser_cm_grad(yM, yO, yP, ratio, d4);
 }

@@ -39,6 +39,7 @@ def hm():
     L.hm_stokes_solve_scaled_f32.argtypes = [_fp, _fp, C.c_float, _fp, C.c_int, _fp]
     L.hm_ray_consts.argtypes = [C.c_double] * 4 + [_dp]
     L.hm_hanle_solve.argtypes = [C.c_double] * 5 + [_dp, _dp]
+    L.hm_solve_pivot5.argtypes = [_dp] * 3
     return L
 
 
@@ -313,3 +314,21 @@ def test_parabolic_control_point_matches_oracle_and_its_gradient(hm, orc):
             dn[k] -= h
             fd = (hm.hm_parabolic_cm(*up) - hm.hm_parabolic_cm(*dn)) / (2 * h)
             assert d[k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_pivoted_solve_needs_and_takes_row_swaps(hm):
+    """The SEE's 5x5 elimination with partial pivoting (the pivot row swapped in by
+    selects) against numpy on random systems whose rows are permuted so that the
+    diagonal is zero or tiny: without the swaps the elimination would divide by it."""
+    rng = np.random.default_rng(11)
+    for trial in range(300):
+        M = rng.normal(size=(5, 5)) + 5 * np.eye(5)
+        A = np.ascontiguousarray(M[rng.permutation(5)])
+        if trial % 3 == 0:
+            A[0, 0] = 0.0
+        elif trial % 3 == 1:
+            A[np.arange(5), np.arange(5)] *= 1e-12
+        b = rng.normal(size=5)
+        x = np.zeros(5)
+        hm.hm_solve_pivot5(p(A), p(b), p(x))
+        np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
