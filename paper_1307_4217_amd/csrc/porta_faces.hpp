@@ -594,8 +594,18 @@ __global__ void __launch_bounds__(256)
       double sum = 0.0;
       if (xw < fr.nx && yw < fr.ny) {
         const size_t pw = (size_t)yw * fr.nx + xw;
-        for (int k = 0; k < nchunk; ++k)
-          sum += jchunk[(((size_t)rb * nchunk + k) * 5 + c) * np + pw];
+        const double* src = jchunk + ((size_t)rb * nchunk * 5 + c) * np + pw;
+        const size_t kst = 5 * np;   // from one chunk to the next
+        int k = 0;
+        // eight loads in flight, then added in chunk order (the sum of one loop)
+        for (; k + 8 <= nchunk; k += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(k + u) * kst];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; k < nchunk; ++k) sum += src[(size_t)k * kst];
       }
       tile[r][tx] = sum;
     }
