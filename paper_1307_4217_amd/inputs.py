@@ -25,7 +25,6 @@ All arrays are stored x-fastest: index p = (k * ny + j) * nx + i.
 from __future__ import annotations
 
 import dataclasses
-import math
 
 import numpy as np
 

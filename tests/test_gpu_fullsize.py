@@ -7,7 +7,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from gpu_common import Case, compare_stokes, require_gpu, rounded, to_dev, up_rays
+from gpu_common import Case, compare_stokes, require_gpu, rounded, to_dev
 from paper_1307_4217_amd import inputs, porta
 
 pytestmark = pytest.mark.gpu
