@@ -11,7 +11,8 @@
 // x and y being periodic, around the box.  The plane is then the fixed point of its
 // node equations.  A block holds one ray and a few frequencies of a whole plane and
 // marches across it row by row: each step solves one row of nodes (the lanes, at
-// consecutive addresses) from the previous row (kept in LDS) and the upwind plane.  A
+// consecutive addresses) from the previous row (kept in LDS, in FP64 in either
+// precision) and the upwind plane.  A
 // ray that reaches an x = const face before a y = const one is solved on a transposed
 // copy of the transfer coefficients (its own plane states transposed too), so that its
 // in-plane dependencies also run from row to row.  The march starts m rows early: the
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(256) k_faces_setup(const FacesArgs<T> a) {
 
 // One plane for one ray and one chunk of frequencies (order: faces_grid).  Lanes
 // are the columns of the working frame; the block walks its rows.  Each lane keeps its
-// own column's Stokes vectors of the previous row in LDS and reads the neighbouring
+// own column's Stokes vectors of the previous row in LDS (FP64) and reads the neighbouring
 // column's there too when that lane is in its wave (the lanes of a wave read before
 // they write); a neighbour in another wave is read from the copy of the first and last
 // lanes of every wave, which is kept for rows of either parity, so one barrier per row
