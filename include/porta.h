@@ -165,9 +165,10 @@ typedef struct {
                                checkpoints, nx and ny <= 512; porta_fs_adjoint returns
                                PORTA_EUNSUPPORTED */
   int32_t faces_chunk;      /* with faces = 1: frequencies one block of the first-face
-                               kernel carries through a plane (0: as many as 64 KiB of LDS
-                               holds, evened out over the chunks); PORTA_EUNSUPPORTED if
-                               more than fit */
+                               kernel carries through a plane (0: 4 in FP32, 7 in FP64,
+                               fewer where 64 KiB of LDS holds fewer rows of that width,
+                               evened out over the chunks); PORTA_EUNSUPPORTED if more
+                               than fit */
 } porta_options;
 
 typedef enum { PORTA_CONTROL_BESSER = 0, PORTA_CONTROL_PARABOLIC = 1 } porta_control;

@@ -181,7 +181,8 @@ def options(ray_batch=0, block=0, xcd_remap=-1, control=0, stokes=4, ray_first=0
     sweep and the adjoint first check that the coefficients are finite and eta_I > 0
     (waits on the stream; PORTA_ENONFINITE otherwise); faces = 1: M and P on the first
     face of the grid the ray crosses (0: on the neighbouring horizontal planes), with
-    faces_chunk frequencies per block of its kernel (0: chosen from the LDS)."""
+    faces_chunk frequencies per block of its kernel (0: 4 in FP32, 7 in FP64, fewer if
+    the LDS of a block holds fewer)."""
     return Options(int(ray_batch), int(block), int(xcd_remap), int(control), int(stokes),
                    int(ray_first), int(ray_count), int(bool(check_inputs)), int(faces),
                    int(faces_chunk))
