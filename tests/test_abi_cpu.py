@@ -382,3 +382,44 @@ def test_faces_option_checks():
     # three fit: the call gets past the option checks to the workspace check
     assert sweep(porta.options(faces=1, faces_chunk=3), g=small_hg(nx=500), ws_bytes=16) == \
         porta.ENOMEM
+
+
+def test_bench_precision_report_on_known_differences():
+    """bench.precision_report (CPU tensors): the largest relative difference on I, the
+    largest absolute one on Q/I, U/I, V/I, J^K_Q rows 0-8 relative to J00 at the same
+    point and Lbar relative, each found where it was planted."""
+    import torch
+    import bench
+    rng = np.random.default_rng(3)
+    it64 = torch.as_tensor(1.0 + rng.uniform(0, 0.1, size=(3, 5, 4, 6, 4)))
+    it64[..., 1:] *= 1e-3
+    it32 = it64.float().clone()
+    it32[2, 4, 1, 5, 0] = float(it64[2, 4, 1, 5, 0]) * (1 + 3e-5)      # I, relative
+    it32[1, 0, 3, 2, 2] += 2e-6 * float(it64[1, 0, 3, 2, 0])            # U/I, absolute
+    j64 = torch.as_tensor(1.0 + rng.uniform(0, 1, size=(10, 24)))
+    j32 = j64.clone()
+    j32[5, 7] += 4e-7 * j64[0, 7]
+    j32[9, 11] *= 1 + 5e-8
+    r = bench.precision_report(it32, it64, j32, j64, 4)
+    assert r["outputs"] == 3 * 5 * 4 * 6
+    assert r["i_rel_max"] == pytest.approx(3e-5, rel=0.02)
+    assert r["pol_abs_max"] == pytest.approx(2e-6, rel=0.02)
+    assert r["jkq_rel_j00_max"] == pytest.approx(4e-7, rel=1e-6)
+    assert r["lbar_rel_max"] == pytest.approx(5e-8, rel=1e-6)
+
+
+def test_bench_algorithmic_bytes():
+    """The algorithmic bytes per plane launch that the roofline divides by: per update the
+    upwind Stokes vector read and the new one written (16 + 16 B in FP32), per node the
+    three coefficient planes (3 x 52 B) and J read and written (160 B); the adjoint reads
+    two Stokes vectors and writes one per update and writes 33 partials per node and ray."""
+    import bench
+    from paper_1307_4217_amd import inputs
+    cfg = inputs.CONFIGS["C3"]
+    np_ = cfg.nx * cfg.ny
+    b, upd = bench.sweep_launch_bytes(cfg, 40, 4)
+    assert upd == 40 * 101 * np_
+    assert b == 40 * 101 * np_ * 32 + np_ * (3 * 52 + 160)
+    a, aupd = bench.adjoint_launch_bytes(cfg, 16, 4)
+    assert aupd == 16 * 101 * np_
+    assert a == 16 * 101 * np_ * 48 + 16 * np_ * 33 * 4 + 3 * np_ * 13 * 4
